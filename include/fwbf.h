@@ -1,0 +1,169 @@
+/*
+ * fwbf.h -- C ABI of libfwbf.so, an MI355X (gfx950) implementation of fast
+ * weighted bit-flipping (FWBF) decoding of LDPC codes (Ma, Li, Zhu, Zhang,
+ * Qi, "An Improved WBF Algorithm for Higher-Speed Decoding of LDPC Codes").
+ *
+ * Conventions shared by every entry point:
+ *   - Return value: FWBF_OK (0) on success, a negative FWBF_E_* code
+ *     otherwise; fwbf_last_error() then returns a message (thread-local,
+ *     valid until the next call on the same thread).  Arguments are checked
+ *     before anything is enqueued: a call that fails enqueues nothing.
+ *   - "_dev" pointers are device memory on the current HIP device, owned by
+ *     the caller (e.g. torch tensors); "_host" pointers are host memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Device work is enqueued asynchronously on it and ordered with the
+ *     caller's other work on that stream; nothing synchronises unless stated.
+ *   - Packed hard decisions / codewords: bit n of a frame sits in 32-bit
+ *     word n/32 at bit position n%32; padding bits of the last word are 0.
+ *   - fwbf_code objects are created and freed by the library, immutable
+ *     after creation and shareable across threads and streams.
+ */
+#ifndef FWBF_H
+#define FWBF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FWBF_OK 0
+#define FWBF_E_INVALID (-1)     /* null pointer, out-of-range size or parameter */
+#define FWBF_E_PARSE (-2)       /* malformed code description */
+#define FWBF_E_GIRTH (-3)       /* no draw met the girth constraint */
+#define FWBF_E_UNSUPPORTED (-4) /* parameters outside what the kernels handle */
+#define FWBF_E_NOMEM (-5)       /* host or device allocation failed */
+#define FWBF_E_HIP (-6)         /* HIP runtime or launch error */
+
+/* received-value type: float, or fixed point (int8 / int16) */
+enum { FWBF_F32 = 0, FWBF_I8 = 1, FWBF_I16 = 2 };
+/* check reliability: WBF (minimum over N(m), no alpha term), MWBF (same
+ * minimum, minus alpha|y_n|), IMWBF (minimum over N(m)\n, eq. (1)) */
+enum { FWBF_WBF = 0, FWBF_MWBF = 1, FWBF_IMWBF = 2 };
+/* bit choice: GROUPS = FWBF (at most one flip per block, if its metric is
+ * > 0; Section III, Step 2), SINGLE = largest metric flipped unconditionally
+ * (IMWBF rule after eq. (1)), TOPL = the lambda largest positive metrics
+ * (the multi-bit choice of MLP-WBF, Section III) */
+enum { FWBF_GROUPS = 0, FWBF_SINGLE = 1, FWBF_TOPL = 2 };
+
+/* flags */
+#define FWBF_FLAG_NO_CYCLE_EXIT 1u /* run every round up to max_iter even after
+                                      the state repeats (for verification) */
+
+typedef struct fwbf_code fwbf_code;
+
+/* Decoder parameters (eq. (1) and Section III). */
+typedef struct {
+    int32_t dtype;     /* FWBF_F32 / FWBF_I8 / FWBF_I16 */
+    int32_t weights;   /* FWBF_WBF / FWBF_MWBF / FWBF_IMWBF */
+    int32_t select;    /* FWBF_GROUPS / FWBF_SINGLE / FWBF_TOPL */
+    int32_t groups;    /* G: number of blocks, p = ceil(N/G), 1 <= G <= N */
+    int32_t lambda;    /* TOPL: flips per round, >= 1 */
+    int32_t max_iter;  /* K_max: maximum number of flip rounds, >= 0 */
+    float alpha;       /* F32: alpha of eq. (1) (ignored for WBF) */
+    int32_t alpha_num; /* I8/I16: alpha = alpha_num / alpha_den (>= 0, > 0) */
+    int32_t alpha_den;
+    int32_t threads_per_frame; /* 0 = automatic; else 64, 128, 256, 512 or 1024 */
+    uint32_t flags;            /* FWBF_FLAG_* */
+} fwbf_params;
+
+/* ---- codes (Section II: H, M(n), N(m), RC constraint) ------------------- */
+
+/* Parse a QC description:
+ *     qc-ldpc v1
+ *     Z <circulant size>
+ *     base <mb> <nb>
+ *     <mb rows of nb shifts>
+ * Shift s >= 0 is the Z x Z permutation taking row r to column (r+s) mod Z;
+ * -1 is the zero block.  '#' starts a comment.  N = nb Z, M = mb Z.
+ * Limits: 1 <= Z <= 65535, N <= 65535, every row and column of the base
+ * with at most 64 nonzero blocks.  *out is owned by the caller and released
+ * with fwbf_code_free.  FWBF_E_PARSE on malformed text. */
+int fwbf_code_from_text(const char *text, fwbf_code **out);
+
+/* Seeded draw of an mb x nb base of circulant permutations: shifts drawn
+ * row-major as SplitMix64(seed) mod Z; with min_girth = 6 the whole base is
+ * redrawn (continuing the stream) until no 4-cycle exists, i.e. the RC
+ * constraint holds.  min_girth must be 4 (no check) or 6.  FWBF_E_GIRTH
+ * after 100000 rejected draws. */
+int fwbf_code_from_seed(int mb, int nb, int Z, uint64_t seed, int min_girth, fwbf_code **out);
+
+/* Canonical text of a code.  Writes at most `cap` bytes including the NUL;
+ * *needed (if not NULL) receives the full length including the NUL.
+ * FWBF_E_INVALID if cap is too small (nothing written then). */
+int fwbf_code_to_text(const fwbf_code *code, char *buf, size_t cap, size_t *needed);
+
+/* Dimensions; any output pointer may be NULL.  K = N - rank_GF2(H) (the
+ * rank is computed on first request and cached). */
+int fwbf_code_dims(const fwbf_code *code, int *N, int *M, int *K, int *dv_max, int *dc_max);
+
+/* Base shifts, row-major mb x nb (-1 = zero block); also returns mb, nb, Z. */
+int fwbf_code_shifts(const fwbf_code *code, int *mb, int *nb, int *Z, int *shifts_host);
+
+/* 1 if H violates the RC constraint (has a 4-cycle), else 0. */
+int fwbf_code_has_4cycle(const fwbf_code *code);
+
+void fwbf_code_free(fwbf_code *code);
+
+/* ---- encoder (Section II: codewords are the null space of H) ----------- */
+
+/* Info positions: the K non-pivot columns of the reduced row-echelon form
+ * of H over GF(2), ascending (out_host holds K ints). */
+int fwbf_code_info_positions(const fwbf_code *code, int *out_host);
+
+/* Codewords first .. first+count-1 of the seeded pool, packed, into
+ * out_host[count][ceil(N/32)].  Info bit k of codeword w is bit k%64 of
+ * SplitMix64 output number w*ceil(K/64) + k/64 of the stream seeded with
+ * `seed`; parity bits follow from H c = 0.  Host-side, synchronous. */
+int fwbf_encode(const fwbf_code *code, uint64_t seed, int64_t first, int64_t count,
+                uint32_t *out_host);
+
+/* ---- channel (Section II BPSK, Section V AWGN) ------------------------- */
+
+/* Received frames f0 .. f0+F-1 into y_dev[F][y_stride] (y_stride >= N):
+ * y = (1 - 2c) + sigma g, c = pool_dev row (f % pool_n) (pool_dev NULL:
+ * all-zero codeword), g standard normal from Philox4x32-10 keyed by `seed`,
+ * counter (n/4, f low, f high, stream_id), Box-Muller over pairs of words
+ * (u = ((x >> 9) + 1/2) 2^-23, exact in single precision; cosine member for even n, sine for odd).
+ * sigma_dev (F floats, may be NULL) overrides `sigma` per frame.
+ * dtype F32 stores y; I8 / I16 store clamp(rint(scale y), -127/-32767,
+ * 127/32767).  Single-precision arithmetic. */
+int fwbf_channel(int N, int64_t F, int64_t f0, const uint32_t *pool_dev, int64_t pool_n,
+                 uint64_t seed, uint32_t stream_id, float sigma, const float *sigma_dev,
+                 float scale, int dtype, void *y_dev, int64_t y_stride, void *stream);
+
+/* ---- decoding (eq. (1), Section III) ------------------------------------ */
+
+/* Decode F frames y_dev[F][y_stride] (element type per params->dtype).
+ * Outputs: z_dev[F][ceil(N/32)] packed hard decisions z_k, iters_dev[F]
+ * the number of flip rounds run (0..max_iter), ok_dev[F] = 1 iff the final
+ * syndrome is zero.  The result is a deterministic function of (H, y,
+ * params): a decoder state that repeats (no flip, or the same flips as the
+ * round before) is followed to max_iter analytically, so outputs equal those
+ * of running every round.  F = 0 is a no-op. */
+int fwbf_decode(const fwbf_code *code, const fwbf_params *params, const void *y_dev, int64_t F,
+                int64_t y_stride, uint32_t *z_dev, int32_t *iters_dev, uint8_t *ok_dev,
+                void *stream);
+
+/* ---- error accounting (Section V) --------------------------------------- */
+
+/* Adds, for frames f0 .. f0+F-1 against pool row (f % pool_n) (pool NULL:
+ * all-zero codeword), into counters_dev (int64, max_iter + 7 entries):
+ * [0] bit errors, [1] frame errors, [2] undetected frame errors (ok = 1 but
+ * z != c), [3] sum of rounds, [4] frames, [5] frames with ok = 1,
+ * [6 .. 6+max_iter] histogram of rounds.  Counters are accumulated, not
+ * cleared. */
+int fwbf_count(int N, int64_t F, int64_t f0, const uint32_t *z_dev, const uint32_t *pool_dev,
+               int64_t pool_n, const int32_t *iters_dev, const uint8_t *ok_dev, int max_iter,
+               int64_t *counters_dev, void *stream);
+
+/* ---- misc ---------------------------------------------------------------- */
+
+const char *fwbf_last_error(void);
+const char *fwbf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FWBF_H */

@@ -699,7 +699,7 @@ int or_decode_trace(const ocode *c, int weights, int select, int G, int lambda, 
 /* Channel (Section II: BPSK s = 1 - 2c; Section V: AWGN, variance N0/2).   */
 /* Noise: Philox4x32-10 (Salmon, Moraes, Dror, Shaw 2011) keyed by the seed,*/
 /* counter (n/4, frame low, frame high, stream); the four words give two    */
-/* Box-Muller pairs (u = (x>>8 + 1/2) 2^-24, r = sqrt(-2 ln u_a),           */
+/* Box-Muller pairs (u = (x>>9 + 1/2) 2^-23, r = sqrt(-2 ln u_a),           */
 /* angle 2 pi u_b; cosine for the even member, sine for the odd one).       */
 /* Computed in double precision.                                            */
 /* ------------------------------------------------------------------------ */
@@ -733,8 +733,8 @@ static double gauss_of(uint64_t seed, uint32_t stream, int64_t f, int n)
     uint32_t x[4];
     or_philox4x32_10(ctr, key, x);
     int pair = (n % 4) / 2, odd = n % 2;
-    double ua = ((double)(x[2 * pair] >> 8) + 0.5) / 16777216.0;
-    double ub = ((double)(x[2 * pair + 1] >> 8) + 0.5) / 16777216.0;
+    double ua = ((double)(x[2 * pair] >> 9) + 0.5) / 8388608.0;
+    double ub = ((double)(x[2 * pair + 1] >> 9) + 0.5) / 8388608.0;
     double r = sqrt(-2.0 * log(ua));
     double ang = 2.0 * M_PI * ub;
     return odd ? r * sin(ang) : r * cos(ang);

@@ -1,0 +1,769 @@
+// FWBF decoding kernels for gfx950 (eq. (1) and Section III of the paper).
+//
+// One workgroup decodes one frame at a time and loops over frames
+// (persistent grid).  Per-frame state lives in LDS:
+//   keys  one 32-bit word per slot: the metric of a bit in order-preserving
+//         unsigned form (optionally packed with its position in the block so
+//         that an unsigned max picks the largest metric and, among equal
+//         metrics, the lowest index);
+//   chk   per check: minimum and second minimum of |y| over N(m) and the
+//         position of the minimum (the IMWBF weight of bit n in check m is
+//         the second minimum when n holds the minimum, else the minimum);
+//   syn   syndrome bits, tog per-round toggle parities, zw hard decisions.
+// Slots: block g (p = ceil(N/G) bits) is padded to Lc = L*C slots held by L
+// consecutive threads with C slots each (L a power of two); padding slots
+// hold key 0 and never win (the "null" metric padding of the paper's
+// footnote to Section V).
+//
+// Round k (Section III, Step 2 then Step 1):
+//   select  each thread takes the max of its C slot keys, an xor-butterfly
+//           over the L threads of the block gives the block maximum;
+//   apply   winners with a positive metric toggle their hard decision and the
+//           toggle parity of their checks;
+//   claim   one winner per net-toggled check flips its syndrome bit and
+//           updates the unsatisfied-check count;
+//   update  the metrics of the bits of every toggled check change: integer
+//           inputs add +-2 a_den w exactly, float inputs recompute the bit's
+//           metric from scratch in the fixed check order (so results equal
+//           a full recomputation bit for bit).
+// The decoder is a deterministic function of the hard-decision vector; a
+// round without flips, or with the same flips as the round before, proves
+// the state sequence periodic with period 1 or 2, and the output at K_max
+// follows without running the remaining rounds.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "internal.h"
+
+namespace fwbf {
+namespace {
+
+constexpr uint32_t NONE = 0xFFFFFFFFu;
+constexpr int CTL_FLAGS = 0, CTL_WEIGHT = 1;
+constexpr int F_ANY = 1, F_DIFF = 2;
+
+struct DecodeArgs {
+    const void *y;
+    int64_t F, stride;
+    uint32_t *z;
+    int32_t *iters;
+    uint8_t *ok;
+    const uint32_t *col, *row;
+    const uint8_t *coldeg, *rowdeg;
+    int N, M, Z, mb, nb, dvmax, dcmax;
+    uint32_t magZ, maskZ, magP, maskP, magD, maskD;  // exact n/d = umulhi(n, mag) + (n & mask)
+    int weights, select, lambda, max_iter;
+    float alpha;
+    int anum, aden;
+    uint32_t flags;
+    // slot layout
+    int C, L, logL, GP, P, Geff, p, Lc, W;
+    int idxb;
+    uint32_t idxmask, bias, zero_val;
+    // LDS offsets (bytes)
+    int o_keys, o_chk, o_chkp, o_mag, o_z, o_syn, o_tog, o_win, o_prv, o_tl, o_gb, o_top, o_ctl,
+        o_col, o_row, o_cdeg, o_rdeg, lds_bytes;
+};
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t mag, uint32_t mask)
+{
+    return __umulhi(n, mag) + (n & mask);
+}
+
+template <int DT> struct Tr;
+template <> struct Tr<FWBF_I8> {
+    using Y = int8_t;
+    using Mag = uint8_t;
+    using Chk = uint32_t;  // min1 | min2 << 8 | pos << 16
+    static constexpr bool isf = false;
+    static constexpr uint32_t BIG = 0xFF;
+};
+template <> struct Tr<FWBF_I16> {
+    using Y = int16_t;
+    using Mag = uint16_t;
+    using Chk = uint64_t;  // min1 | min2 << 16 | pos << 32
+    static constexpr bool isf = false;
+    static constexpr uint32_t BIG = 0xFFFF;
+};
+template <> struct Tr<FWBF_F32> {
+    using Y = float;
+    using Mag = float;
+    using Chk = uint64_t;  // bits(min1) | bits(min2) << 32; position in chkp
+    static constexpr bool isf = true;
+};
+
+template <int DT> __device__ __forceinline__ typename Tr<DT>::Chk pack_chk(uint32_t m1, uint32_t m2, uint32_t pos)
+{
+    if constexpr (DT == FWBF_I8) return m1 | (m2 << 8) | (pos << 16);
+    else if constexpr (DT == FWBF_I16) return (uint64_t)m1 | ((uint64_t)m2 << 16) | ((uint64_t)pos << 32);
+    else return (uint64_t)m1 | ((uint64_t)m2 << 32);
+}
+
+// weight w_{n,m} of the q-th member of check m (int inputs)
+template <int DT>
+__device__ __forceinline__ int32_t weight_i(typename Tr<DT>::Chk c, uint32_t q, bool imwbf)
+{
+    if constexpr (DT == FWBF_I8) {
+        uint32_t m1 = c & 0xFF, m2 = (c >> 8) & 0xFF, pos = (c >> 16) & 0xFF;
+        return (int32_t)((imwbf && pos == q) ? m2 : m1);
+    } else {
+        uint32_t m1 = (uint32_t)c & 0xFFFF, m2 = (uint32_t)(c >> 16) & 0xFFFF, pos = (uint32_t)(c >> 32) & 0xFF;
+        return (int32_t)((imwbf && pos == q) ? m2 : m1);
+    }
+}
+__device__ __forceinline__ float weight_f(uint64_t c, uint32_t pos, uint32_t q, bool imwbf)
+{
+    uint32_t bits = (imwbf && pos == q) ? (uint32_t)(c >> 32) : (uint32_t)c;
+    return __uint_as_float(bits);
+}
+
+// order-preserving map of a float to uint32 (-0 canonicalised to +0)
+__device__ __forceinline__ uint32_t orderable(float e)
+{
+    uint32_t u = __float_as_uint(e == 0.0f ? 0.0f : e);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+struct Lds {
+    uint32_t *keys;
+    void *chk;
+    uint8_t *chkp;
+    void *mag;
+    uint32_t *zw, *syn, *tog, *win, *prv, *tl;
+    unsigned long long *gb;
+    uint32_t *topn;
+    unsigned long long *topk;
+    int *ctl;
+    uint32_t *col, *row;
+    uint8_t *cdeg, *rdeg;
+};
+
+// Metric of bit n (eq. (1)) from the current syndrome, as an order-
+// preserving 32-bit value: int inputs a_den*S - a_num*|y_n| + bias, float
+// inputs fmaf(-alpha, |y_n|, S) with S summed over M(n) in ascending check
+// order from the first term.
+template <int DT>
+__device__ __forceinline__ uint32_t metric_val(const DecodeArgs &a, const Lds &s, uint32_t n, bool imwbf)
+{
+    using T = Tr<DT>;
+    const uint32_t j = fdiv(n, a.magZ, a.maskZ);
+    const int c = (int)(n - j * a.Z);
+    const int deg = s.cdeg[j];
+    const uint32_t *ce = s.col + j * a.dvmax;
+    const typename T::Chk *chk = (const typename T::Chk *)s.chk;
+    const typename T::Mag *mag = (const typename T::Mag *)s.mag;
+    if constexpr (T::isf) {
+        float S = 0.0f;
+        for (int t = 0; t < deg; t++) {
+            const uint32_t e = ce[t];
+            int r = c - (int)(e & 0xFFFF);
+            r += (r < 0) ? a.Z : 0;
+            const uint32_t m = (e >> 24) * a.Z + r;
+            const float w = weight_f(chk[m], s.chkp[m], (e >> 16) & 0xFF, imwbf);
+            const float term = ((s.syn[m >> 5] >> (m & 31)) & 1) ? w : -w;
+            S = (t == 0) ? term : S + term;
+        }
+        return orderable(__builtin_fmaf(-a.alpha, mag[n], S));
+    } else {
+        int32_t S = 0;
+        for (int t = 0; t < deg; t++) {
+            const uint32_t e = ce[t];
+            int r = c - (int)(e & 0xFFFF);
+            r += (r < 0) ? a.Z : 0;
+            const uint32_t m = (e >> 24) * a.Z + r;
+            const int32_t w = weight_i<DT>(chk[m], (e >> 16) & 0xFF, imwbf);
+            S += ((s.syn[m >> 5] >> (m & 31)) & 1) ? w : -w;
+        }
+        return (uint32_t)(a.aden * S - a.anum * (int32_t)mag[n] + (int32_t)a.bias);
+    }
+}
+
+template <bool KEY32>
+__device__ __forceinline__ unsigned long long widen(uint32_t key, uint32_t pos)
+{
+    return ((unsigned long long)key << 32) | (0xFFFFFFFFu - pos);
+}
+
+__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int d)
+{
+    uint32_t lo = __shfl_xor((uint32_t)v, d, 64), hi = __shfl_xor((uint32_t)(v >> 32), d, 64);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// maximum over the slots [s0, s0 + C) of one thread, as a 64-bit key
+// (value << 32 | ~position) where position is the slot offset in the block
+template <bool KEY32>
+__device__ __forceinline__ unsigned long long thread_best(const DecodeArgs &a, const uint32_t *keys, int s0, uint32_t pos0)
+{
+    if constexpr (KEY32) {
+        uint32_t best = 0;
+        for (int k = 0; k < a.C; k++) best = max(best, keys[s0 + k]);
+        // unpack into the common 64-bit form
+        return ((unsigned long long)(best >> a.idxb) << 32) | (0xFFFFFFFFu - (a.idxmask - (best & a.idxmask)));
+    } else {
+        uint32_t best = 0, bk = 0;
+        for (int k = 0; k < a.C; k++) {
+            const uint32_t v = keys[s0 + k];
+            const bool gt = v > best;
+            best = gt ? v : best;
+            bk = gt ? (uint32_t)k : bk;
+        }
+        return ((unsigned long long)best << 32) | (0xFFFFFFFFu - (pos0 + bk));
+    }
+}
+
+template <int DT, bool KEY32, int T>
+__device__ void decode_frame(const DecodeArgs &a, const Lds &s, int64_t f)
+{
+    using Tt = Tr<DT>;
+    using Y = typename Tt::Y;
+    using Mag = typename Tt::Mag;
+    using Chk = typename Tt::Chk;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const bool imwbf = a.weights == FWBF_IMWBF;
+    const int N = a.N, M = a.M;
+    Mag *mag = (Mag *)s.mag;
+    Chk *chk = (Chk *)s.chk;
+
+    // ---- Initialization: |y|, z_0 = [y < 0] (Section III) ----------------
+    const Y *yrow = (const Y *)a.y + f * a.stride;
+    const int Nr = (N + 63) & ~63, Mr = (M + 63) & ~63;
+    for (int n = tid; n < Nr; n += T) {
+        bool neg = false;
+        if (n < N) {
+            const Y v = yrow[n];
+            neg = v < (Y)0;
+            if constexpr (Tt::isf) mag[n] = fabsf(v);
+            else mag[n] = (Mag)(v < 0 ? -(int)v : (int)v);
+        }
+        const unsigned long long b = __ballot(neg);
+        if (lane == 0) {
+            s.zw[(n >> 5)] = (uint32_t)b;
+            s.zw[(n >> 5) + 1] = (uint32_t)(b >> 32);
+        }
+    }
+    for (int w = tid; w < (Mr >> 5); w += T) s.tog[w] = 0;
+    if (tid == 0) { s.ctl[CTL_FLAGS] = 0; s.ctl[CTL_WEIGHT] = 0; }
+    __syncthreads();
+
+    // ---- check minima (weights) and the syndrome s_0 (Step 1 at k=0) -----
+    for (int m = tid; m < Mr; m += T) {
+        bool par = false;
+        if (m < M) {
+            const uint32_t i = fdiv(m, a.magZ, a.maskZ);
+            const int r = m - (int)i * a.Z;
+            const int deg = s.rdeg[i];
+            const uint32_t *re = s.row + i * a.dcmax;
+            if constexpr (Tt::isf) {
+                float m1 = __builtin_inff(), m2 = __builtin_inff();
+                uint32_t pos = 0;
+                for (int q = 0; q < deg; q++) {
+                    const uint32_t e = re[q];
+                    int cc = r + (int)(e & 0xFFFF);
+                    cc -= (cc >= a.Z) ? a.Z : 0;
+                    const uint32_t n = (e >> 16) * a.Z + cc;
+                    const float v = mag[n];
+                    par ^= (s.zw[n >> 5] >> (n & 31)) & 1;
+                    if (v < m1) { m2 = m1; m1 = v; pos = q; }
+                    else if (v < m2) m2 = v;
+                }
+                if (deg < 2) m2 = 0.0f;  // empty minimum over N(m)\n
+                chk[m] = pack_chk<DT>(__float_as_uint(m1), __float_as_uint(m2), 0);
+                s.chkp[m] = (uint8_t)pos;
+            } else {
+                uint32_t m1 = Tt::BIG + 1, m2 = Tt::BIG + 1, pos = 0;
+                for (int q = 0; q < deg; q++) {
+                    const uint32_t e = re[q];
+                    int cc = r + (int)(e & 0xFFFF);
+                    cc -= (cc >= a.Z) ? a.Z : 0;
+                    const uint32_t n = (e >> 16) * a.Z + cc;
+                    const uint32_t v = mag[n];
+                    par ^= (s.zw[n >> 5] >> (n & 31)) & 1;
+                    if (v < m1) { m2 = m1; m1 = v; pos = q; }
+                    else if (v < m2) m2 = v;
+                }
+                if (deg < 2) m2 = 0;
+                chk[m] = pack_chk<DT>(m1 & Tt::BIG, m2 & Tt::BIG, pos);
+            }
+        }
+        const unsigned long long b = __ballot(par);
+        if (lane == 0) {
+            s.syn[m >> 5] = (uint32_t)b;
+            s.syn[(m >> 5) + 1] = (uint32_t)(b >> 32);
+            if (b) atomicAdd(&s.ctl[CTL_WEIGHT], __popcll(b));
+        }
+    }
+    __syncthreads();
+
+    int k = 0, okf = 0;
+    const int weight0 = s.ctl[CTL_WEIGHT];
+    if (weight0 == 0 || a.max_iter == 0) {
+        okf = weight0 == 0;
+    } else {
+        // ---- initial metrics (eq. (1)) into the slots ---------------------
+        for (int pi = 0; pi < a.P; pi++) {
+            const int g = pi * a.GP + (tid >> a.logL);
+            const int pos0 = (tid & (a.L - 1)) * a.C;
+            const int s0 = (pi * T + tid) * a.C;
+            for (int kk = 0; kk < a.C; kk++) {
+                const int pos = pos0 + kk;
+                const int n = g * a.p + pos;
+                uint32_t key = 0;
+                if (g < a.Geff && pos < a.p && n < N) {
+                    const uint32_t v = metric_val<DT>(a, s, n, imwbf);
+                    key = KEY32 ? ((v << a.idxb) | (a.idxmask - pos)) : v;
+                }
+                s.keys[s0 + kk] = key;
+            }
+        }
+        for (int u = tid; u < a.W; u += T) s.prv[u] = NONE;
+        if (tid < 2) s.gb[tid] = 0;
+        for (int u = tid; u < a.Geff && a.L > 64; u += T) s.gb[u] = 0;
+        __syncthreads();
+
+        for (;;) {
+            // ---- Step 2: choose at most one bit per block ------------------
+            if (a.select != FWBF_TOPL) {
+                for (int pi = 0; pi < a.P; pi++) {
+                    const int g = pi * a.GP + (tid >> a.logL);
+                    const int pos0 = (tid & (a.L - 1)) * a.C;
+                    unsigned long long best = thread_best<KEY32>(a, s.keys, (pi * T + tid) * a.C, pos0);
+                    const int lw = a.L < 64 ? a.L : 64;
+                    for (int d = 1; d < lw; d <<= 1) {
+                        const unsigned long long o = shfl_xor_u64(best, d);
+                        best = o > best ? o : best;
+                    }
+                    if (a.L <= 64) {
+                        if ((tid & (a.L - 1)) == 0 && g < a.Geff) {
+                            const uint32_t val = (uint32_t)(best >> 32);
+                            const uint32_t pos = 0xFFFFFFFFu - (uint32_t)best;
+                            const bool flip = (a.select == FWBF_SINGLE) || val > a.zero_val;
+                            s.win[g] = flip ? (uint32_t)(g * a.p) + pos : NONE;
+                        }
+                    } else if (lane == 0 && g < a.Geff) {
+                        atomicMax(&s.gb[g], best);
+                    }
+                }
+                if (a.L > 64) {
+                    __syncthreads();
+                    for (int g = tid; g < a.Geff; g += T) {
+                        const unsigned long long best = s.gb[g];
+                        s.gb[g] = 0;
+                        const uint32_t val = (uint32_t)(best >> 32);
+                        const uint32_t pos = 0xFFFFFFFFu - (uint32_t)best;
+                        const bool flip = (a.select == FWBF_SINGLE) || val > a.zero_val;
+                        s.win[g] = flip ? (uint32_t)(g * a.p) + pos : NONE;
+                    }
+                }
+            } else {
+                // top-lambda: lambda sequential maxima over the whole frame
+                // (single block layout), each excluded before the next
+                int cnt = 0;
+                for (int t = 0; t < a.lambda; t++) {
+                    unsigned long long best = thread_best<KEY32>(a, s.keys, tid * a.C, (tid & (a.L - 1)) * a.C);
+                    for (int d = 1; d < 64; d <<= 1) {
+                        const unsigned long long o = shfl_xor_u64(best, d);
+                        best = o > best ? o : best;
+                    }
+                    if (lane == 0) atomicMax(&s.gb[t & 1], best);
+                    __syncthreads();
+                    best = s.gb[t & 1];
+                    const uint32_t val = (uint32_t)(best >> 32);
+                    const uint32_t pos = 0xFFFFFFFFu - (uint32_t)best;
+                    if (val <= a.zero_val) break;  // uniform: every thread read the same value
+                    if (tid == 0) {
+                        s.gb[(t + 1) & 1] = 0;
+                        s.topn[t] = pos;
+                        s.topk[t] = s.keys[pos];
+                        s.keys[pos] = 0;
+                    }
+                    cnt = t + 1;
+                    __syncthreads();
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    s.gb[0] = 0;
+                    s.gb[1] = 0;
+                    // restore, then list the chosen bits in ascending order
+                    for (int t = 0; t < cnt; t++) s.keys[s.topn[t]] = (uint32_t)s.topk[t];
+                    for (int t = 1; t < cnt; t++) {
+                        const uint32_t v = s.topn[t];
+                        int u = t - 1;
+                        while (u >= 0 && s.topn[u] > v) { s.topn[u + 1] = s.topn[u]; u--; }
+                        s.topn[u + 1] = v;
+                    }
+                    for (int t = 0; t < a.W; t++) s.win[t] = t < cnt ? s.topn[t] : NONE;
+                }
+            }
+            __syncthreads();
+
+            // ---- flip the chosen bits; toggle parity of their checks -------
+            for (int u = tid; u < a.W; u += T) {
+                const uint32_t n = s.win[u];
+                const uint32_t pv = s.prv[u];
+                s.prv[u] = n;
+                int fl = (n != pv) ? F_DIFF : 0;
+                if (n != NONE) {
+                    fl |= F_ANY;
+                    atomicXor(&s.zw[n >> 5], 1u << (n & 31));
+                    const uint32_t j = fdiv(n, a.magZ, a.maskZ);
+                    const int c = (int)(n - j * a.Z);
+                    for (int t = 0; t < s.cdeg[j]; t++) {
+                        const uint32_t e = s.col[j * a.dvmax + t];
+                        int r = c - (int)(e & 0xFFFF);
+                        r += (r < 0) ? a.Z : 0;
+                        const uint32_t m = (e >> 24) * a.Z + r;
+                        atomicXor(&s.tog[m >> 5], 1u << (m & 31));
+                    }
+                }
+                if (fl) atomicOr(&s.ctl[CTL_FLAGS], fl);
+            }
+            __syncthreads();
+            const int flags = s.ctl[CTL_FLAGS];
+            if (!(a.flags & FWBF_FLAG_NO_CYCLE_EXIT)) {
+                if (!(flags & F_ANY)) {  // no flip: fixed point until K_max
+                    k = a.max_iter;
+                    break;
+                }
+                if (!(flags & F_DIFF)) {
+                    // same flips as the previous round: z_{k+1} = z_{k-1}, the
+                    // states alternate; z_{K_max} = z_k iff K_max - k is even
+                    if (((a.max_iter - k) & 1) == 0)
+                        for (int u = tid; u < a.W; u += T) {
+                            const uint32_t n = s.win[u];
+                            if (n != NONE) atomicXor(&s.zw[n >> 5], 1u << (n & 31));
+                        }
+                    k = a.max_iter;
+                    break;
+                }
+            }
+
+            // ---- claim net-toggled checks; update syndrome and its weight --
+            for (int u = tid; u < a.W; u += T) {
+                const uint32_t n = s.win[u];
+                uint32_t *tl = s.tl + u * a.dvmax;
+                for (int t = 0; t < a.dvmax; t++) tl[t] = NONE;
+                if (n == NONE) continue;
+                const uint32_t j = fdiv(n, a.magZ, a.maskZ);
+                const int c = (int)(n - j * a.Z);
+                for (int t = 0; t < s.cdeg[j]; t++) {
+                    const uint32_t e = s.col[j * a.dvmax + t];
+                    int r = c - (int)(e & 0xFFFF);
+                    r += (r < 0) ? a.Z : 0;
+                    const uint32_t m = (e >> 24) * a.Z + r;
+                    const uint32_t bit = 1u << (m & 31);
+                    const uint32_t old = atomicAnd(&s.tog[m >> 5], ~bit);
+                    if (old & bit) {
+                        const uint32_t so = atomicXor(&s.syn[m >> 5], bit);
+                        atomicAdd(&s.ctl[CTL_WEIGHT], (so & bit) ? -1 : 1);
+                        tl[t] = m;
+                    }
+                }
+            }
+            __syncthreads();
+            const int weight = s.ctl[CTL_WEIGHT];
+            if (tid == 0) s.ctl[CTL_FLAGS] = 0;
+            k += 1;
+            if (weight == 0) { okf = 1; break; }
+            if (k == a.max_iter) break;
+
+            // ---- update the metrics of every bit of a toggled check --------
+            const int ntask = a.W * a.dvmax * a.dcmax;
+            for (int id = tid; id < ntask; id += T) {
+                const uint32_t e0 = fdiv(id, a.magD, a.maskD);
+                const uint32_t q = id - e0 * a.dcmax;
+                const uint32_t m = s.tl[e0];
+                if (m == NONE) continue;
+                const uint32_t i = fdiv(m, a.magZ, a.maskZ);
+                if ((int)q >= s.rdeg[i]) continue;
+                const int r = (int)(m - i * a.Z);
+                const uint32_t e = s.row[i * a.dcmax + q];
+                int cc = r + (int)(e & 0xFFFF);
+                cc -= (cc >= a.Z) ? a.Z : 0;
+                const uint32_t n = (e >> 16) * a.Z + cc;
+                const uint32_t g = fdiv(n, a.magP, a.maskP);
+                const uint32_t slot = g * a.Lc + (n - g * a.p);
+                if constexpr (Tt::isf) {
+                    s.keys[slot] = metric_val<DT>(a, s, n, imwbf);  // KEY32 is never used for float
+                } else {
+                    const int32_t w = weight_i<DT>(chk[m], q, imwbf);
+                    const int32_t d = ((s.syn[m >> 5] >> (m & 31)) & 1) ? 2 * a.aden * w : -2 * a.aden * w;
+                    atomicAdd(&s.keys[slot], KEY32 ? ((uint32_t)d << a.idxb) : (uint32_t)d);
+                }
+            }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+
+    // ---- output z_k, rounds, syndrome flag --------------------------------
+    const int NW = (N + 31) >> 5;
+    uint32_t *zo = a.z + f * NW;
+    for (int w = tid; w < NW; w += T) zo[w] = s.zw[w];
+    if (tid == 0) {
+        a.iters[f] = k;
+        a.ok[f] = (uint8_t)okf;
+    }
+    __syncthreads();
+}
+
+template <int DT, bool KEY32, int T>
+__global__ __launch_bounds__(T) void decode_kernel(DecodeArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    Lds s;
+    s.keys = (uint32_t *)(smem + a.o_keys);
+    s.chk = smem + a.o_chk;
+    s.chkp = smem + a.o_chkp;
+    s.mag = smem + a.o_mag;
+    s.zw = (uint32_t *)(smem + a.o_z);
+    s.syn = (uint32_t *)(smem + a.o_syn);
+    s.tog = (uint32_t *)(smem + a.o_tog);
+    s.win = (uint32_t *)(smem + a.o_win);
+    s.prv = (uint32_t *)(smem + a.o_prv);
+    s.tl = (uint32_t *)(smem + a.o_tl);
+    s.gb = (unsigned long long *)(smem + a.o_gb);
+    s.topk = (unsigned long long *)(smem + a.o_top);
+    s.topn = (uint32_t *)(smem + a.o_top + 8 * a.lambda);
+    s.ctl = (int *)(smem + a.o_ctl);
+    s.col = (uint32_t *)(smem + a.o_col);
+    s.row = (uint32_t *)(smem + a.o_row);
+    s.cdeg = smem + a.o_cdeg;
+    s.rdeg = smem + a.o_rdeg;
+    for (int t = threadIdx.x; t < a.nb * a.dvmax; t += T) s.col[t] = a.col[t];
+    for (int t = threadIdx.x; t < a.mb * a.dcmax; t += T) s.row[t] = a.row[t];
+    for (int t = threadIdx.x; t < a.nb; t += T) s.cdeg[t] = a.coldeg[t];
+    for (int t = threadIdx.x; t < a.mb; t += T) s.rdeg[t] = a.rowdeg[t];
+    __syncthreads();
+    for (int64_t f = blockIdx.x; f < a.F; f += gridDim.x) decode_frame<DT, KEY32, T>(a, s, f);
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+void magic(uint32_t d, uint32_t *mag, uint32_t *mask)
+{
+    if (d <= 1) { *mag = 0; *mask = 0xFFFFFFFFu; return; }
+    *mag = (uint32_t)(((1ULL << 32) + d - 1) / d);  // ceil(2^32 / d), exact for n*d < 2^32
+    *mask = 0;
+}
+
+int ilog2(uint32_t v) { int r = 0; while ((1u << r) < v) r++; return r; }
+
+struct Plan {
+    int C, L, P;
+    long cost;
+};
+
+// choose C (slots per thread) and L (threads per block, a power of two)
+Plan plan_layout(int Geff, int p, int T)
+{
+    Plan best{0, 0, 0, -1};
+    for (int C = 1; C <= 64; C++) {
+        const int need = (p + C - 1) / C;
+        const int L = 1 << ilog2(need);
+        if (L > T) continue;
+        const int GP = T / L;
+        const int P = (Geff + GP - 1) / GP;
+        const long cost = (long)P * C + 2L * P * std::min(ilog2(L), 6) + (L > 64 ? 8 : 0);
+        if (best.cost < 0 || cost < best.cost) best = Plan{C, L, P, cost};
+    }
+    return best;
+}
+
+template <int DT, bool KEY32>
+hipError_t launch_t(int T, const DecodeArgs &a, int grid, hipStream_t st)
+{
+    switch (T) {
+#define FWBF_CASE(TT)                                                                                 \
+    case TT:                                                                                          \
+        if (a.lds_bytes > 65536)                                                                      \
+            (void)hipFuncSetAttribute((const void *)decode_kernel<DT, KEY32, TT>,                     \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, a.lds_bytes);       \
+        hipLaunchKernelGGL((decode_kernel<DT, KEY32, TT>), dim3(grid), dim3(TT), a.lds_bytes, st, a); \
+        return hipGetLastError();
+        FWBF_CASE(64)
+        FWBF_CASE(128)
+        FWBF_CASE(256)
+        FWBF_CASE(512)
+        FWBF_CASE(1024)
+#undef FWBF_CASE
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int DT, bool KEY32>
+int occupancy_t(int T, int lds, int *blocks)
+{
+    hipError_t e = hipErrorInvalidValue;
+    switch (T) {
+#define FWBF_CASE(TT)                                                                               \
+    case TT:                                                                                        \
+        if (lds > 65536)                                                                            \
+            (void)hipFuncSetAttribute((const void *)decode_kernel<DT, KEY32, TT>,                   \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);             \
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, decode_kernel<DT, KEY32, TT>, TT, lds); \
+        break;
+        FWBF_CASE(64)
+        FWBF_CASE(128)
+        FWBF_CASE(256)
+        FWBF_CASE(512)
+        FWBF_CASE(1024)
+#undef FWBF_CASE
+    }
+    return e == hipSuccess ? FWBF_OK : hip_fail(e, "occupancy query");
+}
+
+int dispatch(int DT, bool key32, int T, const DecodeArgs &a, int grid, hipStream_t st)
+{
+    hipError_t e;
+    if (DT == FWBF_I8) e = key32 ? launch_t<FWBF_I8, true>(T, a, grid, st) : launch_t<FWBF_I8, false>(T, a, grid, st);
+    else if (DT == FWBF_I16) e = key32 ? launch_t<FWBF_I16, true>(T, a, grid, st) : launch_t<FWBF_I16, false>(T, a, grid, st);
+    else e = launch_t<FWBF_F32, false>(T, a, grid, st);
+    return e == hipSuccess ? FWBF_OK : hip_fail(e, "decode kernel launch");
+}
+
+int occupancy(int DT, bool key32, int T, int lds, int *blocks)
+{
+    if (DT == FWBF_I8) return key32 ? occupancy_t<FWBF_I8, true>(T, lds, blocks) : occupancy_t<FWBF_I8, false>(T, lds, blocks);
+    if (DT == FWBF_I16) return key32 ? occupancy_t<FWBF_I16, true>(T, lds, blocks) : occupancy_t<FWBF_I16, false>(T, lds, blocks);
+    return occupancy_t<FWBF_F32, false>(T, lds, blocks);
+}
+
+}  // namespace
+
+// Validates parameters and fills the kernel arguments (everything but the
+// data pointers).  Shared by the plain decoder and the batched launch.
+int prepare_decode(const fwbf_code *c, const fwbf_params *p, DecodeArgs *out, int *T_out);
+
+int prepare_decode(const fwbf_code *c, const fwbf_params *p, DecodeArgs *out, int *T_out)
+{
+    if (!c || !p) return fail(FWBF_E_INVALID, "null code or params");
+    if (p->dtype < FWBF_F32 || p->dtype > FWBF_I16) return fail(FWBF_E_INVALID, "unknown dtype");
+    if (p->weights < FWBF_WBF || p->weights > FWBF_IMWBF) return fail(FWBF_E_INVALID, "unknown weights");
+    if (p->select < FWBF_GROUPS || p->select > FWBF_TOPL) return fail(FWBF_E_INVALID, "unknown select");
+    if (p->select == FWBF_GROUPS && (p->groups < 1 || p->groups > c->N))
+        return fail(FWBF_E_INVALID, "groups must be in [1, N]");
+    if (p->select == FWBF_TOPL && (p->lambda < 1 || p->lambda > 64))
+        return fail(FWBF_E_INVALID, "lambda must be in [1, 64]");
+    if (p->max_iter < 0) return fail(FWBF_E_INVALID, "max_iter must be >= 0");
+    if (p->dtype != FWBF_F32 && (p->alpha_den < 1 || p->alpha_num < 0))
+        return fail(FWBF_E_INVALID, "alpha_num must be >= 0 and alpha_den >= 1");
+    if (p->dtype == FWBF_F32 && !(p->alpha == p->alpha)) return fail(FWBF_E_INVALID, "alpha is NaN");
+
+    DecodeArgs a;
+    memset(&a, 0, sizeof a);
+    a.N = c->N; a.M = c->M; a.Z = c->Z; a.mb = c->mb; a.nb = c->nb;
+    a.dvmax = c->dv_max; a.dcmax = c->dc_max;
+    a.weights = p->weights; a.select = p->select; a.max_iter = p->max_iter;
+    a.lambda = p->select == FWBF_TOPL ? p->lambda : 1;
+    a.alpha = p->weights == FWBF_WBF ? 0.0f : p->alpha;
+    a.anum = p->weights == FWBF_WBF ? 0 : p->alpha_num;
+    a.aden = p->alpha_den;
+    a.flags = p->flags;
+
+    int T = p->threads_per_frame;
+    if (T == 0) T = c->N <= 2048 ? 64 : c->N <= 4096 ? 128 : c->N <= 16384 ? 256 : 1024;
+    if (T != 64 && T != 128 && T != 256 && T != 512 && T != 1024)
+        return fail(FWBF_E_INVALID, "threads_per_frame must be 0, 64, 128, 256, 512 or 1024");
+
+    const int G = p->select == FWBF_GROUPS ? p->groups : 1;
+    a.p = (c->N + G - 1) / G;
+    a.Geff = (c->N + a.p - 1) / a.p;
+    Plan pl = plan_layout(a.Geff, a.p, T);
+    if (pl.cost < 0) return fail(FWBF_E_UNSUPPORTED, "block too long for threads_per_frame (use more threads)");
+    if (p->select == FWBF_TOPL && pl.P != 1) return fail(FWBF_E_UNSUPPORTED, "top-lambda layout");
+    a.C = pl.C; a.L = pl.L; a.logL = ilog2(pl.L); a.GP = T / pl.L; a.P = pl.P; a.Lc = pl.L * pl.C;
+    a.W = p->select == FWBF_TOPL ? p->lambda : a.Geff;
+    // the update phase divides task ids < W*dv*dc by dc with a 32-bit magic
+    if ((int64_t)a.W * c->dv_max * c->dc_max * c->dc_max >= (1LL << 32))
+        return fail(FWBF_E_UNSUPPORTED, "too many blocks for this code's degrees");
+
+    // value range of the metric
+    bool key32 = false;
+    if (p->dtype == FWBF_F32) {
+        a.bias = 0;
+        a.zero_val = 0x80000000u;  // orderable(+0)
+    } else {
+        const int64_t maxmag = p->dtype == FWBF_I8 ? 128 : 32768;
+        const int64_t maxE = maxmag * ((int64_t)a.aden * c->dv_max + a.anum);
+        if (maxE >= (1LL << 30)) return fail(FWBF_E_UNSUPPORTED, "alpha_num/alpha_den too large for 32-bit metrics");
+        int vb = 1;
+        while ((1LL << (vb - 1)) <= maxE) vb++;
+        a.bias = 1u << (vb - 1);
+        a.zero_val = a.bias;
+        a.idxb = ilog2((uint32_t)a.Lc);
+        if (vb + a.idxb <= 32) key32 = true;
+        a.idxmask = key32 ? (a.idxb ? ((1u << a.idxb) - 1) : 0) : 0;
+    }
+    magic(a.Z, &a.magZ, &a.maskZ);
+    magic(a.p, &a.magP, &a.maskP);
+    magic(a.dcmax, &a.magD, &a.maskD);
+
+    // LDS layout
+    int off = 0;
+    auto take = [&](int bytes, int align) { off = (off + align - 1) / align * align; int o = off; off += bytes; return o; };
+    const int slots = a.P * T * a.C;
+    const int Nr = (c->N + 63) / 64 * 64, Mr = (c->M + 63) / 64 * 64;
+    a.o_keys = take(4 * slots, 16);
+    const int chk_sz = p->dtype == FWBF_I8 ? 4 : 8;
+    a.o_chk = take(chk_sz * c->M, 8);
+    a.o_chkp = take(p->dtype == FWBF_F32 ? c->M : 0, 4);
+    const int mag_sz = p->dtype == FWBF_I8 ? 1 : p->dtype == FWBF_I16 ? 2 : 4;
+    a.o_mag = take(mag_sz * c->N, 4);
+    a.o_z = take(Nr / 8, 8);
+    a.o_syn = take(Mr / 8, 8);
+    a.o_tog = take(Mr / 8, 8);
+    a.o_win = take(4 * a.W, 4);
+    a.o_prv = take(4 * a.W, 4);
+    a.o_tl = take(4 * a.W * a.dvmax, 4);
+    a.o_gb = take(8 * std::max(a.Geff, 2), 8);
+    a.o_top = take(12 * a.lambda, 8);
+    a.o_ctl = take(16, 4);
+    a.o_col = take(4 * c->nb * c->dv_max, 4);
+    a.o_row = take(4 * c->mb * c->dc_max, 4);
+    a.o_cdeg = take(c->nb, 1);
+    a.o_rdeg = take(c->mb, 1);
+    a.lds_bytes = (off + 15) / 16 * 16;
+    if (a.lds_bytes > 160 * 1024) return fail(FWBF_E_UNSUPPORTED, "frame state exceeds 160 KiB of LDS");
+    a.idxb = key32 ? a.idxb : 0;
+    *out = a;
+    *T_out = T;
+    return key32 ? 1 : 0;
+}
+
+}  // namespace fwbf
+
+using namespace fwbf;
+
+extern "C" int fwbf_decode(const fwbf_code *code, const fwbf_params *params, const void *y_dev, int64_t F,
+                           int64_t y_stride, uint32_t *z_dev, int32_t *iters_dev, uint8_t *ok_dev,
+                           void *stream)
+{
+    DecodeArgs a;
+    int T = 0;
+    const int k = prepare_decode(code, params, &a, &T);
+    if (k < 0) return k;
+    const bool key32 = k == 1;
+    if (F < 0) return fail(FWBF_E_INVALID, "F must be >= 0");
+    if (y_stride < code->N) return fail(FWBF_E_INVALID, "y_stride must be >= N");
+    if (F == 0) return FWBF_OK;
+    if (!y_dev || !z_dev || !iters_dev || !ok_dev) return fail(FWBF_E_INVALID, "null buffer");
+    DeviceTables t;
+    int rc = device_tables(const_cast<fwbf_code *>(code), &t);
+    if (rc) return rc;
+    a.y = y_dev; a.F = F; a.stride = y_stride;
+    a.z = z_dev; a.iters = iters_dev; a.ok = ok_dev;
+    a.col = t.col; a.row = t.row; a.coldeg = t.coldeg; a.rowdeg = t.rowdeg;
+    int dev = 0, cus = 0, blocks = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    rc = occupancy(params->dtype, key32, T, a.lds_bytes, &blocks);
+    if (rc) return rc;
+    if (blocks < 1) return fail(FWBF_E_UNSUPPORTED, "decode kernel does not fit on a compute unit");
+    const int64_t grid = std::min<int64_t>(F, (int64_t)blocks * cus);
+    return dispatch(params->dtype, key32, T, a, (int)grid, (hipStream_t)stream);
+}

@@ -1,0 +1,104 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry
+point include/fwbf.h declares, its host-side code construction and encoder
+agree with the oracle's independent implementation, and invalid arguments
+are rejected with the documented error codes before anything is enqueued."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from conftest import CODES, ROOT
+from paper_1206_3362_amd import fwbf
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "fwbf.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^[A-Za-z_][\w\s\*]*?\b(fwbf_\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_exports_every_declared_symbol():
+    L = fwbf.lib()
+    names = header_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(fwbf.EXPORTS) == [n for n in names if n in fwbf.EXPORTS]
+    assert set(names) <= set(fwbf.EXPORTS) | set(getattr(fwbf, "EXPORTS_EXTRA", []))
+    assert fwbf.version().startswith("fwbf")
+
+
+@pytest.mark.parametrize("name", list(CODES))
+def test_seeded_draw_matches_oracle(name):
+    g = fwbf.Code.from_seed(*CODES[name])
+    o = O.Code.from_seed(*CODES[name])
+    assert np.array_equal(g.shifts(), o.shifts)
+    assert not g.has_4cycle()
+    assert (g.N, g.M) == (o.N, o.M)
+
+
+def test_girth4_draws_match_oracle_and_flag_cycles():
+    for s in range(12):
+        g = fwbf.Code.from_seed(3, 6, 7, s, min_girth=4)
+        o = O.Code.from_seed(3, 6, 7, s, min_girth=4)
+        assert np.array_equal(g.shifts(), o.shifts)
+        assert g.has_4cycle() == o.violates_rc()
+
+
+@pytest.mark.parametrize("name", ["n186", "n1008", "n4032", "n8000"])
+def test_rank_info_set_and_encoder_match_oracle(name):
+    g = fwbf.Code.from_seed(*CODES[name])
+    o = O.Code.from_seed(*CODES[name])
+    assert g.K == o.K
+    assert np.array_equal(g.info_positions(), o.info_positions())
+    assert np.array_equal(g.encode(5, 0, 32), o.encode(5, 0, 32))
+    assert np.array_equal(g.encode(99, 1000, 4), o.encode(99, 1000, 4))
+
+
+def test_text_roundtrip_and_parse_errors():
+    txt = "qc-ldpc v1\n# c\nZ 5\nbase 2 3\n0 1 -1\n2 -1 4\n"
+    g = fwbf.Code.from_text(txt)
+    assert g.text() == O.Code.from_text(txt).to_text()
+    assert np.array_equal(fwbf.Code.from_text(g.text()).shifts(), g.shifts())
+    for bad in ["", "qc-ldpc v1\nZ 3\nbase 1 2\n0\n", "qc-ldpc v1\nZ 3\nbase 1 1\n3\n",
+                "qc-ldpc v1\nZ 3\nbase 1 1\n0 0\n", "nope"]:
+        with pytest.raises(fwbf.FwbfError) as e:
+            fwbf.Code.from_text(bad)
+        assert e.value.code == fwbf.E_PARSE
+    with pytest.raises(fwbf.FwbfError) as e:
+        fwbf.Code.from_seed(3, 6, 31, 1, min_girth=5)
+    assert e.value.code == fwbf.E_INVALID
+
+
+def _decode_rc(code, F=1, **kw):
+    p = fwbf.DecodeParams(**kw).c()
+    L = fwbf.lib()
+    return L.fwbf_decode(code._h, C.byref(p), None, F, code.N, None, None, None, None)
+
+
+def test_decode_argument_validation_without_gpu():
+    g = fwbf.Code.from_seed(3, 6, 31, 1)
+    bad = [dict(groups=0), dict(groups=g.N + 1), dict(max_iter=-1), dict(select=2, lam=0),
+           dict(select=7), dict(weights=9), dict(dtype=5), dict(dtype=1, alpha_den=0),
+           dict(dtype=1, alpha_num=-1), dict(threads_per_frame=100)]
+    for kw in bad:
+        assert _decode_rc(g, **kw) == fwbf.E_INVALID, kw
+        assert fwbf.lib().fwbf_last_error()
+    # a valid call with F = 0 is a no-op and touches no device
+    assert _decode_rc(g, F=0, dtype=1) == fwbf.OK
+    # F > 0 with null buffers
+    assert _decode_rc(g, F=4, dtype=1) == fwbf.E_INVALID
+    # too large a rational alpha for 32-bit metrics
+    assert _decode_rc(g, F=4, dtype=2, alpha_num=1 << 20, alpha_den=1 << 10) == fwbf.E_UNSUPPORTED
+
+
+def test_channel_and_count_validation_without_gpu():
+    L = fwbf.lib()
+    assert L.fwbf_channel(0, 1, 0, None, 0, 1, 0, 1.0, None, 1.0, 0, None, 1, None) == fwbf.E_INVALID
+    assert L.fwbf_channel(8, 1, 0, None, 0, 1, 0, 1.0, None, 1.0, 9, None, 8, None) == fwbf.E_INVALID
+    assert L.fwbf_channel(8, 0, 0, None, 0, 1, 0, 1.0, None, 1.0, 0, None, 8, None) == fwbf.OK
+    assert L.fwbf_count(8, 1, 0, None, None, 0, None, None, -1, None, None) == fwbf.E_INVALID
+    assert L.fwbf_count(8, 0, 0, None, None, 0, None, None, 10, None, None) == fwbf.OK

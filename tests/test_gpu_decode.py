@@ -1,0 +1,160 @@
+"""Parity of the HIP decoder (fwbf_decode through the C ABI) with the CPU
+oracle: every output (packed hard decisions, rounds, syndrome flag) must be
+bit-exact, for integer and float inputs, every weight and selection variant,
+exhaustive single and double error patterns, ties, subnormals, signed zeros,
+degenerate calls and the sizes of the workloads."""
+import numpy as np
+import pytest
+
+import oracle as O
+from conftest import CODES
+from gpu_util import assert_same, gpu_decode, need_gpu, oracle_decode, torch
+from paper_1206_3362_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def codes():
+    need_gpu()
+    from paper_1206_3362_amd import fwbf
+    cache = {}
+
+    def get(name):
+        if name not in cache:
+            cache[name] = (fwbf.Code.from_seed(*CODES[name]), O.Code.from_seed(*CODES[name]))
+        return cache[name]
+    return get
+
+
+def run_both(codes, name, y, **kw):
+    g, o = codes(name)
+    print(f"case {name} dtype={y.dtype} F={y.shape[0]} {kw}", flush=True)
+    return gpu_decode(g, y, **kw), oracle_decode(o, y, **kw)
+
+
+def test_small_workload_wbf_f32(codes):
+    """N=186 (3,6) code, all-zero codeword, 3 dB, float, WBF, alpha 0.2, G=6,
+    50 rounds, 1000 frames."""
+    g, o = codes("n186")
+    y = synth.awgn_frames(g.N, 1000, synth.sigma_for(3.0, g.rate), 100, None, np.float32)
+    a, b = run_both(codes, "n186", y, weights=0, groups=6, max_iter=50, alpha=0.2)
+    assert_same(a, b, "n186 wbf f32")
+
+
+@pytest.mark.parametrize("ebn0", [2.0, 4.0, 6.0])
+def test_n1008_int8_codewords(codes, ebn0):
+    g, o = codes("n1008")
+    F = 4096
+    pool = o.encode(seed=77, first=0, count=256)
+    cb = O.unpack(pool[np.arange(F) % 256], g.N)
+    y = synth.awgn_frames(g.N, F, synth.sigma_for(ebn0, g.rate), int(ebn0 * 10), cb, np.int8)
+    a, b = run_both(codes, "n1008", y, weights=2, groups=8, max_iter=100, alpha_num=1, alpha_den=5)
+    assert_same(a, b, f"n1008 i8 {ebn0}dB")
+
+
+VARIANTS = [dict(weights=w, alpha=0.2, alpha_num=1, alpha_den=5) for w in (0, 1, 2)]
+SELECTS = [dict(select=0, groups=1), dict(select=0, groups=8), dict(select=0, groups=126),
+           dict(select=0, groups=1008), dict(select=1), dict(select=2, lam=1),
+           dict(select=2, lam=10)]
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.int8, np.int16])
+@pytest.mark.parametrize("sel", SELECTS, ids=lambda s: "-".join(f"{k}{v}" for k, v in s.items()))
+def test_variants_n1008(codes, dt, sel):
+    g, o = codes("n1008")
+    F = 512
+    y = synth.awgn_frames(g.N, F, synth.sigma_for(5.0, g.rate), 5, None, dt)
+    for v in VARIANTS:
+        a, b = run_both(codes, "n1008", y, max_iter=60, **v, **sel)
+        assert_same(a, b, f"{dt} {sel} {v}")
+
+
+@pytest.mark.parametrize("G", [1, 2, 6, 31, 186])
+def test_exhaustive_single_and_double_errors_n186(codes, G):
+    g, o = codes("n186")
+    singles = [[e] for e in range(g.N)]
+    doubles = [[a, b] for a in range(g.N) for b in range(a + 1, g.N)]
+    for dt, A in ((np.int8, 16), (np.float32, 1.0)):
+        y = synth.error_pattern_frames(g.N, singles + doubles, A, dt)
+        for v in VARIANTS:
+            a, b = run_both(codes, "n186", y, groups=G, max_iter=50, **v)
+            assert_same(a, b, f"n186 patterns G={G} {dt} {v}")
+        if G == 6:
+            assert (a[1][:g.N] == 1).all() and (a[2] == 1).all()
+
+
+def test_exhaustive_single_errors_n1008(codes):
+    g, o = codes("n1008")
+    y = synth.error_pattern_frames(g.N, [[e] for e in range(g.N)], 16, np.int8)
+    for G in (1, 8, 126, 1008):
+        a, b = run_both(codes, "n1008", y, groups=G, max_iter=100)
+        assert_same(a, b, f"n1008 singles G={G}")
+        assert (a[1] == 1).all() and (a[0] == 0).all()
+
+
+@pytest.mark.parametrize("kind", ["ties_f32", "ties_i8", "ties_i16", "subnormal"])
+def test_ties_zeros_subnormals(codes, kind):
+    g, o = codes("n1008")
+    F = 512
+    if kind == "subnormal":
+        y = synth.subnormal_frames(g.N, F, 3)
+    else:
+        dt = {"ties_f32": np.float32, "ties_i8": np.int8, "ties_i16": np.int16}[kind]
+        y = synth.tie_heavy_frames(g.N, F, 9, dt)
+    for sel in (dict(select=0, groups=8), dict(select=1), dict(select=2, lam=5)):
+        for v in VARIANTS:
+            a, b = run_both(codes, "n1008", y, max_iter=40, **v, **sel)
+            assert_same(a, b, f"{kind} {sel} {v}")
+
+
+def test_cycle_exit_is_exact(codes):
+    """Outputs with the repeated-state shortcut equal those of running every
+    round (both on the GPU) and the oracle's."""
+    g, o = codes("n1008")
+    y = synth.awgn_frames(g.N, 2048, synth.sigma_for(3.0, g.rate), 31, None, np.int8)
+    for sel in (dict(select=0, groups=8), dict(select=1), dict(select=2, lam=4)):
+        fast = gpu_decode(g, y, max_iter=57, **sel)
+        slow = gpu_decode(g, y, max_iter=57, flags=1, **sel)
+        assert_same(fast, slow, f"shortcut {sel}")
+        assert_same(fast, oracle_decode(o, y, max_iter=57, **sel), f"oracle {sel}")
+
+
+def test_degenerate_calls(codes):
+    from paper_1206_3362_amd import fwbf
+    g, o = codes("n186")
+    y = synth.awgn_frames(g.N, 64, 0.9, 2, None, np.int8)
+    a, b = run_both(codes, "n186", y, groups=6, max_iter=0)
+    assert_same(a, b, "max_iter 0")
+    a, b = run_both(codes, "n186", y, groups=6, max_iter=1)
+    assert_same(a, b, "max_iter 1")
+    # strided frames: every other row of a wider buffer
+    wide = np.zeros((64, 256), np.int8)
+    wide[:, :g.N] = y
+    yd = torch.from_numpy(wide).to("cuda")[:, :g.N]
+    z, it, ok = fwbf.decode(g, yd, fwbf.DecodeParams(dtype=fwbf.I8, groups=6))
+    zo, ito, oko = O.decode(o, y, G=6)
+    assert np.array_equal(z.cpu().numpy().view(np.uint32), zo)
+    assert np.array_equal(it.cpu().numpy(), ito)
+    # F = 0 is a no-op
+    z, it, ok = fwbf.decode(g, yd[:0], fwbf.DecodeParams(dtype=fwbf.I8, groups=6))
+    assert z.shape[0] == 0
+    # threads per frame does not change results
+    for T in (64, 128, 256):
+        a = gpu_decode(g, y, groups=6, threads_per_frame=T)
+        assert_same(a, b if False else oracle_decode(o, y, groups=6), f"T={T}")
+
+
+@pytest.mark.parametrize("name,dt,G,F,ebn0", [
+    ("n4032", np.float32, 32, 256, 4.0),
+    ("n8000", np.float32, 64, 128, 5.0),
+    ("n32400", np.int16, 64, 32, 6.0),
+])
+def test_large_codes(codes, name, dt, G, F, ebn0):
+    g, o = codes(name)
+    pool = o.encode(seed=3, first=0, count=8)
+    cb = O.unpack(pool[np.arange(F) % 8], g.N)
+    y = synth.awgn_frames(g.N, F, synth.sigma_for(ebn0, g.rate), 17, cb, dt)
+    for sel in (dict(select=0, groups=G), dict(select=0, groups=1)):
+        a, b = run_both(codes, name, y, max_iter=100, **sel)
+        assert_same(a, b, f"{name} {sel}")
