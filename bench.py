@@ -1,0 +1,185 @@
+"""Decoded throughput of plain FWBF on one MI355X.
+
+Workload: the (3,6)-regular QC-LDPC code with Z=168 (N=1008, M=504, seeded
+draw, seed 2), random codewords from the seeded systematic encoder, BPSK over
+AWGN at Eb/N0 = 4 dB, y quantised to int8 (scale 16), IMWBF metric (eq. (1))
+with alpha = 1/5, G = 8 blocks (p = 126), at most 100 flip rounds, 2^20
+frames per batch.  Frames are generated on the GPU (Philox + Box-Muller)
+before the timed region; a step decodes one resident batch and accumulates
+its error counts.  Value = coded decoded Gb/s = frames * N / time.
+
+Prints one JSON line (rank 0).  Only N=1 is supported: the decoder runs on a
+single GPU (frames are independent; see the design notes for sharding).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "decoded Gb/s at fixed FER (N=1008, 4 dB), learned vs plain FWBF; % HBM peak"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--frames", type=int, default=1 << 20)
+    ap.add_argument("--ebn0", type=float, default=4.0)
+    ap.add_argument("--groups", type=int, default=8)
+    ap.add_argument("--max-iter", type=int, default=100)
+    ap.add_argument("--batches", type=int, default=2, help="distinct resident batches cycled")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target CPU time of the oracle baseline sample (0 = skip)")
+    ap.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "traffic_decode_n1008_i8_4db.json"))
+    return ap.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the FWBF decoder has no multi-GPU path "
+              "(frames are independent; see the design notes for how it would shard).",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1206_3362_amd import fwbf, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    code = fwbf.Code.from_seed(3, 6, 168, 2)
+    N, K = code.N, code.K
+    sigma = float(synth.sigma_for(a.ebn0, code.rate))
+    pool_h = code.encode(seed=1001, first=0, count=1024)
+    pool = torch.from_numpy(pool_h.view(np.int32)).to(dev)
+    F = a.frames
+    ys = []
+    for b in range(a.batches):
+        y = torch.empty((F, N), dtype=torch.int8, device=dev)
+        fwbf.channel_into(N, y, b * F, pool, seed=1100, stream_id=4, sigma=sigma, scale=16.0)
+        ys.append(y)
+    params = fwbf.DecodeParams(dtype=fwbf.I8, weights=fwbf.IMWBF, select=fwbf.GROUPS,
+                               groups=a.groups, max_iter=a.max_iter, alpha_num=1, alpha_den=5)
+    z = torch.empty((F, (N + 31) // 32), dtype=torch.int32, device=dev)
+    it = torch.empty(F, dtype=torch.int32, device=dev)
+    ok = torch.empty(F, dtype=torch.uint8, device=dev)
+    counters = torch.zeros(7 + a.max_iter, dtype=torch.int64, device=dev)
+
+    def step(s, ev=None):
+        b = s % a.batches
+        if ev is not None:
+            ev[0].record()
+        fwbf.decode_into(code, ys[b], params, z, it, ok)
+        if ev is not None:
+            ev[1].record()
+        fwbf.count_into(N, z, pool, b * F, it, ok, a.max_iter, counters)
+
+    for s in range(a.warmup):
+        step(s)
+    torch.cuda.synchronize()
+    counters.zero_()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(a.steps)]
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record()
+    for s in range(a.steps):
+        step(s, evs[s])
+    t1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = t0.elapsed_time(t1)
+    dec_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
+    ms_step = total_ms / a.steps
+    c = counters.cpu().numpy()
+    frames = int(c[4])
+    value = F * N / (ms_step * 1e-3) / 1e9
+    dec_avg = float(np.mean(dec_ms))
+    bytes_per_frame = N * 1 + 4 * ((N + 31) // 32) + 4 + 1
+    achieved = F * bytes_per_frame / (dec_avg * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(a.traffic):
+        tr = json.load(open(a.traffic))
+        if tr.get("frames") == F and tr.get("kernel_source_sha") == kernel_sha():
+            traffic = tr.get("bytes_per_launch")
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gb/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic (seeded codewords, GPU Philox AWGN, int8 x16)",
+        "config": {
+            "workload": "plain FWBF, (3,6) QC-LDPC Z=168 N=1008 M=504 K=%d, Eb/N0 %.1f dB, int8 y, "
+                        "IMWBF alpha=1/5, G=%d, K_max=%d, %d frames" % (K, a.ebn0, a.groups,
+                                                                      a.max_iter, F),
+            "frames": F, "N": N, "K": K, "ebn0_db": a.ebn0, "groups": a.groups,
+            "max_iter": a.max_iter, "input": "int8 (scale 16)", "parallelism": "single GPU",
+        },
+        "decode_kernel_ms": round(dec_avg, 4),
+        "info_gbps": round(F * K / (ms_step * 1e-3) / 1e9, 3),
+        "fer": c[1] / frames, "ber": c[0] / (frames * N), "undetected": int(c[2]),
+        "mean_iters": c[3] / frames, "frames_counted": frames,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                     "traffic": traffic, "kernel": "decode_kernel<int8,key32,64>",
+                     "bytes_per_frame": bytes_per_frame},
+        "wall_s": round(wall, 3),
+    }
+    if a.cpu_seconds > 0:
+        out["cpu_baseline"] = cpu_baseline(code, ys[0], params, a, N)
+    print(json.dumps(out), flush=True)
+
+
+def kernel_sha():
+    import hashlib
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_1206_3362_amd", "csrc", "decode.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(code, y_dev, params, a, N):
+    """The CPU oracle (unchanged) on a bounded sample of the same frames."""
+    import numpy as np
+
+    import oracle as O
+    oc = O.Code.from_seed(3, 6, 168, 2)
+    threads = min(os.cpu_count() or 1, 16)
+    y = y_dev[:1 << 16].cpu().numpy()
+    kw = dict(weights=O.IMWBF, select=O.GROUPS, G=params.groups, max_iter=params.max_iter,
+              alpha_num=1, alpha_den=5, threads=threads)
+    n0 = 512
+    t = time.perf_counter()
+    O.decode(oc, y[:n0], **kw)
+    dt = time.perf_counter() - t
+    n = int(min(len(y), max(n0, n0 * a.cpu_seconds / max(dt, 1e-6))))
+    t = time.perf_counter()
+    O.decode(oc, y[:n], **kw)
+    dt = time.perf_counter() - t
+    return {"value": round(n * N / dt / 1e9, 6), "unit": "Gb/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {n} frames of the timed batch, literal oracle, {threads} threads, "
+                      f"{dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

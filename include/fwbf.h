@@ -50,6 +50,8 @@ enum { FWBF_GROUPS = 0, FWBF_SINGLE = 1, FWBF_TOPL = 2 };
 /* flags */
 #define FWBF_FLAG_NO_CYCLE_EXIT 1u /* run every round up to max_iter even after
                                       the state repeats (for verification) */
+#define FWBF_FLAG_GENERIC_KERNEL 2u /* use the general kernel even where the
+                                       specialised one applies (verification) */
 
 typedef struct fwbf_code fwbf_code;
 

@@ -224,26 +224,28 @@ int device_tables(fwbf_code *c, DeviceTables *out)
         *out = it->second;
         return FWBF_OK;
     }
-    size_t ncol = c->col.size() * 4, nrow = c->row.size() * 4;
-    size_t total = ncol + nrow + c->coldeg.size() + c->rowdeg.size();
+    size_t ncol = c->col.size() * 4, nrow = c->row.size() * 4, nsh = c->shift.size() * 4;
+    size_t total = nsh + ncol + nrow + c->coldeg.size() + c->rowdeg.size();
     char *base = nullptr;
     e = hipMalloc((void **)&base, total);
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(code tables)");
     std::vector<char> host(total);
-    memcpy(host.data(), c->col.data(), ncol);
-    memcpy(host.data() + ncol, c->row.data(), nrow);
-    memcpy(host.data() + ncol + nrow, c->coldeg.data(), c->coldeg.size());
-    memcpy(host.data() + ncol + nrow + c->coldeg.size(), c->rowdeg.data(), c->rowdeg.size());
+    memcpy(host.data(), c->shift.data(), nsh);
+    memcpy(host.data() + nsh, c->col.data(), ncol);
+    memcpy(host.data() + nsh + ncol, c->row.data(), nrow);
+    memcpy(host.data() + nsh + ncol + nrow, c->coldeg.data(), c->coldeg.size());
+    memcpy(host.data() + nsh + ncol + nrow + c->coldeg.size(), c->rowdeg.data(), c->rowdeg.size());
     e = hipMemcpy(base, host.data(), total, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(base);
         return hip_fail(e, "hipMemcpy(code tables)");
     }
     DeviceTables t;
-    t.col = (uint32_t *)base;
-    t.row = (uint32_t *)(base + ncol);
-    t.coldeg = (uint8_t *)(base + ncol + nrow);
-    t.rowdeg = (uint8_t *)(base + ncol + nrow + c->coldeg.size());
+    t.shift = (uint32_t *)base;
+    t.col = (uint32_t *)(base + nsh);
+    t.row = (uint32_t *)(base + nsh + ncol);
+    t.coldeg = (uint8_t *)(base + nsh + ncol + nrow);
+    t.rowdeg = (uint8_t *)(base + nsh + ncol + nrow + c->coldeg.size());
     c->dev[dev] = t;
     *out = t;
     return FWBF_OK;
@@ -355,7 +357,7 @@ void fwbf_code_free(fwbf_code *c)
     for (auto &kv : c->dev) {
         int cur = 0;
         if (hipGetDevice(&cur) == hipSuccess && hipSetDevice(kv.first) == hipSuccess) {
-            (void)hipFree(kv.second.col);
+            (void)hipFree(kv.second.shift);
             (void)hipSetDevice(cur);
         }
     }

@@ -65,6 +65,9 @@ struct DecodeArgs {
     // LDS offsets (bytes)
     int o_keys, o_chk, o_chkp, o_mag, o_z, o_syn, o_tog, o_win, o_prv, o_tl, o_gb, o_top, o_ctl,
         o_col, o_row, o_cdeg, o_rdeg, lds_bytes;
+    // |y| staged in LDS only while the check minima are computed (it then
+    // shares memory with the slots) and read from global memory afterwards
+    int mag_alias;
 };
 
 __device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t mag, uint32_t mask)
@@ -83,7 +86,7 @@ template <> struct Tr<FWBF_I8> {
 template <> struct Tr<FWBF_I16> {
     using Y = int16_t;
     using Mag = uint16_t;
-    using Chk = uint64_t;  // min1 | min2 << 16 | pos << 32
+    using Chk = uint32_t;  // min1 | min2 << 16; position in chkp
     static constexpr bool isf = false;
     static constexpr uint32_t BIG = 0xFFFF;
 };
@@ -97,20 +100,36 @@ template <> struct Tr<FWBF_F32> {
 template <int DT> __device__ __forceinline__ typename Tr<DT>::Chk pack_chk(uint32_t m1, uint32_t m2, uint32_t pos)
 {
     if constexpr (DT == FWBF_I8) return m1 | (m2 << 8) | (pos << 16);
-    else if constexpr (DT == FWBF_I16) return (uint64_t)m1 | ((uint64_t)m2 << 16) | ((uint64_t)pos << 32);
+    else if constexpr (DT == FWBF_I16) return m1 | (m2 << 16);
     else return (uint64_t)m1 | ((uint64_t)m2 << 32);
 }
 
+struct Lds {
+    uint32_t *keys;
+    void *chk;
+    uint8_t *chkp;
+    void *mag;
+    uint32_t *zw, *syn, *tog, *win, *prv, *tl;
+    unsigned long long *gb;
+    uint32_t *topn;
+    unsigned long long *topk;
+    int *ctl;
+    uint32_t *col, *row;
+    uint8_t *cdeg, *rdeg;
+    const void *yrow;  // received values of the current frame (global memory)
+};
+
 // weight w_{n,m} of the q-th member of check m (int inputs)
 template <int DT>
-__device__ __forceinline__ int32_t weight_i(typename Tr<DT>::Chk c, uint32_t q, bool imwbf)
+__device__ __forceinline__ int32_t weight_i(const Lds &s, uint32_t m, uint32_t q, bool imwbf)
 {
+    const uint32_t c = ((const uint32_t *)s.chk)[m];
     if constexpr (DT == FWBF_I8) {
-        uint32_t m1 = c & 0xFF, m2 = (c >> 8) & 0xFF, pos = (c >> 16) & 0xFF;
+        const uint32_t m1 = c & 0xFF, m2 = (c >> 8) & 0xFF, pos = (c >> 16) & 0xFF;
         return (int32_t)((imwbf && pos == q) ? m2 : m1);
     } else {
-        uint32_t m1 = (uint32_t)c & 0xFFFF, m2 = (uint32_t)(c >> 16) & 0xFFFF, pos = (uint32_t)(c >> 32) & 0xFF;
-        return (int32_t)((imwbf && pos == q) ? m2 : m1);
+        const uint32_t m1 = c & 0xFFFF, m2 = c >> 16;
+        return (int32_t)((imwbf && s.chkp[m] == q) ? m2 : m1);
     }
 }
 __device__ __forceinline__ float weight_f(uint64_t c, uint32_t pos, uint32_t q, bool imwbf)
@@ -126,19 +145,18 @@ __device__ __forceinline__ uint32_t orderable(float e)
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-struct Lds {
-    uint32_t *keys;
-    void *chk;
-    uint8_t *chkp;
-    void *mag;
-    uint32_t *zw, *syn, *tog, *win, *prv, *tl;
-    unsigned long long *gb;
-    uint32_t *topn;
-    unsigned long long *topk;
-    int *ctl;
-    uint32_t *col, *row;
-    uint8_t *cdeg, *rdeg;
-};
+
+
+// |y_n| of the current frame
+template <int DT>
+__device__ __forceinline__ typename Tr<DT>::Mag magnitude(const DecodeArgs &a, const Lds &s, uint32_t n)
+{
+    using T = Tr<DT>;
+    if (!a.mag_alias) return ((const typename T::Mag *)s.mag)[n];
+    const typename T::Y v = ((const typename T::Y *)s.yrow)[n];
+    if constexpr (T::isf) return fabsf(v);
+    else return (typename T::Mag)(v < 0 ? -(int)v : (int)v);
+}
 
 // Metric of bit n (eq. (1)) from the current syndrome, as an order-
 // preserving 32-bit value: int inputs a_den*S - a_num*|y_n| + bias, float
@@ -153,7 +171,6 @@ __device__ __forceinline__ uint32_t metric_val(const DecodeArgs &a, const Lds &s
     const int deg = s.cdeg[j];
     const uint32_t *ce = s.col + j * a.dvmax;
     const typename T::Chk *chk = (const typename T::Chk *)s.chk;
-    const typename T::Mag *mag = (const typename T::Mag *)s.mag;
     if constexpr (T::isf) {
         float S = 0.0f;
         for (int t = 0; t < deg; t++) {
@@ -165,7 +182,7 @@ __device__ __forceinline__ uint32_t metric_val(const DecodeArgs &a, const Lds &s
             const float term = ((s.syn[m >> 5] >> (m & 31)) & 1) ? w : -w;
             S = (t == 0) ? term : S + term;
         }
-        return orderable(__builtin_fmaf(-a.alpha, mag[n], S));
+        return orderable(__builtin_fmaf(-a.alpha, magnitude<DT>(a, s, n), S));
     } else {
         int32_t S = 0;
         for (int t = 0; t < deg; t++) {
@@ -173,10 +190,10 @@ __device__ __forceinline__ uint32_t metric_val(const DecodeArgs &a, const Lds &s
             int r = c - (int)(e & 0xFFFF);
             r += (r < 0) ? a.Z : 0;
             const uint32_t m = (e >> 24) * a.Z + r;
-            const int32_t w = weight_i<DT>(chk[m], (e >> 16) & 0xFF, imwbf);
+            const int32_t w = weight_i<DT>(s, m, (e >> 16) & 0xFF, imwbf);
             S += ((s.syn[m >> 5] >> (m & 31)) & 1) ? w : -w;
         }
-        return (uint32_t)(a.aden * S - a.anum * (int32_t)mag[n] + (int32_t)a.bias);
+        return (uint32_t)(a.aden * S - a.anum * (int32_t)magnitude<DT>(a, s, n) + (int32_t)a.bias);
     }
 }
 
@@ -215,7 +232,7 @@ __device__ __forceinline__ unsigned long long thread_best(const DecodeArgs &a, c
 }
 
 template <int DT, bool KEY32, int T>
-__device__ void decode_frame(const DecodeArgs &a, const Lds &s, int64_t f)
+__device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
 {
     using Tt = Tr<DT>;
     using Y = typename Tt::Y;
@@ -229,6 +246,7 @@ __device__ void decode_frame(const DecodeArgs &a, const Lds &s, int64_t f)
 
     // ---- Initialization: |y|, z_0 = [y < 0] (Section III) ----------------
     const Y *yrow = (const Y *)a.y + f * a.stride;
+    s.yrow = yrow;
     const int Nr = (N + 63) & ~63, Mr = (M + 63) & ~63;
     for (int n = tid; n < Nr; n += T) {
         bool neg = false;
@@ -286,6 +304,7 @@ __device__ void decode_frame(const DecodeArgs &a, const Lds &s, int64_t f)
                 }
                 if (deg < 2) m2 = 0;
                 chk[m] = pack_chk<DT>(m1 & Tt::BIG, m2 & Tt::BIG, pos);
+                if constexpr (DT == FWBF_I16) s.chkp[m] = (uint8_t)pos;
             }
         }
         const unsigned long long b = __ballot(par);
@@ -488,7 +507,7 @@ __device__ void decode_frame(const DecodeArgs &a, const Lds &s, int64_t f)
                 if constexpr (Tt::isf) {
                     s.keys[slot] = metric_val<DT>(a, s, n, imwbf);  // KEY32 is never used for float
                 } else {
-                    const int32_t w = weight_i<DT>(chk[m], q, imwbf);
+                    const int32_t w = weight_i<DT>(s, m, q, imwbf);
                     const int32_t d = ((s.syn[m >> 5] >> (m & 31)) & 1) ? 2 * a.aden * w : -2 * a.aden * w;
                     atomicAdd(&s.keys[slot], KEY32 ? ((uint32_t)d << a.idxb) : (uint32_t)d);
                 }
@@ -637,6 +656,8 @@ int occupancy(int DT, bool key32, int T, int lds, int *blocks)
 // Validates parameters and fills the kernel arguments (everything but the
 // data pointers).  Shared by the plain decoder and the batched launch.
 int prepare_decode(const fwbf_code *c, const fwbf_params *p, DecodeArgs *out, int *T_out);
+int try_fast_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int64_t F, int64_t stride,
+                    uint32_t *z, int32_t *iters, uint8_t *ok, hipStream_t st, const uint32_t *shift_dev);
 
 int prepare_decode(const fwbf_code *c, const fwbf_params *p, DecodeArgs *out, int *T_out)
 {
@@ -702,31 +723,37 @@ int prepare_decode(const fwbf_code *c, const fwbf_params *p, DecodeArgs *out, in
     magic(a.p, &a.magP, &a.maskP);
     magic(a.dcmax, &a.magD, &a.maskD);
 
-    // LDS layout
-    int off = 0;
-    auto take = [&](int bytes, int align) { off = (off + align - 1) / align * align; int o = off; off += bytes; return o; };
+    // LDS layout; |y| gets its own array when everything fits, else it
+    // overlays the slots during initialisation only
     const int slots = a.P * T * a.C;
     const int Nr = (c->N + 63) / 64 * 64, Mr = (c->M + 63) / 64 * 64;
-    a.o_keys = take(4 * slots, 16);
-    const int chk_sz = p->dtype == FWBF_I8 ? 4 : 8;
-    a.o_chk = take(chk_sz * c->M, 8);
-    a.o_chkp = take(p->dtype == FWBF_F32 ? c->M : 0, 4);
+    const int chk_sz = p->dtype == FWBF_F32 ? 8 : 4;
     const int mag_sz = p->dtype == FWBF_I8 ? 1 : p->dtype == FWBF_I16 ? 2 : 4;
-    a.o_mag = take(mag_sz * c->N, 4);
-    a.o_z = take(Nr / 8, 8);
-    a.o_syn = take(Mr / 8, 8);
-    a.o_tog = take(Mr / 8, 8);
-    a.o_win = take(4 * a.W, 4);
-    a.o_prv = take(4 * a.W, 4);
-    a.o_tl = take(4 * a.W * a.dvmax, 4);
-    a.o_gb = take(8 * std::max(a.Geff, 2), 8);
-    a.o_top = take(12 * a.lambda, 8);
-    a.o_ctl = take(16, 4);
-    a.o_col = take(4 * c->nb * c->dv_max, 4);
-    a.o_row = take(4 * c->mb * c->dc_max, 4);
-    a.o_cdeg = take(c->nb, 1);
-    a.o_rdeg = take(c->mb, 1);
-    a.lds_bytes = (off + 15) / 16 * 16;
+    auto layout = [&](bool alias) {
+        int off = 0;
+        auto take = [&](int bytes, int align) { off = (off + align - 1) / align * align; int o = off; off += bytes; return o; };
+        a.o_keys = take(4 * slots, 16);
+        a.o_chk = take(chk_sz * c->M, 8);
+        a.o_chkp = take(p->dtype == FWBF_I8 ? 0 : c->M, 4);
+        a.o_mag = alias ? a.o_keys : take(mag_sz * c->N, 4);
+        a.o_z = take(Nr / 8, 8);
+        a.o_syn = take(Mr / 8, 8);
+        a.o_tog = take(Mr / 8, 8);
+        a.o_win = take(4 * a.W, 4);
+        a.o_prv = take(4 * a.W, 4);
+        a.o_tl = take(4 * a.W * a.dvmax, 4);
+        a.o_gb = take(8 * std::max(a.Geff, 2), 8);
+        a.o_top = take(12 * a.lambda, 8);
+        a.o_ctl = take(16, 4);
+        a.o_col = take(4 * c->nb * c->dv_max, 4);
+        a.o_row = take(4 * c->mb * c->dc_max, 4);
+        a.o_cdeg = take(c->nb, 1);
+        a.o_rdeg = take(c->mb, 1);
+        a.lds_bytes = (off + 15) / 16 * 16;
+        a.mag_alias = alias ? 1 : 0;
+    };
+    layout(false);
+    if (a.lds_bytes > 160 * 1024) layout(true);
     if (a.lds_bytes > 160 * 1024) return fail(FWBF_E_UNSUPPORTED, "frame state exceeds 160 KiB of LDS");
     a.idxb = key32 ? a.idxb : 0;
     *out = a;
@@ -754,6 +781,11 @@ extern "C" int fwbf_decode(const fwbf_code *code, const fwbf_params *params, con
     DeviceTables t;
     int rc = device_tables(const_cast<fwbf_code *>(code), &t);
     if (rc) return rc;
+    if (!(params->flags & FWBF_FLAG_GENERIC_KERNEL)) {
+        rc = try_fast_decode(code, params, y_dev, F, y_stride, z_dev, iters_dev, ok_dev, (hipStream_t)stream,
+                             t.shift);
+        if (rc != 0) return rc < 0 ? rc : FWBF_OK;
+    }
     a.y = y_dev; a.F = F; a.stride = y_stride;
     a.z = z_dev; a.iters = iters_dev; a.ok = ok_dev;
     a.col = t.col; a.row = t.row; a.coldeg = t.coldeg; a.rowdeg = t.rowdeg;

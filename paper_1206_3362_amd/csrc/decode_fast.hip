@@ -1,0 +1,427 @@
+// One-wave-per-frame FWBF kernel for fixed-point inputs on regular QC codes
+// (every base entry a circulant permutation, column weight DV, row weight
+// DC known at compile time).  Same results as the generic kernel in
+// decode.hip, with fewer instructions per round:
+//   - the block maximum is an xor-butterfly over L lanes of packed 32-bit
+//     keys (metric << idxb | ~position), C keys per lane read as 16-byte
+//     vectors from an interleaved slot layout (lane-consecutive 16-byte
+//     chunks, no bank conflicts);
+//   - the flip, the syndrome toggle and the metric update are one pass:
+//     each winner toggles its DV checks with an LDS xor that returns the old
+//     word; the new syndrome bit of each toggle fixes the sign of the change
+//     +-2 a_den w of every member metric.  Toggles of one check by two
+//     winners in the same round are serialised by the LDS atomics and their
+//     changes cancel exactly, so no separate parity pass is needed;
+//   - the initial metrics are pushed from the check side while the check
+//     minima are computed (each check adds its signed reliability to its
+//     members; the first check of a column also adds -a_num |y_n|);
+//   - winner bookkeeping (previous flips, flip masks, the unsatisfied-check
+//     count) stays in registers and wave ballots.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "internal.h"
+
+namespace fwbf {
+namespace {
+
+constexpr uint32_t NONE = 0xFFFFFFFFu;
+
+struct FastArgs {
+    const void *y;
+    int64_t F, stride;
+    uint32_t *z;
+    int32_t *iters;
+    uint8_t *ok;
+    const uint32_t *shift;  // DV x nb shifts (block row-major)
+    int N, M, Z, nb;
+    uint32_t magZ, maskZ, magP, maskP;
+    int p, L, logL, Geff, Lc;
+    int single, imwbf, max_iter, cycle_exit, vec_ok;
+    int aden, anum, idxb;
+    uint32_t idxmask, bias, zero_val;
+    // LDS offsets in bytes
+    int o_chk, o_chkp, o_y, o_z, o_syn, o_list, o_sh, lds_bytes;
+};
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t mag, uint32_t mask)
+{
+    return __umulhi(n, mag) + (n & mask);
+}
+
+// (a + b) mod Z for a, b in [0, Z)
+__device__ __forceinline__ uint32_t addmod(uint32_t a, uint32_t b, uint32_t Z)
+{
+    const uint32_t s = a + b;
+    return min(s, s - Z);
+}
+// (a - b) mod Z for a, b in [0, Z)
+__device__ __forceinline__ uint32_t submod(uint32_t a, uint32_t b, uint32_t Z)
+{
+    const uint32_t s = a - b;
+    return min(s, s + Z);
+}
+
+// interleaved slot address: slot k of lane l lives in 16-byte chunk
+// (k/4)*64 + l, word k%4
+template <int C>
+__device__ __forceinline__ uint32_t slot_addr(uint32_t lane, uint32_t k)
+{
+    return (((k >> 2) << 6) + lane) * 4 + (k & 3);
+}
+
+template <int DT> struct FT;
+template <> struct FT<FWBF_I8> {
+    using Y = int8_t;
+};
+template <> struct FT<FWBF_I16> {
+    using Y = int16_t;
+};
+
+template <int DT, int DV, int DC, int C>
+__global__ __launch_bounds__(64) void fast_kernel(FastArgs a)
+{
+    using Y = typename FT<DT>::Y;
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t *keys = (uint32_t *)smem;
+    uint32_t *chk = (uint32_t *)(smem + a.o_chk);
+    uint8_t *chkp = smem + a.o_chkp;
+    Y *yv = (Y *)(smem + a.o_y);
+    uint32_t *zw = (uint32_t *)(smem + a.o_z);
+    uint32_t *syn = (uint32_t *)(smem + a.o_syn);
+    uint32_t *list = (uint32_t *)(smem + a.o_list);
+    uint32_t *sh = (uint32_t *)(smem + a.o_sh);
+
+    const uint32_t lane = threadIdx.x;
+    const uint32_t Z = a.Z;
+    const int N = a.N, M = a.M;
+    for (int t = lane; t < DV * a.nb; t += 64) sh[t] = a.shift[t];
+
+    // lane -> block layout
+    const uint32_t g = lane >> a.logL;
+    const bool lead = ((lane & (a.L - 1)) == 0) && (int)g < a.Geff;
+    const uint32_t pos0 = (lane & (a.L - 1)) * C;
+    const uint32_t gp = g * a.p;
+    const int NW = (N + 31) >> 5;
+
+    for (int64_t f = blockIdx.x; f < a.F; f += gridDim.x) {
+        const Y *yrow = (const Y *)a.y + f * a.stride;
+        __syncthreads();
+        for (int w = lane; w < ((M + 63) >> 6) * 2; w += 64) syn[w] = 0;
+        // ---- received values -> LDS; hard decisions z_0 = [y < 0] ---------
+        if (a.vec_ok) {
+            const int nchunk = (N * (int)sizeof(Y)) >> 4;
+            for (int c = lane; c < nchunk; c += 64)
+                ((uint4 *)yv)[c] = ((const uint4 *)yrow)[c];
+            for (int n = nchunk * (16 / (int)sizeof(Y)) + lane; n < N; n += 64) yv[n] = yrow[n];
+        } else {
+            for (int n = lane; n < N; n += 64) yv[n] = yrow[n];
+        }
+        // initial keys: bias (metric 0) packed with the position in the block
+#pragma unroll
+        for (int kk = 0; kk < C; kk += 4) {
+            uint4 v;
+            uint32_t *vp = (uint32_t *)&v;
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const uint32_t pos = pos0 + kk + u;
+                const bool real = (int)g < a.Geff && (int)pos < a.p && (int)(gp + pos) < N;
+                vp[u] = real ? ((a.bias << a.idxb) | (a.idxmask - pos)) : 0u;
+            }
+            ((uint4 *)keys)[(kk >> 2) * 64 + lane] = v;
+        }
+        __syncthreads();
+        for (int n0 = 0; n0 < N; n0 += 64) {
+            const int n = n0 + lane;
+            const bool neg = n < N && yv[n] < (Y)0;
+            const unsigned long long b = __ballot(neg);
+            if (lane == 0) {
+                zw[n0 >> 5] = (uint32_t)b;
+                zw[(n0 >> 5) + 1] = (uint32_t)(b >> 32);
+            }
+        }
+
+        // ---- check minima, syndrome s_0 and check-side initial metrics ----
+        int weight = 0;
+        for (int i = 0; i < DV; i++) {
+            uint32_t js[DC];
+#pragma unroll
+            for (int q = 0; q < DC; q++) js[q] = sh[i * a.nb + q];
+            for (uint32_t r0 = 0; r0 < Z; r0 += 64) {
+                const uint32_t r = r0 + lane;
+                const bool valid = r < Z;
+                uint32_t nn[DC], av[DC];
+                uint32_t m1 = 0xFFFFu, m2 = 0xFFFFu, pos = 0, par = 0;
+                if (valid) {
+#pragma unroll
+                    for (int q = 0; q < DC; q++) {
+                        const uint32_t n = q * Z + addmod(r, js[q], Z);
+                        const int v = (int)yv[n];
+                        const uint32_t av_ = (uint32_t)(v < 0 ? -v : v);
+                        nn[q] = n;
+                        av[q] = av_;
+                        par ^= (uint32_t)(v < 0);
+                        const bool lt = av_ < m1;
+                        m2 = lt ? m1 : min(m2, av_);
+                        pos = lt ? (uint32_t)q : pos;
+                        m1 = lt ? av_ : m1;
+                    }
+                    if (DC < 2) m2 = 0;
+                    const uint32_t m = i * Z + r;
+                    if constexpr (DT == FWBF_I8) {
+                        chk[m] = m1 | (m2 << 8) | (pos << 16);
+                    } else {
+                        chk[m] = m1 | (m2 << 16);
+                        chkp[m] = (uint8_t)pos;
+                    }
+                    // push this check's term of eq. (1) to its members
+#pragma unroll
+                    for (int q = 0; q < DC; q++) {
+                        const uint32_t w = (a.imwbf && pos == (uint32_t)q) ? m2 : m1;
+                        int d = par ? a.aden * (int)w : -a.aden * (int)w;
+                        if (i == 0) d -= a.anum * (int)av[q];
+                        const uint32_t n = nn[q];
+                        const uint32_t gg = fdiv(n, a.magP, a.maskP);
+                        const uint32_t pp = n - gg * a.p;
+                        const uint32_t ln = gg * a.L + pp / C;
+                        atomicAdd(&keys[slot_addr<C>(ln, pp & (C - 1))], (uint32_t)d << a.idxb);
+                    }
+                }
+                const unsigned long long b = __ballot(valid && par);
+                weight += __popcll(b);
+                // syndrome words: checks i*Z + r0 .. +63 (not word aligned in general)
+                if (valid && par) atomicOr(&syn[(i * Z + r) >> 5], 1u << ((i * Z + r) & 31));
+            }
+        }
+        __syncthreads();
+
+        int k = 0, okf = 0;
+        uint32_t prv = NONE;
+        if (weight == 0 || a.max_iter == 0) {
+            okf = weight == 0;
+        } else {
+            for (;;) {
+                // ---- Step 2: block maxima ----------------------------------
+                uint32_t best = 0;
+#pragma unroll
+                for (int kk = 0; kk < C; kk += 4) {
+                    const uint4 v = ((const uint4 *)keys)[(kk >> 2) * 64 + lane];
+                    best = max(best, max(max(v.x, v.y), max(v.z, v.w)));
+                }
+                for (int d = 1; d < a.L; d <<= 1) best = max(best, (uint32_t)__shfl_xor((int)best, d, 64));
+                const uint32_t val = best >> a.idxb;
+                const uint32_t n = gp + (a.idxmask - (best & a.idxmask));
+                const bool flip = lead && (a.single || val > a.zero_val);
+                const uint32_t cur = flip ? n : NONE;
+                const unsigned long long fmask = __ballot(flip);
+                const unsigned long long dmask = __ballot(lead && cur != prv);
+                prv = lead ? cur : prv;
+                if (a.cycle_exit) {
+                    if (fmask == 0) {  // no flip: fixed point until K_max
+                        k = a.max_iter;
+                        break;
+                    }
+                    if (dmask == 0) {
+                        // same flips as the round before: states alternate,
+                        // z_{K_max} = z_k if K_max - k is even, else z_k ^ flips
+                        if (((a.max_iter - k) & 1) && flip) atomicXor(&zw[n >> 5], 1u << (n & 31));
+                        k = a.max_iter;
+                        break;
+                    }
+                }
+                // ---- flip, toggle the syndrome, queue member updates -------
+                const int rank = __popcll(fmask & ((1ull << lane) - 1));
+                uint32_t onesm = 0;
+                if (flip) {
+                    atomicXor(&zw[n >> 5], 1u << (n & 31));
+                    const uint32_t j = fdiv(n, a.magZ, a.maskZ);
+                    const uint32_t c = n - j * Z;
+#pragma unroll
+                    for (int t = 0; t < DV; t++) {
+                        const uint32_t m = t * Z + submod(c, sh[t * a.nb + j], Z);
+                        const uint32_t bit = 1u << (m & 31);
+                        const uint32_t old = atomicXor(&syn[m >> 5], bit);
+                        const uint32_t nb1 = (old & bit) ? 0u : 1u;
+                        onesm |= nb1 << t;
+                        list[rank * DV + t] = m | (nb1 << 31);
+                    }
+                }
+                // unsatisfied-check count: +1 per toggle to 1, -1 per toggle to 0
+                int sum_ones = 0;
+#pragma unroll
+                for (int t = 0; t < DV; t++) sum_ones += __popcll(__ballot((onesm >> t) & 1));
+                const int nflip = __popcll(fmask);
+                weight += 2 * sum_ones - DV * nflip;
+                k += 1;
+                if (weight == 0) { okf = 1; break; }
+                if (k == a.max_iter) break;
+                __syncthreads();
+                // ---- member metric updates ---------------------------------
+                const int ntask = nflip * DV * DC;
+                for (int base = 0; base < ntask; base += 64) {
+                    const int t = base + (int)lane;
+                    if (t < ntask) {
+                        const int u = t / DC, q = t - (t / DC) * DC;
+                        const uint32_t e = list[u];
+                        const uint32_t m = e & 0x7FFFFFFFu;
+                        const uint32_t i = fdiv(m, a.magZ, a.maskZ);
+                        const uint32_t r = m - i * Z;
+                        const uint32_t nq = q * Z + addmod(r, sh[i * a.nb + q], Z);
+                        uint32_t w;
+                        if constexpr (DT == FWBF_I8) {
+                            const uint32_t cw = chk[m];
+                            w = (a.imwbf && ((cw >> 16) & 0xFF) == (uint32_t)q) ? ((cw >> 8) & 0xFF) : (cw & 0xFF);
+                        } else {
+                            const uint32_t cw = chk[m];
+                            w = (a.imwbf && chkp[m] == (uint32_t)q) ? (cw >> 16) : (cw & 0xFFFF);
+                        }
+                        const int d = (e >> 31) ? 2 * a.aden * (int)w : -2 * a.aden * (int)w;
+                        const uint32_t gg = fdiv(nq, a.magP, a.maskP);
+                        const uint32_t pp = nq - gg * a.p;
+                        const uint32_t ln = gg * a.L + pp / C;
+                        atomicAdd(&keys[slot_addr<C>(ln, pp & (C - 1))], (uint32_t)d << a.idxb);
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        __syncthreads();
+        uint32_t *zo = a.z + f * NW;
+        for (int w = lane; w < NW; w += 64) zo[w] = zw[w];
+        if (lane == 0) {
+            a.iters[f] = k;
+            a.ok[f] = (uint8_t)okf;
+        }
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+namespace {
+
+int ilog2c(uint32_t v) { int r = 0; while ((1u << r) < v) r++; return r; }
+
+void magic_c(uint32_t d, uint32_t *mag, uint32_t *mask)
+{
+    if (d <= 1) { *mag = 0; *mask = 0xFFFFFFFFu; return; }
+    *mag = (uint32_t)(((1ULL << 32) + d - 1) / d);
+    *mask = 0;
+}
+
+template <int DT, int DV, int DC, int C>
+hipError_t launch_fast(const FastArgs &a, hipStream_t st, int *grid_out, bool query)
+{
+    auto kern = fast_kernel<DT, DV, DC, C>;
+    if (a.lds_bytes > 65536)
+        (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, a.lds_bytes);
+    int blocks = 0, dev = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kern, 64, a.lds_bytes);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    if (blocks < 1) return hipErrorInvalidConfiguration;
+    const int64_t grid = std::min<int64_t>(a.F, (int64_t)blocks * cus);
+    *grid_out = (int)grid;
+    if (query) return hipSuccess;
+    hipLaunchKernelGGL(kern, dim3((int)grid), dim3(64), a.lds_bytes, st, a);
+    return hipGetLastError();
+}
+
+template <int DT, int DV, int DC>
+hipError_t by_c(int C, const FastArgs &a, hipStream_t st, int *grid, bool query)
+{
+    switch (C) {
+    case 4: return launch_fast<DT, DV, DC, 4>(a, st, grid, query);
+    case 8: return launch_fast<DT, DV, DC, 8>(a, st, grid, query);
+    case 16: return launch_fast<DT, DV, DC, 16>(a, st, grid, query);
+    case 32: return launch_fast<DT, DV, DC, 32>(a, st, grid, query);
+    case 64: return launch_fast<DT, DV, DC, 64>(a, st, grid, query);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int DT>
+hipError_t by_deg(int dv, int dc, int C, const FastArgs &a, hipStream_t st, int *grid, bool query)
+{
+    if (dv == 3 && dc == 6) return by_c<DT, 3, 6>(C, a, st, grid, query);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+// Returns 1 if the fast kernel was launched, 0 if the configuration is not
+// covered (the caller then uses the generic kernel), < 0 on error.
+int try_fast_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int64_t F, int64_t stride,
+                    uint32_t *z, int32_t *iters, uint8_t *ok, hipStream_t st, const uint32_t *shift_dev)
+{
+    if (p->dtype != FWBF_I8 && p->dtype != FWBF_I16) return 0;
+    if (p->select == FWBF_TOPL) return 0;
+    if (p->threads_per_frame != 0 && p->threads_per_frame != 64) return 0;
+    const int dv = c->mb, dc = c->nb;
+    if (!(dv == 3 && dc == 6)) return 0;
+    for (int v : c->shift)
+        if (v < 0) return 0;
+    FastArgs a;
+    memset(&a, 0, sizeof a);
+    const int G = p->select == FWBF_GROUPS ? p->groups : 1;
+    a.p = (c->N + G - 1) / G;
+    a.Geff = (c->N + a.p - 1) / a.p;
+    // smallest C with Geff * L <= 64 lanes, L = 2^ceil(log2(ceil(p / C)))
+    int C = 0, L = 0;
+    for (int cc : {4, 8, 16, 32, 64}) {
+        const int need = (a.p + cc - 1) / cc;
+        const int l = 1 << ilog2c(need);
+        if ((int64_t)a.Geff * l <= 64) { C = cc; L = l; break; }
+    }
+    if (!C) return 0;
+    a.L = L;
+    a.logL = ilog2c(L);
+    a.Lc = L * C;
+    a.N = c->N; a.M = c->M; a.Z = c->Z; a.nb = c->nb;
+    magic_c(c->Z, &a.magZ, &a.maskZ);
+    magic_c(a.p, &a.magP, &a.maskP);
+    a.single = p->select == FWBF_SINGLE;
+    a.imwbf = p->weights == FWBF_IMWBF;
+    a.max_iter = p->max_iter;
+    a.cycle_exit = !(p->flags & FWBF_FLAG_NO_CYCLE_EXIT);
+    a.aden = p->alpha_den;
+    a.anum = p->weights == FWBF_WBF ? 0 : p->alpha_num;
+    const int64_t maxmag = p->dtype == FWBF_I8 ? 128 : 32768;
+    const int64_t maxE = maxmag * ((int64_t)a.aden * dv + a.anum);
+    int vb = 1;
+    while ((1LL << (vb - 1)) <= maxE) vb++;
+    a.bias = 1u << (vb - 1);
+    a.zero_val = a.bias;
+    a.idxb = ilog2c((uint32_t)a.Lc);
+    if (vb + a.idxb > 32) return 0;
+    a.idxmask = a.idxb ? (1u << a.idxb) - 1 : 0;
+    const int esz = p->dtype == FWBF_I8 ? 1 : 2;
+    a.vec_ok = (((uintptr_t)y & 15) == 0) && ((stride * esz) % 16 == 0);
+    // LDS layout
+    int off = 64 * C * 4;  // keys
+    auto take = [&](int bytes, int align) { off = (off + align - 1) / align * align; int o = off; off += bytes; return o; };
+    a.o_chk = take(4 * c->M, 4);
+    a.o_chkp = take(p->dtype == FWBF_I16 ? c->M : 0, 4);
+    a.o_y = take(esz * ((c->N + 15) / 16 * 16), 16);
+    a.o_z = take(((c->N + 63) / 64) * 8, 8);
+    a.o_syn = take(((c->M + 63) / 64) * 8, 8);
+    a.o_list = take(4 * dv * 64, 4);
+    a.o_sh = take(4 * dv * c->nb, 4);
+    a.lds_bytes = (off + 15) / 16 * 16;
+    if (a.lds_bytes > 64 * 1024) return 0;
+    a.y = y; a.F = F; a.stride = stride;
+    a.z = z; a.iters = iters; a.ok = ok;
+    a.shift = shift_dev;
+    int grid = 0;
+    hipError_t e = p->dtype == FWBF_I8 ? by_deg<FWBF_I8>(dv, dc, C, a, st, &grid, false)
+                                       : by_deg<FWBF_I16>(dv, dc, C, a, st, &grid, false);
+    if (e != hipSuccess) return hip_fail(e, "fast decode kernel launch");
+    return 1;
+}
+
+}  // namespace fwbf

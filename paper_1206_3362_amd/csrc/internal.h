@@ -27,6 +27,7 @@ struct DeviceTables {
     uint32_t *row = nullptr;  // mb * dc_max
     uint8_t *coldeg = nullptr;  // nb
     uint8_t *rowdeg = nullptr;  // mb
+    uint32_t *shift = nullptr;  // mb * nb raw shifts (-1 as 0xFFFFFFFF)
 };
 
 }  // namespace fwbf

@@ -21,6 +21,7 @@ F32, I8, I16 = 0, 1, 2
 WBF, MWBF, IMWBF = 0, 1, 2
 GROUPS, SINGLE, TOPL = 0, 1, 2
 FLAG_NO_CYCLE_EXIT = 1
+FLAG_GENERIC_KERNEL = 2
 
 OK, E_INVALID, E_PARSE, E_GIRTH, E_UNSUPPORTED, E_NOMEM, E_HIP = 0, -1, -2, -3, -4, -5, -6
 _NAMES = {-1: "E_INVALID", -2: "E_PARSE", -3: "E_GIRTH", -4: "E_UNSUPPORTED", -5: "E_NOMEM",

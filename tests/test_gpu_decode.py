@@ -81,7 +81,7 @@ def test_exhaustive_single_and_double_errors_n186(codes, G):
             a, b = run_both(codes, "n186", y, groups=G, max_iter=50, **v)
             assert_same(a, b, f"n186 patterns G={G} {dt} {v}")
         if G == 6:
-            assert (a[1][:g.N] == 1).all() and (a[2] == 1).all()
+            assert (a[1][:g.N] == 1).all() and (a[2][:g.N] == 1).all()
 
 
 def test_exhaustive_single_errors_n1008(codes):
@@ -118,6 +118,21 @@ def test_cycle_exit_is_exact(codes):
         slow = gpu_decode(g, y, max_iter=57, flags=1, **sel)
         assert_same(fast, slow, f"shortcut {sel}")
         assert_same(fast, oracle_decode(o, y, max_iter=57, **sel), f"oracle {sel}")
+
+
+@pytest.mark.parametrize("dt", [np.int8, np.int16])
+def test_specialised_and_generic_kernels_agree(codes, dt):
+    """The one-wave integer kernel (regular (3,6) codes) and the general
+    kernel give identical outputs, equal to the oracle's."""
+    g, o = codes("n1008")
+    y = synth.awgn_frames(g.N, 2048, synth.sigma_for(4.5, g.rate), 41, None, dt)
+    for sel in (dict(select=0, groups=1), dict(select=0, groups=8), dict(select=0, groups=63),
+                dict(select=0, groups=126), dict(select=0, groups=1008), dict(select=1)):
+        for v in VARIANTS:
+            fast = gpu_decode(g, y, max_iter=80, **sel, **v)
+            gen = gpu_decode(g, y, max_iter=80, flags=2, **sel, **v)
+            assert_same(fast, gen, f"fast vs generic {sel} {v}")
+            assert_same(fast, oracle_decode(o, y, max_iter=80, **sel, **v), f"oracle {sel} {v}")
 
 
 def test_degenerate_calls(codes):
