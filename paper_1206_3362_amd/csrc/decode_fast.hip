@@ -64,12 +64,38 @@ __device__ __forceinline__ uint32_t submod(uint32_t a, uint32_t b, uint32_t Z)
     return min(s, s + Z);
 }
 
-// interleaved slot address: slot k of lane l lives in 16-byte chunk
-// (k/4)*64 + l, word k%4
-template <int C>
+// Slot layout: the kk-th 16-byte chunk of lane l sits at chunk index
+// kk*64 + (l ^ 4*(kk mod 16)).  For a fixed kk the lanes read 64 distinct
+// consecutive chunks (conflict-free vector reads in the block maximum), and
+// 64 consecutive bits (4 lanes x 16 slots) land in 64 distinct banks
+// (conflict-free atomics when a check pushes to its members).
+__device__ __forceinline__ uint32_t chunk_of(uint32_t lane, uint32_t kk)
+{
+    return (kk << 6) + (lane ^ ((kk & 15) << 2));
+}
 __device__ __forceinline__ uint32_t slot_addr(uint32_t lane, uint32_t k)
 {
-    return (((k >> 2) << 6) + lane) * 4 + (k & 3);
+    return chunk_of(lane, k >> 2) * 4 + (k & 3);
+}
+
+// row-local data movement (DPP): xor 1, xor 2, mirror within 8, mirror within 16
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+// maximum over aligned groups of L lanes (L a power of two <= 64); every
+// lane of a group ends with the group maximum
+__device__ __forceinline__ uint32_t group_max(uint32_t v, int L)
+{
+    if (L > 1) v = max(v, dpp<0xB1>(v));   // quad_perm [1,0,3,2]
+    if (L > 2) v = max(v, dpp<0x4E>(v));   // quad_perm [2,3,0,1]
+    if (L > 4) v = max(v, dpp<0x141>(v));  // row_half_mirror
+    if (L > 8) v = max(v, dpp<0x140>(v));  // row_mirror
+    if (L > 16) v = max(v, (uint32_t)__shfl_xor((int)v, 16, 64));
+    if (L > 32) v = max(v, (uint32_t)__shfl_xor((int)v, 32, 64));
+    return v;
 }
 
 template <int DT> struct FT;
@@ -110,15 +136,30 @@ __global__ __launch_bounds__(64) void fast_kernel(FastArgs a)
         const Y *yrow = (const Y *)a.y + f * a.stride;
         __syncthreads();
         for (int w = lane; w < ((M + 63) >> 6) * 2; w += 64) syn[w] = 0;
-        // ---- received values -> LDS; hard decisions z_0 = [y < 0] ---------
-        if (a.vec_ok) {
-            const int nchunk = (N * (int)sizeof(Y)) >> 4;
-            for (int c = lane; c < nchunk; c += 64)
-                ((uint4 *)yv)[c] = ((const uint4 *)yrow)[c];
-            for (int n = nchunk * (16 / (int)sizeof(Y)) + lane; n < N; n += 64) yv[n] = yrow[n];
-        } else {
-            for (int n = lane; n < N; n += 64) yv[n] = yrow[n];
+        for (int w = lane; w < ((N + 63) >> 6) * 2; w += 64) zw[w] = 0;
+        // ---- received values -> LDS ---------------------------------------
+        constexpr int E = 16 / (int)sizeof(Y);  // values per 16-byte chunk
+        const int nchunk = a.vec_ok ? min(N / E, 128) : 0;
+        uint32_t zmask[2] = {0, 0};
+        for (int it = 0; it < 2; it++) {
+            const int cidx = lane + 64 * it;
+            if (cidx < nchunk) {
+                const uint4 v = ((const uint4 *)yrow)[cidx];
+                ((uint4 *)yv)[cidx] = v;
+                // sign bits of the chunk (z_0 = [y < 0]), E bits
+                uint32_t msk = 0;
+                const uint32_t xs[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    uint32_t nib;
+                    if constexpr (sizeof(Y) == 1) nib = ((((xs[u] >> 7) & 0x01010101u) * 0x01020408u) >> 24) & 0xFu;
+                    else nib = ((xs[u] >> 15) & 1u) | ((xs[u] >> 30) & 2u);
+                    msk |= nib << (u * (sizeof(Y) == 1 ? 4 : 2));
+                }
+                zmask[it] = msk;
+            }
         }
+        for (int n = nchunk * E + lane; n < N; n += 64) yv[n] = yrow[n];
         // initial keys: bias (metric 0) packed with the position in the block
 #pragma unroll
         for (int kk = 0; kk < C; kk += 4) {
@@ -130,17 +171,21 @@ __global__ __launch_bounds__(64) void fast_kernel(FastArgs a)
                 const bool real = (int)g < a.Geff && (int)pos < a.p && (int)(gp + pos) < N;
                 vp[u] = real ? ((a.bias << a.idxb) | (a.idxmask - pos)) : 0u;
             }
-            ((uint4 *)keys)[(kk >> 2) * 64 + lane] = v;
+            ((uint4 *)keys)[chunk_of(lane, kk >> 2)] = v;
         }
         __syncthreads();
-        for (int n0 = 0; n0 < N; n0 += 64) {
+        // hard decisions z_0 = [y < 0] (Section III, Initialization)
+        for (int it = 0; it < 2; it++) {
+            const int cidx = lane + 64 * it;
+            if (cidx < nchunk && zmask[it]) {
+                const int b0 = cidx * E;
+                atomicOr(&zw[b0 >> 5], zmask[it] << (b0 & 31));
+            }
+        }
+        for (int n0 = nchunk * E; n0 < N; n0 += 64) {
             const int n = n0 + lane;
             const bool neg = n < N && yv[n] < (Y)0;
-            const unsigned long long b = __ballot(neg);
-            if (lane == 0) {
-                zw[n0 >> 5] = (uint32_t)b;
-                zw[(n0 >> 5) + 1] = (uint32_t)(b >> 32);
-            }
+            if (neg) atomicOr(&zw[n >> 5], 1u << (n & 31));
         }
 
         // ---- check minima, syndrome s_0 and check-side initial metrics ----
@@ -186,7 +231,7 @@ __global__ __launch_bounds__(64) void fast_kernel(FastArgs a)
                         const uint32_t gg = fdiv(n, a.magP, a.maskP);
                         const uint32_t pp = n - gg * a.p;
                         const uint32_t ln = gg * a.L + pp / C;
-                        atomicAdd(&keys[slot_addr<C>(ln, pp & (C - 1))], (uint32_t)d << a.idxb);
+                        atomicAdd(&keys[slot_addr(ln, pp & (C - 1))], (uint32_t)d << a.idxb);
                     }
                 }
                 const unsigned long long b = __ballot(valid && par);
@@ -207,10 +252,10 @@ __global__ __launch_bounds__(64) void fast_kernel(FastArgs a)
                 uint32_t best = 0;
 #pragma unroll
                 for (int kk = 0; kk < C; kk += 4) {
-                    const uint4 v = ((const uint4 *)keys)[(kk >> 2) * 64 + lane];
+                    const uint4 v = ((const uint4 *)keys)[chunk_of(lane, kk >> 2)];
                     best = max(best, max(max(v.x, v.y), max(v.z, v.w)));
                 }
-                for (int d = 1; d < a.L; d <<= 1) best = max(best, (uint32_t)__shfl_xor((int)best, d, 64));
+                best = group_max(best, a.L);
                 const uint32_t val = best >> a.idxb;
                 const uint32_t n = gp + (a.idxmask - (best & a.idxmask));
                 const bool flip = lead && (a.single || val > a.zero_val);
@@ -238,14 +283,20 @@ __global__ __launch_bounds__(64) void fast_kernel(FastArgs a)
                     atomicXor(&zw[n >> 5], 1u << (n & 31));
                     const uint32_t j = fdiv(n, a.magZ, a.maskZ);
                     const uint32_t c = n - j * Z;
+                    uint32_t rr[DV], old[DV];
+#pragma unroll
+                    for (int t = 0; t < DV; t++) rr[t] = submod(c, sh[t * a.nb + j], Z);
 #pragma unroll
                     for (int t = 0; t < DV; t++) {
-                        const uint32_t m = t * Z + submod(c, sh[t * a.nb + j], Z);
-                        const uint32_t bit = 1u << (m & 31);
-                        const uint32_t old = atomicXor(&syn[m >> 5], bit);
-                        const uint32_t nb1 = (old & bit) ? 0u : 1u;
+                        const uint32_t m = t * Z + rr[t];
+                        old[t] = atomicXor(&syn[m >> 5], 1u << (m & 31));
+                    }
+#pragma unroll
+                    for (int t = 0; t < DV; t++) {
+                        const uint32_t m = t * Z + rr[t];
+                        const uint32_t nb1 = ((old[t] >> (m & 31)) & 1u) ^ 1u;
                         onesm |= nb1 << t;
-                        list[rank * DV + t] = m | (nb1 << 31);
+                        list[rank * DV + t] = rr[t] | ((uint32_t)t << 16) | (nb1 << 31);
                     }
                 }
                 // unsatisfied-check count: +1 per toggle to 1, -1 per toggle to 0
@@ -265,9 +316,8 @@ __global__ __launch_bounds__(64) void fast_kernel(FastArgs a)
                     if (t < ntask) {
                         const int u = t / DC, q = t - (t / DC) * DC;
                         const uint32_t e = list[u];
-                        const uint32_t m = e & 0x7FFFFFFFu;
-                        const uint32_t i = fdiv(m, a.magZ, a.maskZ);
-                        const uint32_t r = m - i * Z;
+                        const uint32_t r = e & 0xFFFFu, i = (e >> 16) & 0x7FFFu;
+                        const uint32_t m = i * Z + r;
                         const uint32_t nq = q * Z + addmod(r, sh[i * a.nb + q], Z);
                         uint32_t w;
                         if constexpr (DT == FWBF_I8) {
@@ -281,7 +331,7 @@ __global__ __launch_bounds__(64) void fast_kernel(FastArgs a)
                         const uint32_t gg = fdiv(nq, a.magP, a.maskP);
                         const uint32_t pp = nq - gg * a.p;
                         const uint32_t ln = gg * a.L + pp / C;
-                        atomicAdd(&keys[slot_addr<C>(ln, pp & (C - 1))], (uint32_t)d << a.idxb);
+                        atomicAdd(&keys[slot_addr(ln, pp & (C - 1))], (uint32_t)d << a.idxb);
                     }
                 }
                 __syncthreads();
