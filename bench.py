@@ -39,11 +39,27 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")
     ap.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "traffic_decode_n1008_i8_4db.json"))
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy three times (scales the HBM counters)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": n, "launches": 3}))
 
 
 def main():
     a = parse()
+    if a.copy_calibration:
+        copy_calibration()
+        return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the FWBF decoder has no multi-GPU path "
               "(frames are independent; see the design notes for how it would shard).",
@@ -140,7 +156,7 @@ def main():
         "mean_iters": c[3] / frames, "frames_counted": frames,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": traffic, "kernel": "decode_kernel<int8,key32,64>",
+                     "traffic": traffic, "kernel": "fast_kernel<int8,3,6,16>",
                      "bytes_per_frame": bytes_per_frame},
         "wall_s": round(wall, 3),
     }
@@ -152,8 +168,9 @@ def main():
 def kernel_sha():
     import hashlib
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1206_3362_amd", "csrc", "decode.hip"), "rb") as f:
-        h.update(f.read())
+    for name in ("decode.hip", "decode_fast.hip", "frames.h"):
+        with open(os.path.join(ROOT, "paper_1206_3362_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -164,7 +181,7 @@ def cpu_baseline(code, y_dev, params, a, N):
     import oracle as O
     oc = O.Code.from_seed(3, 6, 168, 2)
     threads = min(os.cpu_count() or 1, 16)
-    y = y_dev[:1 << 16].cpu().numpy()
+    y = y_dev[:1 << 18].cpu().numpy()
     kw = dict(weights=O.IMWBF, select=O.GROUPS, G=params.groups, max_iter=params.max_iter,
               alpha_num=1, alpha_den=5, threads=threads)
     n0 = 512

@@ -35,6 +35,7 @@
 #include <algorithm>
 #include <cstring>
 
+#include "frames.h"
 #include "internal.h"
 
 namespace fwbf {
@@ -556,7 +557,8 @@ __global__ __launch_bounds__(T) void decode_kernel(DecodeArgs a)
     for (int t = threadIdx.x; t < a.nb; t += T) s.cdeg[t] = a.coldeg[t];
     for (int t = threadIdx.x; t < a.mb; t += T) s.rdeg[t] = a.rowdeg[t];
     __syncthreads();
-    for (int64_t f = blockIdx.x; f < a.F; f += gridDim.x) decode_frame<DT, KEY32, T>(a, s, f);
+    const FrameRange fr = xcd_frames(a.F);
+    for (int64_t f = fr.first; f < fr.end; f += fr.step) decode_frame<DT, KEY32, T>(a, s, f);
 }
 
 // ---------------------------------------------------------------------------

@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <cstring>
 
+#include "frames.h"
 #include "internal.h"
 
 namespace fwbf {
@@ -132,7 +133,8 @@ __global__ __launch_bounds__(64) void fast_kernel(FastArgs a)
     const uint32_t gp = g * a.p;
     const int NW = (N + 31) >> 5;
 
-    for (int64_t f = blockIdx.x; f < a.F; f += gridDim.x) {
+    const FrameRange fr = xcd_frames(a.F);
+    for (int64_t f = fr.first; f < fr.end; f += fr.step) {
         const Y *yrow = (const Y *)a.y + f * a.stride;
         __syncthreads();
         for (int w = lane; w < ((M + 63) >> 6) * 2; w += 64) syn[w] = 0;

@@ -1,0 +1,31 @@
+// Frame scheduling of the persistent decode grids (device code only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fwbf {
+
+// Workgroups are dispatched to the 8 XCDs of the device round-robin, so
+// workgroup b runs on XCD b % 8.  XCD x owns the contiguous frame range
+// [x*Fx, (x+1)*Fx) and its workgroups stride through it: neighbouring frames,
+// which share cache lines whenever a frame row is not a multiple of the line
+// size, are then read (and their outputs written) through one L2 instead of
+// two.  Falls back to a plain grid stride when the grid is not a multiple of 8.
+struct FrameRange {
+    int64_t first, end, step;
+};
+
+__device__ __forceinline__ FrameRange xcd_frames(int64_t F)
+{
+    constexpr int NX = 8;
+    const int64_t G = gridDim.x, b = blockIdx.x;
+    if (G % NX != 0 || F < G) return FrameRange{b, F, G};
+    const int64_t x = b % NX, per = G / NX;
+    const int64_t Fx = (F + NX - 1) / NX;
+    const int64_t end = (x + 1) * Fx < F ? (x + 1) * Fx : F;
+    return FrameRange{x * Fx + b / NX, end, per};
+}
+
+}  // namespace fwbf
