@@ -160,6 +160,73 @@ int fwbf_count(int N, int64_t F, int64_t f0, const uint32_t *z_dev, const uint32
                int64_t pool_n, const int32_t *iters_dev, const uint8_t *ok_dev, int max_iter,
                int64_t *counters_dev, void *stream);
 
+/* ---- learned flip scorer (extension; keeps the per-block choice) -------- */
+
+/* The learned pass: in round t (t < rounds) the metric
+ * E_t = fmaf(-alpha_t, |y_n|, beta_t S_n), with S_n the check sum of eq. (1),
+ * proposes the `topk` best bits of each of `groups` blocks (Section III);
+ * a ReLU network 4 -> 32 -> 32 -> 1 (bfloat16 weights, MFMA, single-precision
+ * sums) scores each proposal from [|y|/scale, E_t/scale, u_n/dv, t/rounds]
+ * (u_n: unsatisfied checks of bit n) and, in each block, the best-scoring
+ * proposal is flipped if its score is positive.  The pass stops on a zero
+ * syndrome, on a round without flips, on a round repeating the previous
+ * round's flips, or after `rounds` rounds.  Scorer parameters: float32
+ * vector of fwbf_scorer_size(rounds) = 1249 + 2*rounds values:
+ * W1[32][4], b1[32], W2[32][32], b2[32], W3[32], b3, alpha[rounds],
+ * beta[rounds]. */
+typedef struct {
+    int32_t rounds; /* 1..64 */
+    int32_t groups; /* blocks of the learned pass; groups * topk <= 32 */
+    int32_t topk;   /* proposals per block: 1, 2 or 4 */
+    float scale;    /* fixed-point scale of y (16 for the int8 inputs) */
+} fwbf_learned_params;
+
+/* One scored proposal, emitted by fwbf_decode_learned for training:
+ * records[frame][round][slot], slot = block * topk + rank (32 slots). */
+typedef struct {
+    int16_t S;      /* check sum S_n of eq. (1) when scored */
+    uint8_t a;      /* |y_n| */
+    uint8_t u;      /* unsatisfied checks of bit n */
+    uint8_t label;  /* z_n xor c_n when scored: 1 if the bit is wrong */
+    uint8_t valid;  /* 0 for empty slots and rounds not run */
+    uint16_t n;     /* bit index */
+} fwbf_record;
+
+/* Number of scorer parameters for `rounds` rounds (or a negative error). */
+int fwbf_scorer_size(int rounds);
+
+/* Learned decoding of int8 frames on a full (3,6) base, then plain FWBF
+ * (params `plain`: FWBF_GROUPS, int8) from the original y for every frame
+ * whose syndrome is still nonzero; such frames report the learned rounds
+ * plus the plain rounds.  Outputs as fwbf_decode; learned_ok_dev (optional,
+ * F bytes) receives 1 for frames decoded by the learned pass alone.
+ * records_dev (optional, F * rounds * 32 records) receives the proposals;
+ * labels compare with pool_dev row ((f0 + f) % pool_n) (NULL: all-zero
+ * codeword).  scorer_dev: device float32 parameters, read only. */
+int fwbf_decode_learned(const fwbf_code *code, const fwbf_params *plain, const fwbf_learned_params *lp,
+                        const float *scorer_dev, const void *y_dev, int64_t F, int64_t y_stride,
+                        uint32_t *z_dev, int32_t *iters_dev, uint8_t *ok_dev, uint8_t *learned_ok_dev,
+                        fwbf_record *records_dev, const uint32_t *pool_dev, int64_t pool_n, int64_t f0,
+                        void *stream);
+
+/* Scorer forward and backward over n_tiles tiles of 32 records (records laid
+ * out as emitted, tile index = frame * rounds + round).  scores_dev
+ * (optional, n_tiles * 32 floats) receives the scores.  out_dev (optional,
+ * P + 2 floats) receives the gradient of the mean weighted binary
+ * cross-entropy with logits over the valid records (positives weighted by
+ * pos_weight), then the mean loss and the number of valid records; the sum
+ * over records runs per workgroup and then over workgroups in a fixed
+ * order, so results do not depend on scheduling.  workspace_dev: at least
+ * 1024 * (P + 2) floats when out_dev is given. */
+int fwbf_scorer_grad(const fwbf_record *records_dev, int64_t n_tiles, const fwbf_learned_params *lp,
+                     const float *scorer_dev, float pos_weight, float *out_dev, float *scores_dev,
+                     float *workspace_dev, int64_t workspace_floats, void *stream);
+
+/* One Adam step (Kingma & Ba) on P float32 parameters: moments m, v updated
+ * in place, bias correction for step number `step` (>= 1). */
+int fwbf_adam(float *params_dev, const float *grad_dev, float *m_dev, float *v_dev, int P, int step, float lr,
+              float beta1, float beta2, float eps, void *stream);
+
 /* ---- misc ---------------------------------------------------------------- */
 
 const char *fwbf_last_error(void);

@@ -659,7 +659,8 @@ int occupancy(int DT, bool key32, int T, int lds, int *blocks)
 // data pointers).  Shared by the plain decoder and the batched launch.
 int prepare_decode(const fwbf_code *c, const fwbf_params *p, DecodeArgs *out, int *T_out);
 int try_fast_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int64_t F, int64_t stride,
-                    uint32_t *z, int32_t *iters, uint8_t *ok, hipStream_t st, const uint32_t *shift_dev);
+                    uint32_t *z, int32_t *iters, uint8_t *ok, hipStream_t st, const uint32_t *shift_dev,
+                    const uint8_t *skip, int iters_add);
 
 int prepare_decode(const fwbf_code *c, const fwbf_params *p, DecodeArgs *out, int *T_out)
 {
@@ -785,7 +786,7 @@ extern "C" int fwbf_decode(const fwbf_code *code, const fwbf_params *params, con
     if (rc) return rc;
     if (!(params->flags & FWBF_FLAG_GENERIC_KERNEL)) {
         rc = try_fast_decode(code, params, y_dev, F, y_stride, z_dev, iters_dev, ok_dev, (hipStream_t)stream,
-                             t.shift);
+                             t.shift, nullptr, 0);
         if (rc != 0) return rc < 0 ? rc : FWBF_OK;
     }
     a.y = y_dev; a.F = F; a.stride = y_stride;

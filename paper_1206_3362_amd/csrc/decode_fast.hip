@@ -37,6 +37,8 @@ struct FastArgs {
     int32_t *iters;
     uint8_t *ok;
     const uint32_t *shift;  // DV x nb shifts (block row-major)
+    const uint8_t *skip;    // optional: frames with skip[f] != 0 are left untouched
+    int iters_add;          // add the rounds to iters[f] instead of storing them
     int N, M, Z, nb;
     uint32_t magZ, maskZ, magP, maskP;
     int p, L, logL, Geff, Lc;
@@ -135,6 +137,7 @@ __global__ __launch_bounds__(64) void fast_kernel(FastArgs a)
 
     const FrameRange fr = xcd_frames(a.F);
     for (int64_t f = fr.first; f < fr.end; f += fr.step) {
+        if (a.skip && a.skip[f]) continue;  // uniform across the wave
         const Y *yrow = (const Y *)a.y + f * a.stride;
         __syncthreads();
         for (int w = lane; w < ((M + 63) >> 6) * 2; w += 64) syn[w] = 0;
@@ -343,7 +346,7 @@ __global__ __launch_bounds__(64) void fast_kernel(FastArgs a)
         uint32_t *zo = a.z + f * NW;
         for (int w = lane; w < NW; w += 64) zo[w] = zw[w];
         if (lane == 0) {
-            a.iters[f] = k;
+            a.iters[f] = a.iters_add ? a.iters[f] + k : k;
             a.ok[f] = (uint8_t)okf;
         }
     }
@@ -409,7 +412,8 @@ hipError_t by_deg(int dv, int dc, int C, const FastArgs &a, hipStream_t st, int 
 // Returns 1 if the fast kernel was launched, 0 if the configuration is not
 // covered (the caller then uses the generic kernel), < 0 on error.
 int try_fast_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int64_t F, int64_t stride,
-                    uint32_t *z, int32_t *iters, uint8_t *ok, hipStream_t st, const uint32_t *shift_dev)
+                    uint32_t *z, int32_t *iters, uint8_t *ok, hipStream_t st, const uint32_t *shift_dev,
+                    const uint8_t *skip, int iters_add)
 {
     if (p->dtype != FWBF_I8 && p->dtype != FWBF_I16) return 0;
     if (p->select == FWBF_TOPL) return 0;
@@ -469,6 +473,8 @@ int try_fast_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int
     a.y = y; a.F = F; a.stride = stride;
     a.z = z; a.iters = iters; a.ok = ok;
     a.shift = shift_dev;
+    a.skip = skip;
+    a.iters_add = iters_add;
     int grid = 0;
     hipError_t e = p->dtype == FWBF_I8 ? by_deg<FWBF_I8>(dv, dc, C, a, st, &grid, false)
                                        : by_deg<FWBF_I16>(dv, dc, C, a, st, &grid, false);

@@ -1,0 +1,783 @@
+// Learned flip scorer for FWBF: a per-round metric E_t = beta_t S - alpha_t |y|
+// proposes the k best bits of each block (the paper's partially parallel
+// choice, Section III), and a 4 -> 32 -> 32 -> 1 ReLU network scores the
+// proposals; in each block the best-scoring proposal is flipped if its score
+// is positive.  Frames whose syndrome is still nonzero after the learned pass
+// are decoded again from the original y by plain FWBF (the fast kernel with
+// a skip list).  Training kernels (forward, backward, deterministic
+// reduction, Adam) run on records the learned pass emits.
+//
+// The network runs on MFMA v_mfma_f32_32x32x8_bf16 in transposed form: a
+// tile holds 32 candidates, activations are (hidden x candidate) with the
+// candidate on lane % 32, so the accumulator of one layer is already laid out
+// as the B operand of the next (items 4c..4c+3 of lane l hold rows
+// 8c + 4(l/32) + 0..3 of column l % 32), and the weights are per-lane
+// constant A operands.  Operands are bfloat16 (round to nearest even), sums
+// single precision.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "frames.h"
+#include "internal.h"
+
+namespace fwbf {
+
+int try_fast_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int64_t F, int64_t stride,
+                    uint32_t *z, int32_t *iters, uint8_t *ok, hipStream_t st, const uint32_t *shift_dev,
+                    const uint8_t *skip, int iters_add);
+
+namespace {
+
+constexpr int H = 32;
+constexpr uint32_t NONE = 0xFFFFFFFFu;
+constexpr int SOFF = 2048;  // offset of S in a packed slot word (S + SOFF) << 4 | u
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// parameter vector offsets (float32): W1[32][4] b1 W2[32][32] b2 W3 b3 alpha[T] beta[T]
+constexpr int O_W1 = 0, O_B1 = 128, O_W2 = 160, O_B2 = 1184, O_W3 = 1216, O_B3 = 1248, O_AL = 1249;
+
+__device__ __forceinline__ uint16_t bf16_rne(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d)
+{
+    bf16x4 v;
+    v[0] = (short)bf16_rne(a);
+    v[1] = (short)bf16_rne(b);
+    v[2] = (short)bf16_rne(c);
+    v[3] = (short)bf16_rne(d);
+    return v;
+}
+
+// row (hidden unit) held by accumulator item q of lane l
+__device__ __forceinline__ int row_of(int q, int lane) { return 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3); }
+
+struct Net {
+    bf16x4 w1;      // W1[l%32][4(l/32) + 0..3] (zero for the upper half: only 4 inputs)
+    bf16x4 w2[4];   // W2[l%32][8c + 4(l/32) + 0..3]
+    float b1[16], b2[16], w3[16];
+    float b3;
+};
+
+__device__ void load_net(Net &n, const float *p)
+{
+    const int l = threadIdx.x & 63, i = l & 31, hi = l >> 5;
+    if (hi == 0) n.w1 = pack4(p[O_W1 + i * 4 + 0], p[O_W1 + i * 4 + 1], p[O_W1 + i * 4 + 2], p[O_W1 + i * 4 + 3]);
+    else n.w1 = pack4(0.f, 0.f, 0.f, 0.f);
+    for (int c = 0; c < 4; c++) {
+        const float *r = p + O_W2 + i * H + 8 * c + 4 * hi;
+        n.w2[c] = pack4(r[0], r[1], r[2], r[3]);
+    }
+    for (int q = 0; q < 16; q++) {
+        const int row = row_of(q, l);
+        n.b1[q] = p[O_B1 + row];
+        n.b2[q] = p[O_B2 + row];
+        n.w3[q] = p[O_W3 + row];
+    }
+    n.b3 = p[O_B3];
+}
+
+struct Act {
+    f32x16 pre1, pre2;
+    bf16x4 h1[4];
+};
+
+// Scores the 32 candidates of a tile.  x: the four features of candidate
+// l % 32 in lanes 0..31 (rounded to bfloat16), zero in lanes 32..63.
+// Returns the score of candidate l % 32 (in both halves of the wave).
+__device__ __forceinline__ float net_forward(const Net &n, bf16x4 x, Act &a)
+{
+    const int l = threadIdx.x & 63;
+    f32x16 acc = {};
+    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(n.w1, x, acc, 0, 0, 0);
+    float h[16];
+    for (int q = 0; q < 16; q++) {
+        a.pre1[q] = acc[q] + n.b1[q];
+        h[q] = fmaxf(a.pre1[q], 0.0f);
+    }
+    for (int c = 0; c < 4; c++) a.h1[c] = pack4(h[4 * c], h[4 * c + 1], h[4 * c + 2], h[4 * c + 3]);
+    f32x16 acc2 = {};
+    for (int c = 0; c < 4; c++) acc2 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(n.w2[c], a.h1[c], acc2, 0, 0, 0);
+    float part = 0.0f;
+    for (int q = 0; q < 16; q++) {
+        a.pre2[q] = acc2[q] + n.b2[q];
+        part = __builtin_fmaf(n.w3[q], fmaxf(a.pre2[q], 0.0f), part);
+    }
+    (void)l;
+    return part + __shfl_xor(part, 32, 64) + n.b3;
+}
+
+__device__ __forceinline__ uint32_t orderable(float e)
+{
+    uint32_t u = __float_as_uint(e == 0.0f ? 0.0f : e);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t mag, uint32_t mask) { return __umulhi(n, mag) + (n & mask); }
+__device__ __forceinline__ uint32_t addmod(uint32_t a, uint32_t b, uint32_t Z) { const uint32_t s = a + b; return min(s, s - Z); }
+__device__ __forceinline__ uint32_t submod(uint32_t a, uint32_t b, uint32_t Z) { const uint32_t s = a - b; return min(s, s + Z); }
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ unsigned long long umax64(unsigned long long a, unsigned long long b) { return a > b ? a : b; }
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp64(unsigned long long v)
+{
+    return ((unsigned long long)dpp<CTRL>((uint32_t)(v >> 32)) << 32) | dpp<CTRL>((uint32_t)v);
+}
+// maximum over aligned groups of L lanes, L a power of two <= 64
+__device__ __forceinline__ unsigned long long group_max64(unsigned long long v, int L)
+{
+    if (L > 1) v = umax64(v, dpp64<0xB1>(v));
+    if (L > 2) v = umax64(v, dpp64<0x4E>(v));
+    if (L > 4) v = umax64(v, dpp64<0x141>(v));
+    if (L > 8) v = umax64(v, dpp64<0x140>(v));
+    for (int d = 16; d < L; d <<= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)v, d, 64), hi = __shfl_xor((uint32_t)(v >> 32), d, 64);
+        v = umax64(v, ((unsigned long long)hi << 32) | lo);
+    }
+    return v;
+}
+
+struct LearnArgs {
+    const int8_t *y;
+    int64_t F, stride;
+    uint32_t *z;
+    int32_t *iters;
+    uint8_t *ok;
+    uint8_t *learned_ok;  // optional
+    fwbf_record *rec;     // optional [F][T][32]
+    const uint32_t *pool; // labels for records (pool row f % pool_n, NULL: all-zero)
+    int64_t pool_n, f0;
+    const float *params;
+    const uint32_t *shift;
+    int N, M, Z, nb;
+    uint32_t magZ, maskZ, magP, maskP;
+    int p, L, logL, Geff, k, T;
+    float A, dv;
+    int o_chk, o_y, o_z, o_syn, o_list, o_sh, o_cand, lds_bytes;
+};
+
+__device__ __forceinline__ uint32_t slot_chunk(uint32_t lane, uint32_t kk) { return (kk << 6) + (lane ^ ((kk & 15) << 2)); }
+__device__ __forceinline__ uint32_t slot_word(uint32_t lane, uint32_t k) { return slot_chunk(lane, k >> 2) * 4 + (k & 3); }
+
+template <int DV, int DC, int C>
+__global__ __launch_bounds__(64) void learned_kernel(LearnArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t *slots = (uint32_t *)smem;  // (S + SOFF) << 4 | u per bit
+    uint32_t *chk = (uint32_t *)(smem + a.o_chk);
+    int8_t *yv = (int8_t *)(smem + a.o_y);
+    uint32_t *zw = (uint32_t *)(smem + a.o_z);
+    uint32_t *syn = (uint32_t *)(smem + a.o_syn);
+    uint32_t *list = (uint32_t *)(smem + a.o_list);
+    uint32_t *sh = (uint32_t *)(smem + a.o_sh);
+    uint4 *cand = (uint4 *)(smem + a.o_cand);  // 32 proposals: n, S+SOFF, u, a
+
+    const uint32_t lane = threadIdx.x;
+    const uint32_t Z = a.Z;
+    const int N = a.N, M = a.M;
+    for (int t = lane; t < DV * a.nb; t += 64) sh[t] = a.shift[t];
+    Net net;
+    load_net(net, a.params);
+
+    const uint32_t g = lane >> a.logL;
+    const bool lead = ((lane & (a.L - 1)) == 0) && (int)g < a.Geff;
+    const uint32_t pos0 = (lane & (a.L - 1)) * C;
+    const uint32_t gp = g * a.p;
+    const int NW = (N + 31) >> 5;
+    const int NC = a.Geff * a.k;  // proposals per round (<= 32)
+
+    const FrameRange fr = xcd_frames(a.F);
+    for (int64_t f = fr.first; f < fr.end; f += fr.step) {
+        const int8_t *yrow = a.y + f * a.stride;
+        __syncthreads();
+        for (int w = lane; w < ((M + 63) >> 6) * 2; w += 64) syn[w] = 0;
+        for (int w = lane; w < ((N + 63) >> 6) * 2; w += 64) zw[w] = 0;
+        for (int n = lane; n < N; n += 64) yv[n] = yrow[n];
+#pragma unroll
+        for (int kk = 0; kk < C; kk += 4) {
+            uint4 v;
+            uint32_t *vp = (uint32_t *)&v;
+#pragma unroll
+            for (int u = 0; u < 4; u++) vp[u] = (uint32_t)SOFF << 4;
+            ((uint4 *)slots)[slot_chunk(lane, kk >> 2)] = v;
+        }
+        __syncthreads();
+        for (int n0 = 0; n0 < N; n0 += 64) {
+            const int n = n0 + (int)lane;
+            const unsigned long long b = __ballot(n < N && yv[n] < 0);
+            if (lane == 0) {
+                zw[n0 >> 5] = (uint32_t)b;
+                zw[(n0 >> 5) + 1] = (uint32_t)(b >> 32);
+            }
+        }
+        // |y| of the slots of this lane
+        float amag[C];
+#pragma unroll
+        for (int kk = 0; kk < C; kk++) {
+            const uint32_t pos = pos0 + kk;
+            const uint32_t n = gp + pos;
+            const bool real = (int)g < a.Geff && (int)pos < a.p && (int)n < N;
+            const int v = real ? (int)yv[n] : 0;
+            amag[kk] = (float)(v < 0 ? -v : v);
+        }
+        // check minima, syndrome, initial S and u pushed from the check side
+        int weight = 0;
+        for (int i = 0; i < DV; i++) {
+            uint32_t js[DC];
+#pragma unroll
+            for (int q = 0; q < DC; q++) js[q] = sh[i * a.nb + q];
+            for (uint32_t r0 = 0; r0 < Z; r0 += 64) {
+                const uint32_t r = r0 + lane;
+                const bool valid = r < Z;
+                uint32_t nn[DC];
+                uint32_t m1 = 0xFFFFu, m2 = 0xFFFFu, pos = 0, par = 0;
+                if (valid) {
+#pragma unroll
+                    for (int q = 0; q < DC; q++) {
+                        const uint32_t n = q * Z + addmod(r, js[q], Z);
+                        const int v = (int)yv[n];
+                        const uint32_t av = (uint32_t)(v < 0 ? -v : v);
+                        nn[q] = n;
+                        par ^= (uint32_t)(v < 0);
+                        const bool lt = av < m1;
+                        m2 = lt ? m1 : min(m2, av);
+                        pos = lt ? (uint32_t)q : pos;
+                        m1 = lt ? av : m1;
+                    }
+                    chk[i * Z + r] = m1 | (m2 << 8) | (pos << 16);
+#pragma unroll
+                    for (int q = 0; q < DC; q++) {
+                        const uint32_t w = (pos == (uint32_t)q) ? m2 : m1;
+                        const int d = ((par ? (int)w : -(int)w) << 4) + (int)par;
+                        const uint32_t n = nn[q];
+                        const uint32_t gg = fdiv(n, a.magP, a.maskP);
+                        const uint32_t pp = n - gg * a.p;
+                        atomicAdd(&slots[slot_word(gg * a.L + pp / C, pp & (C - 1))], (uint32_t)d);
+                    }
+                }
+                const unsigned long long b = __ballot(valid && par);
+                weight += __popcll(b);
+                if (valid && par) atomicOr(&syn[(i * Z + r) >> 5], 1u << ((i * Z + r) & 31));
+            }
+        }
+        __syncthreads();
+
+        int t = 0, okf = 0, rec_end = 0;
+        uint32_t prv = NONE;
+        const uint32_t *cw = a.pool ? a.pool + (size_t)((a.f0 + f) % a.pool_n) * NW : nullptr;
+        for (;;) {
+            if (weight == 0) { okf = 1; break; }
+            if (t == a.T) break;
+            const float al = a.params[O_AL + t], be = a.params[O_AL + a.T + t];
+            // metric E_t of this lane's slots, as order-preserving keys
+            uint32_t key[C];
+#pragma unroll
+            for (int kk = 0; kk < C; kk += 4) {
+                const uint4 v = ((const uint4 *)slots)[slot_chunk(lane, kk >> 2)];
+                const uint32_t vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const uint32_t pos = pos0 + kk + u;
+                    const bool real = (int)g < a.Geff && (int)pos < a.p && (int)(gp + pos) < N;
+                    const float S = (float)((int)(vv[u] >> 4) - SOFF);
+                    const float E = __builtin_fmaf(-al, amag[kk + u], be * S);
+                    key[kk + u] = real ? orderable(E) : 0u;
+                }
+            }
+            // k best per block (ties: lower index), each excluded before the next
+            for (int rk = 0; rk < a.k; rk++) {
+                unsigned long long best = 0;
+#pragma unroll
+                for (int kk = 0; kk < C; kk++) {
+                    const unsigned long long v = ((unsigned long long)key[kk] << 32) | (0xFFFFFFFFu - (pos0 + kk));
+                    best = umax64(best, v);
+                }
+                best = group_max64(best, a.L);
+                const uint32_t bpos = 0xFFFFFFFFu - (uint32_t)best;
+                // the owner of the chosen slot excludes it
+                if ((int)g < a.Geff && bpos / C == (lane & (a.L - 1))) {
+#pragma unroll
+                    for (int kk = 0; kk < C; kk++)
+                        if ((uint32_t)kk == (bpos & (C - 1))) key[kk] = 0;
+                }
+                if (lead) {
+                    const uint32_t n = gp + bpos;
+                    const bool real = (best >> 32) != 0;
+                    uint32_t word = 0;
+                    if (real) word = slots[slot_word(g * a.L + bpos / C, bpos & (C - 1))];
+                    const int yvn = real ? (int)yv[n] : 0;
+                    cand[g * a.k + rk] = make_uint4(real ? n : NONE, word >> 4, word & 15u, (uint32_t)(yvn < 0 ? -yvn : yvn));
+                }
+            }
+            __syncthreads();
+            // features of proposal lane % 32, score
+            const uint32_t j = lane & 31;
+            const uint4 cj = j < (uint32_t)NC ? cand[j] : make_uint4(NONE, 0, 0, 0);
+            const bool realc = cj.x != NONE;
+            bf16x4 x = pack4(0.f, 0.f, 0.f, 0.f);
+            if (lane < 32 && realc) {
+                const float S = (float)((int)cj.y - SOFF);
+                const float E = __builtin_fmaf(-al, (float)cj.w, be * S);
+                x = pack4((float)cj.w / a.A, E / a.A, (float)cj.z / a.dv, (float)t / (float)a.T);
+            }
+            Act act;
+            const float score = net_forward(net, x, act);
+            if (a.rec && lane < 32 && j < (uint32_t)NC) {
+                fwbf_record r;
+                r.S = (int16_t)((int)cj.y - SOFF);
+                r.a = (uint8_t)cj.w;
+                r.u = (uint8_t)cj.z;
+                uint32_t lab = 0;
+                if (realc) {
+                    const uint32_t zb = (zw[cj.x >> 5] >> (cj.x & 31)) & 1u;
+                    const uint32_t cb = cw ? (cw[cj.x >> 5] >> (cj.x & 31)) & 1u : 0u;
+                    lab = zb ^ cb;
+                }
+                r.label = (uint8_t)lab;
+                r.valid = realc ? 1 : 0;
+                r.n = (uint16_t)(realc ? cj.x : 0xFFFF);
+                a.rec[((size_t)f * a.T + t) * 32 + j] = r;
+            }
+            rec_end = t + 1;
+            // best score among the k proposals of each block (ties: lower index)
+            unsigned long long sk = realc ? (((unsigned long long)orderable(score) << 32) | (0xFFFFFFFFu - cj.x)) : 0ull;
+            if (a.k > 1) sk = group_max64(sk, a.k);
+            const bool blead = lane < 32 && (j % a.k) == 0 && j < (uint32_t)NC;
+            const uint32_t nsel = 0xFFFFFFFFu - (uint32_t)sk;
+            const bool flip = blead && (sk >> 32) > orderable(0.0f) && sk != 0;
+            const uint32_t cur = flip ? nsel : NONE;
+            const unsigned long long fmask = __ballot(flip);
+            const unsigned long long dmask = __ballot(blead && cur != prv);
+            prv = blead ? cur : prv;
+            if (fmask == 0 || dmask == 0) break;  // no flip, or the previous round's flips: stop
+            const int rank = __popcll(fmask & ((1ull << lane) - 1));
+            uint32_t onesm = 0;
+            if (flip) {
+                const uint32_t n = nsel;
+                atomicXor(&zw[n >> 5], 1u << (n & 31));
+                const uint32_t jb = fdiv(n, a.magZ, a.maskZ);
+                const uint32_t c = n - jb * Z;
+                uint32_t rr[DV], old[DV];
+#pragma unroll
+                for (int tt = 0; tt < DV; tt++) rr[tt] = submod(c, sh[tt * a.nb + jb], Z);
+#pragma unroll
+                for (int tt = 0; tt < DV; tt++) {
+                    const uint32_t m = tt * Z + rr[tt];
+                    old[tt] = atomicXor(&syn[m >> 5], 1u << (m & 31));
+                }
+#pragma unroll
+                for (int tt = 0; tt < DV; tt++) {
+                    const uint32_t m = tt * Z + rr[tt];
+                    const uint32_t nb1 = ((old[tt] >> (m & 31)) & 1u) ^ 1u;
+                    onesm |= nb1 << tt;
+                    list[rank * DV + tt] = rr[tt] | ((uint32_t)tt << 16) | (nb1 << 31);
+                }
+            }
+            int sum_ones = 0;
+#pragma unroll
+            for (int tt = 0; tt < DV; tt++) sum_ones += __popcll(__ballot((onesm >> tt) & 1));
+            const int nflip = __popcll(fmask);
+            weight += 2 * sum_ones - DV * nflip;
+            t += 1;
+            __syncthreads();
+            const int ntask = nflip * DV * DC;
+            for (int base = 0; base < ntask; base += 64) {
+                const int tk = base + (int)lane;
+                if (tk < ntask) {
+                    const int u = tk / DC, q = tk - (tk / DC) * DC;
+                    const uint32_t e = list[u];
+                    const uint32_t r = e & 0xFFFFu, i = (e >> 16) & 0x7FFFu;
+                    const uint32_t m = i * Z + r;
+                    const uint32_t nq = q * Z + addmod(r, sh[i * a.nb + q], Z);
+                    const uint32_t cwd = chk[m];
+                    const uint32_t w = (((cwd >> 16) & 0xFF) == (uint32_t)q) ? ((cwd >> 8) & 0xFF) : (cwd & 0xFF);
+                    const int d = (e >> 31) ? ((2 * (int)w) << 4) + 1 : -((2 * (int)w) << 4) - 1;
+                    const uint32_t gg = fdiv(nq, a.magP, a.maskP);
+                    const uint32_t pp = nq - gg * a.p;
+                    atomicAdd(&slots[slot_word(gg * a.L + pp / C, pp & (C - 1))], (uint32_t)d);
+                }
+            }
+            __syncthreads();
+        }
+        __syncthreads();
+        // records of the rounds not run are marked invalid
+        if (a.rec)
+            for (int s = rec_end; s < a.T; s++)
+                if (lane < 32) a.rec[((size_t)f * a.T + s) * 32 + lane].valid = 0;
+        uint32_t *zo = a.z + f * NW;
+        for (int w = lane; w < NW; w += 64) zo[w] = zw[w];
+        if (lane == 0) {
+            a.iters[f] = t;
+            a.ok[f] = (uint8_t)okf;
+            if (a.learned_ok) a.learned_ok[f] = (uint8_t)okf;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// training kernels
+// ---------------------------------------------------------------------------
+struct GradArgs {
+    const fwbf_record *rec;
+    int64_t n_tiles;
+    const float *params;
+    float pos_weight, A, dv;
+    int T, P;
+    float *partial;  // [gridDim][P + 2]
+    float *scores;   // optional forward output [n_tiles][32]
+    int backward;
+};
+
+// features of record j of a tile in lanes 0..31 (bfloat16), zero above
+__device__ __forceinline__ bf16x4 record_features(const fwbf_record &r, int t, const GradArgs &g, float al, float be)
+{
+    const float S = (float)r.S;
+    const float E = __builtin_fmaf(-al, (float)r.a, be * S);
+    return pack4((float)r.a / g.A, E / g.A, (float)r.u / g.dv, (float)t / (float)g.T);
+}
+
+__global__ __launch_bounds__(64) void grad_kernel(GradArgs g)
+{
+    __shared__ float sp2[32][33];  // dpre2 (rounded) [hidden][cand]
+    __shared__ float sp1[32][33];  // dpre1 [hidden][cand]
+    __shared__ float sh1[32][33];  // h1 (rounded) [hidden][cand]
+    __shared__ float sh2[32][33];  // h2 [hidden][cand]
+    __shared__ float sx[4][33];    // features (rounded) [feature][cand]
+    __shared__ float sab[2][64];   // alpha / beta gradient accumulators per round
+    const int l = threadIdx.x, j = l & 31, hi = l >> 5;
+    Net net;
+    load_net(net, g.params);
+    for (int t = l; t < 128; t += 64) (&sab[0][0])[t] = 0.0f;
+    // per-lane accumulators
+    float aW1a = 0, aW1b = 0, aB = 0, aW3 = 0, aB3 = 0, aLoss = 0, aCnt = 0;
+    f32x16 aW2 = {};
+    // W2 transposed as the A operand of dh1 = W2^T dpre2: lane l holds
+    // W2[8c + 4(l/32) + 0..3][l % 32]
+    bf16x4 w2t[4];
+    for (int c = 0; c < 4; c++) {
+        const int k0 = 8 * c + 4 * hi;
+        w2t[c] = pack4(g.params[O_W2 + (k0 + 0) * H + j], g.params[O_W2 + (k0 + 1) * H + j],
+                       g.params[O_W2 + (k0 + 2) * H + j], g.params[O_W2 + (k0 + 3) * H + j]);
+    }
+    const float w1col1 = bf16_f(bf16_rne(g.params[O_W1 + j * 4 + 1]));
+    __syncthreads();
+    for (int64_t tile = blockIdx.x; tile < g.n_tiles; tile += gridDim.x) {
+        const int t = (int)(tile % g.T);
+        const fwbf_record r = g.rec[tile * 32 + j];
+        const bool valid = r.valid != 0;
+        if (!__ballot(valid)) continue;
+        const float al = g.params[O_AL + t], be = g.params[O_AL + g.T + t];
+        bf16x4 x = pack4(0.f, 0.f, 0.f, 0.f);
+        if (hi == 0 && valid) x = record_features(r, t, g, al, be);
+        Act act;
+        const float s = net_forward(net, x, act);
+        if (g.scores && hi == 0) g.scores[tile * 32 + j] = valid ? s : 0.0f;
+        if (!g.backward) continue;
+        // d loss / d score (weighted binary cross-entropy with logits)
+        const float y = (float)r.label;
+        const float sig = 1.0f / (1.0f + __expf(-s));
+        const float ds = valid ? (g.pos_weight * y * (sig - 1.0f) + (1.0f - y) * sig) : 0.0f;
+        if (hi == 0 && valid) {
+            aLoss += g.pos_weight * y * log1pf(__expf(-fabsf(s))) + g.pos_weight * y * fmaxf(-s, 0.0f) +
+                     (1.0f - y) * (log1pf(__expf(-fabsf(s))) + fmaxf(s, 0.0f));
+            aCnt += 1.0f;
+            aB3 += ds;
+        }
+        // layer 3 and the ReLU of layer 2
+        bf16x4 d2[4];
+        for (int q = 0; q < 16; q++) {
+            const int row = row_of(q, l);
+            const float h2 = fmaxf(act.pre2[q], 0.0f);
+            const float dp2 = act.pre2[q] > 0.0f ? ds * net.w3[q] : 0.0f;
+            const uint16_t dp2b = bf16_rne(dp2);
+            sp2[row][j] = dp2;
+            sh2[row][j] = h2;
+            sh1[row][j] = bf16_f((uint16_t)act.h1[q >> 2][q & 3]);
+            if ((q & 3) == 0) d2[q >> 2] = bf16x4{0, 0, 0, 0};
+            d2[q >> 2][q & 3] = (short)dp2b;
+        }
+        // dh1 = W2^T dpre2 (MFMA, chained layout)
+        f32x16 dh1 = {};
+        for (int c = 0; c < 4; c++) dh1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(w2t[c], d2[c], dh1, 0, 0, 0);
+        for (int q = 0; q < 16; q++) {
+            const int row = row_of(q, l);
+            sp1[row][j] = act.pre1[q] > 0.0f ? dh1[q] : 0.0f;
+        }
+        if (hi == 0) {
+            sx[0][j] = bf16_f((uint16_t)x[0]);
+            sx[1][j] = bf16_f((uint16_t)x[1]);
+            sx[2][j] = bf16_f((uint16_t)x[2]);
+            sx[3][j] = bf16_f((uint16_t)x[3]);
+        }
+        __syncthreads();
+        // dW2 += dpre2 h1^T: A[i][cand] = dpre2 (rounded), B[cand][k] = h1
+        for (int c = 0; c < 4; c++) {
+            const int k0 = 8 * c + 4 * hi;
+            const bf16x4 A = pack4(sp2[j][k0], sp2[j][k0 + 1], sp2[j][k0 + 2], sp2[j][k0 + 3]);
+            const bf16x4 B = pack4(sh1[j][k0], sh1[j][k0 + 1], sh1[j][k0 + 2], sh1[j][k0 + 3]);
+            aW2 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A, B, aW2, 0, 0, 0);
+        }
+        // row sums over the 32 candidates (fixed order)
+        if (hi == 0) {
+            float s1a = 0, s1b = 0, sb1 = 0, sw3 = 0;
+            for (int c = 0; c < 32; c++) {
+                s1a = __builtin_fmaf(sp1[j][c], sx[0][c], s1a);
+                s1b = __builtin_fmaf(sp1[j][c], sx[1][c], s1b);
+                sb1 += sp1[j][c];
+                sw3 = __builtin_fmaf(sh2[j][c], __shfl(ds, c, 64), sw3);
+            }
+            aW1a += s1a; aW1b += s1b; aB += sb1; aW3 += sw3;
+        } else {
+            float s1c = 0, s1d = 0, sb2 = 0;
+            for (int c = 0; c < 32; c++) {
+                s1c = __builtin_fmaf(sp1[j][c], sx[2][c], s1c);
+                s1d = __builtin_fmaf(sp1[j][c], sx[3][c], s1d);
+                sb2 += sp2[j][c];
+            }
+            aW1a += s1c; aW1b += s1d; aB += sb2;
+        }
+        // d x1 of candidate j -> alpha_t, beta_t
+        float dx1 = 0;
+        for (int k = 0; k < 32; k++) dx1 = __builtin_fmaf(sp1[k][j], __shfl(w1col1, k, 64), dx1);
+        float ga = 0, gb = 0;
+        if (hi == 0 && valid) {
+            ga = dx1 * (-(float)r.a / g.A);
+            gb = dx1 * ((float)r.S / g.A);
+        }
+        for (int d = 16; d >= 1; d >>= 1) {
+            ga += __shfl_xor(ga, d, 64);
+            gb += __shfl_xor(gb, d, 64);
+        }
+        if (l == 0) {
+            sab[0][t] += ga;
+            sab[1][t] += gb;
+        }
+        __syncthreads();
+    }
+    // write this workgroup's partial gradient
+    float *out = g.partial + (size_t)blockIdx.x * (g.P + 2);
+    if (hi == 0) {
+        out[O_W1 + j * 4 + 0] = aW1a;
+        out[O_W1 + j * 4 + 1] = aW1b;
+        out[O_B1 + j] = aB;
+        out[O_W3 + j] = aW3;
+    } else {
+        out[O_W1 + j * 4 + 2] = aW1a;
+        out[O_W1 + j * 4 + 3] = aW1b;
+        out[O_B2 + j] = aB;
+    }
+    for (int q = 0; q < 16; q++) out[O_W2 + row_of(q, l) * H + j] = aW2[q];
+    float b3 = aB3, ls = aLoss, cn = aCnt;
+    for (int d = 32; d >= 1; d >>= 1) {
+        b3 += __shfl_xor(b3, d, 64);
+        ls += __shfl_xor(ls, d, 64);
+        cn += __shfl_xor(cn, d, 64);
+    }
+    if (l == 0) {
+        out[O_B3] = b3;
+        out[g.P] = ls;
+        out[g.P + 1] = cn;
+    }
+    for (int t = l; t < g.T; t += 64) {
+        out[O_AL + t] = sab[0][t];
+        out[O_AL + g.T + t] = sab[1][t];
+    }
+}
+
+// sums the per-workgroup partials in workgroup order and divides by the
+// number of valid records: out[0..P) gradient, out[P] loss, out[P+1] count
+__global__ void reduce_kernel(const float *partial, int nparts, int P, float *out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P + 2) return;
+    double acc = 0.0, cnt = 0.0;
+    for (int b = 0; b < nparts; b++) {
+        acc += partial[(size_t)b * (P + 2) + i];
+        cnt += partial[(size_t)b * (P + 2) + P + 1];
+    }
+    out[i] = (i == P + 1) ? (float)cnt : (float)(cnt > 0 ? acc / cnt : 0.0);
+}
+
+__global__ void adam_kernel(float *p, const float *g, float *m, float *v, int P, float lr, float b1, float b2,
+                            float eps, float c1, float c2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+namespace {
+int ilog2l(uint32_t v) { int r = 0; while ((1u << r) < v) r++; return r; }
+void magic_l(uint32_t d, uint32_t *mag, uint32_t *mask)
+{
+    if (d <= 1) { *mag = 0; *mask = 0xFFFFFFFFu; return; }
+    *mag = (uint32_t)(((1ULL << 32) + d - 1) / d);
+    *mask = 0;
+}
+int check_lp(const fwbf_learned_params *lp)
+{
+    if (!lp) return fail(FWBF_E_INVALID, "null learned params");
+    if (lp->rounds < 1 || lp->rounds > 64) return fail(FWBF_E_INVALID, "rounds must be in [1, 64]");
+    if (lp->topk < 1 || lp->topk > 4 || (lp->topk & (lp->topk - 1)))
+        return fail(FWBF_E_INVALID, "topk must be 1, 2 or 4");
+    if (lp->groups < 1) return fail(FWBF_E_INVALID, "groups must be >= 1");
+    if (!(lp->scale > 0.0f)) return fail(FWBF_E_INVALID, "scale must be > 0");
+    return FWBF_OK;
+}
+}  // namespace
+
+}  // namespace fwbf
+
+using namespace fwbf;
+
+extern "C" int fwbf_scorer_size(int rounds) { return rounds < 1 ? fail(FWBF_E_INVALID, "rounds must be >= 1") : 1249 + 2 * rounds; }
+
+extern "C" int fwbf_decode_learned(const fwbf_code *code, const fwbf_params *plain, const fwbf_learned_params *lp,
+                                   const float *scorer_dev, const void *y_dev, int64_t F, int64_t y_stride,
+                                   uint32_t *z_dev, int32_t *iters_dev, uint8_t *ok_dev, uint8_t *learned_ok_dev,
+                                   fwbf_record *records_dev, const uint32_t *pool_dev, int64_t pool_n, int64_t f0,
+                                   void *stream)
+{
+    int rc = check_lp(lp);
+    if (rc) return rc;
+    if (!code || !plain) return fail(FWBF_E_INVALID, "null code or params");
+    if (plain->dtype != FWBF_I8) return fail(FWBF_E_UNSUPPORTED, "the learned decoder takes int8 inputs");
+    if (code->mb != 3 || code->nb != 6) return fail(FWBF_E_UNSUPPORTED, "the learned decoder covers (3,6) base matrices");
+    for (int v : code->shift)
+        if (v < 0) return fail(FWBF_E_UNSUPPORTED, "the learned decoder needs a full base (no zero blocks)");
+    if (plain->select != FWBF_GROUPS || plain->threads_per_frame != 0)
+        return fail(FWBF_E_UNSUPPORTED, "the fallback must be plain FWBF (GROUPS)");
+    if (F < 0 || y_stride < code->N || f0 < 0 || (pool_dev && pool_n < 1)) return fail(FWBF_E_INVALID, "invalid size");
+    if (lp->groups > code->N) return fail(FWBF_E_INVALID, "groups must be <= N");
+    if (F == 0) return FWBF_OK;
+    if (!scorer_dev || !y_dev || !z_dev || !iters_dev || !ok_dev) return fail(FWBF_E_INVALID, "null buffer");
+    LearnArgs a;
+    memset(&a, 0, sizeof a);
+    a.p = (code->N + lp->groups - 1) / lp->groups;
+    a.Geff = (code->N + a.p - 1) / a.p;
+    a.k = lp->topk;
+    if (a.Geff * a.k > 32) return fail(FWBF_E_UNSUPPORTED, "groups * topk must be <= 32");
+    int C = 0, L = 0;
+    for (int cc : {4, 8, 16, 32, 64}) {
+        const int need = (a.p + cc - 1) / cc;
+        const int l = 1 << ilog2l(need);
+        if ((int64_t)a.Geff * l <= 64) { C = cc; L = l; break; }
+    }
+    if (!C) return fail(FWBF_E_UNSUPPORTED, "block too long for one wave");
+    a.L = L; a.logL = ilog2l(L);
+    a.N = code->N; a.M = code->M; a.Z = code->Z; a.nb = code->nb;
+    magic_l(code->Z, &a.magZ, &a.maskZ);
+    magic_l(a.p, &a.magP, &a.maskP);
+    a.T = lp->rounds;
+    a.A = lp->scale;
+    a.dv = 3.0f;
+    int off = 64 * C * 4;
+    auto take = [&](int bytes, int align) { off = (off + align - 1) / align * align; int o = off; off += bytes; return o; };
+    a.o_chk = take(4 * code->M, 4);
+    a.o_y = take((code->N + 15) / 16 * 16, 16);
+    a.o_z = take(((code->N + 63) / 64) * 8, 8);
+    a.o_syn = take(((code->M + 63) / 64) * 8, 8);
+    a.o_list = take(4 * 3 * 64, 4);
+    a.o_sh = take(4 * 3 * code->nb, 4);
+    a.o_cand = take(16 * 32, 16);
+    a.lds_bytes = (off + 15) / 16 * 16;
+    if (a.lds_bytes > 64 * 1024) return fail(FWBF_E_UNSUPPORTED, "frame state exceeds 64 KiB of LDS");
+    DeviceTables tb;
+    rc = device_tables(const_cast<fwbf_code *>(code), &tb);
+    if (rc) return rc;
+    a.y = (const int8_t *)y_dev; a.F = F; a.stride = y_stride;
+    a.z = z_dev; a.iters = iters_dev; a.ok = ok_dev; a.learned_ok = learned_ok_dev;
+    a.rec = records_dev; a.pool = pool_dev; a.pool_n = pool_n; a.f0 = f0;
+    a.params = scorer_dev; a.shift = tb.shift;
+    hipStream_t st = (hipStream_t)stream;
+    auto launch = [&](auto kern) -> int {
+        int blocks = 0, dev = 0, cus = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kern, 64, a.lds_bytes);
+        if (e == hipSuccess) e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return hip_fail(e, "learned decode occupancy");
+        if (blocks < 1) return fail(FWBF_E_UNSUPPORTED, "learned kernel does not fit");
+        const int64_t grid = std::min<int64_t>(F, (int64_t)blocks * cus);
+        hipLaunchKernelGGL(kern, dim3((int)grid), dim3(64), a.lds_bytes, st, a);
+        e = hipGetLastError();
+        return e == hipSuccess ? FWBF_OK : hip_fail(e, "learned decode launch");
+    };
+    switch (C) {
+    case 4: rc = launch(learned_kernel<3, 6, 4>); break;
+    case 8: rc = launch(learned_kernel<3, 6, 8>); break;
+    case 16: rc = launch(learned_kernel<3, 6, 16>); break;
+    case 32: rc = launch(learned_kernel<3, 6, 32>); break;
+    default: rc = launch(learned_kernel<3, 6, 64>); break;
+    }
+    if (rc) return rc;
+    // plain FWBF from the original y for every frame the learned pass left
+    // with a nonzero syndrome; its rounds add to the learned ones
+    rc = try_fast_decode(code, plain, y_dev, F, y_stride, z_dev, iters_dev, ok_dev, st, tb.shift, ok_dev, 1);
+    if (rc == 0) return fail(FWBF_E_UNSUPPORTED, "no fallback kernel for these parameters");
+    return rc < 0 ? rc : FWBF_OK;
+}
+
+extern "C" int fwbf_scorer_grad(const fwbf_record *records_dev, int64_t n_tiles, const fwbf_learned_params *lp,
+                                const float *scorer_dev, float pos_weight, float *out_dev, float *scores_dev,
+                                float *workspace_dev, int64_t workspace_floats, void *stream)
+{
+    int rc = check_lp(lp);
+    if (rc) return rc;
+    if (n_tiles < 0) return fail(FWBF_E_INVALID, "n_tiles must be >= 0");
+    if (!scorer_dev || (!out_dev && !scores_dev)) return fail(FWBF_E_INVALID, "null buffer");
+    const int P = 1249 + 2 * lp->rounds;
+    const int parts = 1024;
+    if (out_dev && (!workspace_dev || workspace_floats < (int64_t)parts * (P + 2)))
+        return fail(FWBF_E_INVALID, "workspace too small (need 1024 * (P + 2) floats)");
+    if (n_tiles > 0 && !records_dev) return fail(FWBF_E_INVALID, "null records");
+    GradArgs g;
+    g.rec = records_dev; g.n_tiles = n_tiles; g.params = scorer_dev;
+    g.pos_weight = pos_weight; g.A = lp->scale; g.dv = 3.0f;
+    g.T = lp->rounds; g.P = P;
+    g.partial = workspace_dev; g.scores = scores_dev; g.backward = out_dev != nullptr;
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(grad_kernel, dim3(parts), dim3(64), 0, st, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "scorer gradient launch");
+    if (out_dev) {
+        hipLaunchKernelGGL(reduce_kernel, dim3((P + 2 + 255) / 256), dim3(256), 0, st, workspace_dev, parts, P, out_dev);
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "gradient reduction launch");
+    }
+    return FWBF_OK;
+}
+
+extern "C" int fwbf_adam(float *params_dev, const float *grad_dev, float *m_dev, float *v_dev, int P, int step,
+                         float lr, float beta1, float beta2, float eps, void *stream)
+{
+    if (!params_dev || !grad_dev || !m_dev || !v_dev || P < 1 || step < 1) return fail(FWBF_E_INVALID, "invalid argument");
+    const float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
+    hipLaunchKernelGGL(adam_kernel, dim3((P + 255) / 256), dim3(256), 0, (hipStream_t)stream, params_dev, grad_dev,
+                       m_dev, v_dev, P, lr, beta1, beta2, eps, c1, c2);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FWBF_OK : hip_fail(e, "adam launch");
+}

@@ -32,6 +32,7 @@ EXPORTS = [
     "fwbf_code_from_text", "fwbf_code_from_seed", "fwbf_code_to_text", "fwbf_code_dims",
     "fwbf_code_shifts", "fwbf_code_has_4cycle", "fwbf_code_free", "fwbf_code_info_positions",
     "fwbf_encode", "fwbf_channel", "fwbf_decode", "fwbf_count", "fwbf_last_error", "fwbf_version",
+    "fwbf_scorer_size", "fwbf_decode_learned", "fwbf_scorer_grad", "fwbf_adam",
 ]
 
 
@@ -46,6 +47,15 @@ class Params(C.Structure):
                 ("groups", C.c_int32), ("lambda_", C.c_int32), ("max_iter", C.c_int32),
                 ("alpha", C.c_float), ("alpha_num", C.c_int32), ("alpha_den", C.c_int32),
                 ("threads_per_frame", C.c_int32), ("flags", C.c_uint32)]
+
+
+class LearnedParams(C.Structure):
+    _fields_ = [("rounds", C.c_int32), ("groups", C.c_int32), ("topk", C.c_int32),
+                ("scale", C.c_float)]
+
+
+RECORD_DTYPE = np.dtype([("S", "<i2"), ("a", "u1"), ("u", "u1"), ("label", "u1"), ("valid", "u1"),
+                         ("n", "<u2")])
 
 
 _lib = None
@@ -75,6 +85,13 @@ def lib():
                                    C.c_float, i32, vp, i64, vp]
         L.fwbf_decode.argtypes = [vp, C.POINTER(Params), vp, i64, i64, vp, vp, vp, vp]
         L.fwbf_count.argtypes = [i32, i64, i64, vp, vp, i64, vp, vp, i32, vp, vp]
+        L.fwbf_scorer_size.argtypes = [i32]
+        L.fwbf_decode_learned.argtypes = [vp, C.POINTER(Params), C.POINTER(LearnedParams), vp, vp, i64,
+                                          i64, vp, vp, vp, vp, vp, vp, i64, i64, vp]
+        L.fwbf_scorer_grad.argtypes = [vp, i64, C.POINTER(LearnedParams), vp, C.c_float, vp, vp, vp,
+                                       i64, vp]
+        L.fwbf_adam.argtypes = [vp, vp, vp, vp, i32, i32, C.c_float, C.c_float, C.c_float, C.c_float,
+                                vp]
         _lib = L
     return _lib
 
@@ -263,3 +280,56 @@ def count(N: int, z, pool, f0: int, iters, ok, max_iter: int):
     c = counters.cpu().numpy()
     return dict(bit_err=int(c[0]), frame_err=int(c[1]), undetected=int(c[2]),
                 iter_sum=int(c[3]), frames=int(c[4]), syn_ok=int(c[5]), hist=c[6:])
+
+
+# ---- learned scorer -------------------------------------------------------
+
+def scorer_size(rounds: int) -> int:
+    return _check_nonneg(lib().fwbf_scorer_size(rounds))
+
+
+def decode_learned_into(code: Code, y, plain: DecodeParams, lp: LearnedParams, scorer, z, iters, ok,
+                        learned_ok=None, records=None, pool=None, f0: int = 0):
+    """Learned pass then plain FWBF for the frames it leaves undecoded."""
+    p = plain.c()
+    F = y.shape[0]
+    _check(lib().fwbf_decode_learned(code._h, C.byref(p), C.byref(lp), _ptr(scorer), _ptr(y), F,
+                                     y.stride(0), _ptr(z), _ptr(iters), _ptr(ok), _ptr(learned_ok),
+                                     _ptr(records), _ptr(pool),
+                                     0 if pool is None else pool.shape[0], f0, _stream()))
+
+
+def decode_learned(code: Code, y, plain: DecodeParams, lp: LearnedParams, scorer, records=None,
+                   pool=None, f0: int = 0):
+    torch = _torch()
+    F = y.shape[0]
+    dev = y.device
+    z = torch.empty((F, (code.N + 31) // 32), dtype=torch.int32, device=dev)
+    it = torch.empty(F, dtype=torch.int32, device=dev)
+    ok = torch.empty(F, dtype=torch.uint8, device=dev)
+    lok = torch.empty(F, dtype=torch.uint8, device=dev)
+    decode_learned_into(code, y, plain, lp, scorer, z, it, ok, lok, records, pool, f0)
+    return z, it, ok, lok
+
+
+def record_buffer(F: int, rounds: int, device="cuda"):
+    """Device buffer for F * rounds * 32 records (8 bytes each)."""
+    torch = _torch()
+    return torch.empty((F, rounds, 32, 8), dtype=torch.uint8, device=device)
+
+
+def scorer_grad(records, n_tiles: int, lp: LearnedParams, scorer, pos_weight: float, out=None,
+                scores=None, workspace=None):
+    torch = _torch()
+    P = scorer_size(lp.rounds)
+    if workspace is None and out is not None:
+        workspace = torch.empty(1024 * (P + 2), dtype=torch.float32, device=scorer.device)
+    _check(lib().fwbf_scorer_grad(_ptr(records), n_tiles, C.byref(lp), _ptr(scorer), pos_weight,
+                                  _ptr(out), _ptr(scores), _ptr(workspace),
+                                  0 if workspace is None else workspace.numel(), _stream()))
+    return out, scores
+
+
+def adam(params, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(lib().fwbf_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), params.numel(), step, lr,
+                           beta1, beta2, eps, _stream()))
