@@ -479,7 +479,10 @@ __global__ __launch_bounds__(64) void grad_kernel(GradArgs g)
         const int t = (int)(tile % g.T);
         const fwbf_record r = g.rec[tile * 32 + j];
         const bool valid = r.valid != 0;
-        if (!__ballot(valid)) continue;
+        if (!__ballot(valid)) {  // empty tile
+            if (g.scores && hi == 0) g.scores[tile * 32 + j] = 0.0f;
+            continue;
+        }
         const float al = g.params[O_AL + t], be = g.params[O_AL + g.T + t];
         bf16x4 x = pack4(0.f, 0.f, 0.f, 0.f);
         if (hi == 0 && valid) x = record_features(r, t, g, al, be);
@@ -568,6 +571,7 @@ __global__ __launch_bounds__(64) void grad_kernel(GradArgs g)
         }
         __syncthreads();
     }
+    if (!g.backward) return;  // forward only: no partials (g.partial may be null)
     // write this workgroup's partial gradient
     float *out = g.partial + (size_t)blockIdx.x * (g.P + 2);
     if (hi == 0) {
