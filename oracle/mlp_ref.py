@@ -124,8 +124,10 @@ def backward(x, label, t_idx, a, S, A, params, T, pos_weight, round_bf16=True):
     W1, b1, W2, b2, W3, b3, al, be = unpack_params(params, T)
     s, c = forward(x, params, T)
     R = len(s)
-    sig = 1.0 / (1.0 + np.exp(-s))
-    ds = (pos_weight * label * (sig - 1.0) + (1 - label) * sig) / R
+    # per-record derivative of the unnormalised sum; the mean's 1/R is
+    # applied to the finished sums (after the bfloat16 rounding points), and
+    # sigma(s) - 1 = -sigma(-s) is written without cancellation
+    ds = -pos_weight * label / (1.0 + np.exp(s)) + (1 - label) / (1.0 + np.exp(-s))
     dW3 = c["h2"].T @ ds
     db3 = ds.sum()
     dpre2 = np.outer(ds, W3) * (c["pre2"] > 0)
@@ -143,7 +145,7 @@ def backward(x, label, t_idx, a, S, A, params, T, pos_weight, round_bf16=True):
     dbe = np.zeros(T)
     np.add.at(dal, t_idx, dx1 * (-np.asarray(a, np.float64) / A))
     np.add.at(dbe, t_idx, dx1 * (np.asarray(S, np.float64) / A))
-    return np.concatenate([dW1.ravel(), db1, dW2.ravel(), db2, dW3, [db3], dal, dbe])
+    return np.concatenate([dW1.ravel(), db1, dW2.ravel(), db2, dW3, [db3], dal, dbe]) / R
 
 
 def loss_of_params(params, a, S, u, t_idx, label, A, dv, T, pos_weight):
@@ -171,8 +173,7 @@ def exact_backward(params, a, S, u, t_idx, label, A, dv, T, pos_weight):
     h2 = np.maximum(pre2, 0)
     s = h2 @ W3 + b3
     R = len(s)
-    sig = 1.0 / (1.0 + np.exp(-s))
-    ds = (pos_weight * label * (sig - 1.0) + (1 - label) * sig) / R
+    ds = (-pos_weight * label / (1.0 + np.exp(s)) + (1 - label) / (1.0 + np.exp(-s))) / R
     dW3 = h2.T @ ds
     db3 = ds.sum()
     dpre2 = np.outer(ds, W3) * (pre2 > 0)

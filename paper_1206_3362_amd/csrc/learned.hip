@@ -491,12 +491,13 @@ __global__ __launch_bounds__(64) void grad_kernel(GradArgs g)
         if (g.scores && hi == 0) g.scores[tile * 32 + j] = valid ? s : 0.0f;
         if (!g.backward) continue;
         // d loss / d score (weighted binary cross-entropy with logits)
+        // sigma(s) - 1 = -sigma(-s): both terms without cancellation
         const float y = (float)r.label;
-        const float sig = 1.0f / (1.0f + __expf(-s));
-        const float ds = valid ? (g.pos_weight * y * (sig - 1.0f) + (1.0f - y) * sig) : 0.0f;
+        const float sig = 1.0f / (1.0f + expf(-s)), sign = 1.0f / (1.0f + expf(s));
+        const float ds = valid ? (-g.pos_weight * y * sign + (1.0f - y) * sig) : 0.0f;
         if (hi == 0 && valid) {
-            aLoss += g.pos_weight * y * log1pf(__expf(-fabsf(s))) + g.pos_weight * y * fmaxf(-s, 0.0f) +
-                     (1.0f - y) * (log1pf(__expf(-fabsf(s))) + fmaxf(s, 0.0f));
+            const float l1p = log1pf(expf(-fabsf(s)));
+            aLoss += g.pos_weight * y * (l1p + fmaxf(-s, 0.0f)) + (1.0f - y) * (l1p + fmaxf(s, 0.0f));
             aCnt += 1.0f;
             aB3 += ds;
         }
