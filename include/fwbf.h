@@ -148,6 +148,29 @@ int fwbf_decode(const fwbf_code *code, const fwbf_params *params, const void *y_
                 int64_t y_stride, uint32_t *z_dev, int32_t *iters_dev, uint8_t *ok_dev,
                 void *stream);
 
+/* One decode job of a mixed-code batch (buffers as for fwbf_decode). */
+typedef struct {
+    const fwbf_code *code;
+    const fwbf_params *params; /* all items share params->dtype */
+    const void *y_dev;
+    int64_t F, y_stride;
+    uint32_t *z_dev;
+    int32_t *iters_dev;
+    uint8_t *ok_dev;
+} fwbf_batch_item;
+
+/* Decodes the frames of up to 8 items (each with its own code and
+ * parameters) in one persistent launch: workgroups claim frames one at a
+ * time from a ticket counter in workspace_dev (>= 256 bytes of device
+ * memory, owned by the caller, reset by the call), so frames that finish
+ * early free their workgroup for the next unclaimed frame of any item.
+ * Results are those of fwbf_decode on each item (the general kernel).
+ * threads_per_frame: 0 = automatic (the largest code decides), else 64..1024;
+ * blocks_per_cu: 0 = as many as fit, else an upper bound.  Concurrent calls
+ * must use distinct workspaces. */
+int fwbf_decode_batched(const fwbf_batch_item *items, int n_items, int threads_per_frame, int blocks_per_cu,
+                        void *workspace_dev, size_t workspace_bytes, void *stream);
+
 /* ---- error accounting (Section V) --------------------------------------- */
 
 /* Adds, for frames f0 .. f0+F-1 against pool row (f % pool_n) (pool NULL:
@@ -159,6 +182,26 @@ int fwbf_decode(const fwbf_code *code, const fwbf_params *params, const void *y_
 int fwbf_count(int N, int64_t F, int64_t f0, const uint32_t *z_dev, const uint32_t *pool_dev,
                int64_t pool_n, const int32_t *iters_dev, const uint8_t *ok_dev, int max_iter,
                int64_t *counters_dev, void *stream);
+
+/* ---- Eb/N0 sweep in one HIP graph ---------------------------------------- */
+
+typedef struct fwbf_sweep fwbf_sweep;
+
+/* Records, for each of n_points noise levels sigma_host[i], frame generation
+ * (fwbf_channel with stream_id i, frames 0 .. frames_per_point-1) ->
+ * fwbf_decode -> fwbf_count into one HIP graph, instantiated for the
+ * current device.  The sweep owns its frame, output and counter buffers
+ * (counters cleared by a kernel at the start of every replay, never by a
+ * memset node).  pool_dev must stay valid while the sweep is used. */
+int fwbf_sweep_create(const fwbf_code *code, const fwbf_params *params, const float *sigma_host, int n_points,
+                      int64_t frames_per_point, const uint32_t *pool_dev, int64_t pool_n, uint64_t seed,
+                      float scale, fwbf_sweep **out);
+/* Replays the whole sweep on `stream` (one graph launch). */
+int fwbf_sweep_launch(fwbf_sweep *sweep, void *stream);
+/* Copies the counters (n_points x (max_iter + 7) int64, layout of
+ * fwbf_count) to host memory after the work queued on `stream`; waits. */
+int fwbf_sweep_counters(fwbf_sweep *sweep, int64_t *counters_host, void *stream);
+void fwbf_sweep_free(fwbf_sweep *sweep);
 
 /* ---- learned flip scorer (extension; keeps the per-block choice) -------- */
 

@@ -562,6 +562,77 @@ __global__ __launch_bounds__(T) void decode_kernel(DecodeArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// Mixed-code persistent launch: frames of up to 8 decode jobs (each its own
+// code, parameters and buffers) are claimed one at a time from a global
+// ticket counter, so a workgroup whose frame ends early takes the next
+// unclaimed frame of any job.  Job descriptors travel as kernel arguments.
+// ---------------------------------------------------------------------------
+constexpr int MAX_JOBS = 8;
+
+struct BatchArgs {
+    DecodeArgs job[MAX_JOBS];
+    int64_t base[MAX_JOBS + 1];  // first ticket of each job; base[njobs] = total
+    int njobs;
+    unsigned long long *counter;
+};
+static_assert(sizeof(BatchArgs) <= 4096, "batch descriptors must fit the kernel argument segment");
+
+__device__ __forceinline__ Lds lds_of(unsigned char *smem, const DecodeArgs &a)
+{
+    Lds s;
+    s.keys = (uint32_t *)(smem + a.o_keys);
+    s.chk = smem + a.o_chk;
+    s.chkp = smem + a.o_chkp;
+    s.mag = smem + a.o_mag;
+    s.zw = (uint32_t *)(smem + a.o_z);
+    s.syn = (uint32_t *)(smem + a.o_syn);
+    s.tog = (uint32_t *)(smem + a.o_tog);
+    s.win = (uint32_t *)(smem + a.o_win);
+    s.prv = (uint32_t *)(smem + a.o_prv);
+    s.tl = (uint32_t *)(smem + a.o_tl);
+    s.gb = (unsigned long long *)(smem + a.o_gb);
+    s.topk = (unsigned long long *)(smem + a.o_top);
+    s.topn = (uint32_t *)(smem + a.o_top + 8 * a.lambda);
+    s.ctl = (int *)(smem + a.o_ctl);
+    s.col = (uint32_t *)(smem + a.o_col);
+    s.row = (uint32_t *)(smem + a.o_row);
+    s.cdeg = smem + a.o_cdeg;
+    s.rdeg = smem + a.o_rdeg;
+    s.yrow = nullptr;
+    return s;
+}
+
+template <int DT, bool KEY32, int T>
+__global__ __launch_bounds__(T) void batched_kernel(BatchArgs b)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ long long s_ticket;
+    int cur = -1;
+    for (;;) {
+        if (threadIdx.x == 0) s_ticket = (long long)atomicAdd(b.counter, 1ull);
+        __syncthreads();
+        const long long tk = s_ticket;
+        __syncthreads();  // every thread has read the ticket before it is overwritten
+        if (tk >= b.base[b.njobs]) break;
+        int j = 0;
+        while (j + 1 < b.njobs && b.base[j + 1] <= tk) j++;
+        const DecodeArgs &a = b.job[j];
+        Lds s = lds_of(smem, a);
+        if (j != cur) {
+            for (int t = threadIdx.x; t < a.nb * a.dvmax; t += T) s.col[t] = a.col[t];
+            for (int t = threadIdx.x; t < a.mb * a.dcmax; t += T) s.row[t] = a.row[t];
+            for (int t = threadIdx.x; t < a.nb; t += T) s.cdeg[t] = a.coldeg[t];
+            for (int t = threadIdx.x; t < a.mb; t += T) s.rdeg[t] = a.rowdeg[t];
+            __syncthreads();
+            cur = j;
+        }
+        decode_frame<DT, KEY32, T>(a, s, tk - b.base[j]);
+    }
+}
+
+__global__ void reset_counter(unsigned long long *c) { *c = 0ull; }
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 void magic(uint32_t d, uint32_t *mag, uint32_t *mask)
@@ -657,12 +728,12 @@ int occupancy(int DT, bool key32, int T, int lds, int *blocks)
 
 // Validates parameters and fills the kernel arguments (everything but the
 // data pointers).  Shared by the plain decoder and the batched launch.
-int prepare_decode(const fwbf_code *c, const fwbf_params *p, DecodeArgs *out, int *T_out);
+int prepare_decode(const fwbf_code *c, const fwbf_params *p, DecodeArgs *out, int *T_out, bool force_key64 = false);
 int try_fast_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int64_t F, int64_t stride,
                     uint32_t *z, int32_t *iters, uint8_t *ok, hipStream_t st, const uint32_t *shift_dev,
                     const uint8_t *skip, int iters_add);
 
-int prepare_decode(const fwbf_code *c, const fwbf_params *p, DecodeArgs *out, int *T_out)
+int prepare_decode(const fwbf_code *c, const fwbf_params *p, DecodeArgs *out, int *T_out, bool force_key64)
 {
     if (!c || !p) return fail(FWBF_E_INVALID, "null code or params");
     if (p->dtype < FWBF_F32 || p->dtype > FWBF_I16) return fail(FWBF_E_INVALID, "unknown dtype");
@@ -719,7 +790,7 @@ int prepare_decode(const fwbf_code *c, const fwbf_params *p, DecodeArgs *out, in
         a.bias = 1u << (vb - 1);
         a.zero_val = a.bias;
         a.idxb = ilog2((uint32_t)a.Lc);
-        if (vb + a.idxb <= 32) key32 = true;
+        if (vb + a.idxb <= 32 && !force_key64) key32 = true;
         a.idxmask = key32 ? (a.idxb ? ((1u << a.idxb) - 1) : 0) : 0;
     }
     magic(a.Z, &a.magZ, &a.maskZ);
@@ -801,4 +872,119 @@ extern "C" int fwbf_decode(const fwbf_code *code, const fwbf_params *params, con
     if (blocks < 1) return fail(FWBF_E_UNSUPPORTED, "decode kernel does not fit on a compute unit");
     const int64_t grid = std::min<int64_t>(F, (int64_t)blocks * cus);
     return dispatch(params->dtype, key32, T, a, (int)grid, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// mixed-code batch
+// ---------------------------------------------------------------------------
+namespace fwbf {
+namespace {
+template <int DT>
+hipError_t launch_batched(int T, const BatchArgs &b, int lds, int grid, hipStream_t st)
+{
+    switch (T) {
+#define FWBF_CASE(TT)                                                                                \
+    case TT:                                                                                         \
+        if (lds > 65536)                                                                             \
+            (void)hipFuncSetAttribute((const void *)batched_kernel<DT, false, TT>,                   \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);              \
+        hipLaunchKernelGGL((batched_kernel<DT, false, TT>), dim3(grid), dim3(TT), lds, st, b);       \
+        return hipGetLastError();
+        FWBF_CASE(64)
+        FWBF_CASE(128)
+        FWBF_CASE(256)
+        FWBF_CASE(512)
+        FWBF_CASE(1024)
+#undef FWBF_CASE
+    }
+    return hipErrorInvalidValue;
+}
+template <int DT>
+hipError_t occupancy_batched(int T, int lds, int *blocks)
+{
+    switch (T) {
+#define FWBF_CASE(TT)                                                                                \
+    case TT:                                                                                         \
+        if (lds > 65536)                                                                             \
+            (void)hipFuncSetAttribute((const void *)batched_kernel<DT, false, TT>,                   \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);              \
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, batched_kernel<DT, false, TT>, TT, lds);
+        FWBF_CASE(64)
+        FWBF_CASE(128)
+        FWBF_CASE(256)
+        FWBF_CASE(512)
+        FWBF_CASE(1024)
+#undef FWBF_CASE
+    }
+    return hipErrorInvalidValue;
+}
+}  // namespace
+}  // namespace fwbf
+
+extern "C" int fwbf_decode_batched(const fwbf_batch_item *items, int n_items, int threads_per_frame,
+                                   int blocks_per_cu, void *workspace_dev, size_t workspace_bytes, void *stream)
+{
+    if (!items || n_items < 1 || n_items > MAX_JOBS)
+        return fail(FWBF_E_INVALID, "n_items must be in [1, 8]");
+    if (!workspace_dev || workspace_bytes < 256) return fail(FWBF_E_INVALID, "workspace must hold 256 bytes");
+    if (blocks_per_cu < 0) return fail(FWBF_E_INVALID, "blocks_per_cu must be >= 0");
+    const int dtype = items[0].params ? items[0].params->dtype : -1;
+    int T = threads_per_frame;
+    for (int i = 0; i < n_items; i++) {
+        const fwbf_batch_item &it = items[i];
+        if (!it.code || !it.params) return fail(FWBF_E_INVALID, "null code or params in a batch item");
+        if (it.params->dtype != dtype) return fail(FWBF_E_UNSUPPORTED, "all batch items must share the dtype");
+        if (it.F < 0 || it.y_stride < it.code->N) return fail(FWBF_E_INVALID, "invalid size in a batch item");
+        if (it.F > 0 && (!it.y_dev || !it.z_dev || !it.iters_dev || !it.ok_dev))
+            return fail(FWBF_E_INVALID, "null buffer in a batch item");
+        if (threads_per_frame == 0) {
+            const int N = it.code->N;
+            const int t = N <= 2048 ? 64 : N <= 4096 ? 128 : N <= 16384 ? 256 : 1024;
+            T = std::max(T, t);
+        }
+    }
+    BatchArgs b;
+    memset(&b, 0, sizeof b);
+    b.njobs = n_items;
+    int lds = 0;
+    int64_t total = 0;
+    for (int i = 0; i < n_items; i++) {
+        const fwbf_batch_item &it = items[i];
+        fwbf_params p = *it.params;
+        p.threads_per_frame = T;
+        int Ti = 0;
+        const int k = prepare_decode(it.code, &p, &b.job[i], &Ti, true);
+        if (k < 0) return k;
+        DeviceTables tb;
+        const int rc = device_tables(const_cast<fwbf_code *>(it.code), &tb);
+        if (rc) return rc;
+        DecodeArgs &a = b.job[i];
+        a.y = it.y_dev; a.F = it.F; a.stride = it.y_stride;
+        a.z = it.z_dev; a.iters = it.iters_dev; a.ok = it.ok_dev;
+        a.col = tb.col; a.row = tb.row; a.coldeg = tb.coldeg; a.rowdeg = tb.rowdeg;
+        b.base[i] = total;
+        total += it.F;
+        lds = std::max(lds, a.lds_bytes);
+    }
+    b.base[n_items] = total;
+    if (total == 0) return FWBF_OK;
+    b.counter = (unsigned long long *)workspace_dev;
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0, cus = 0, blocks = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = dtype == FWBF_F32 ? occupancy_batched<FWBF_F32>(T, lds, &blocks)
+                             : dtype == FWBF_I8 ? occupancy_batched<FWBF_I8>(T, lds, &blocks)
+                                                : occupancy_batched<FWBF_I16>(T, lds, &blocks);
+    if (e != hipSuccess) return hip_fail(e, "batched occupancy");
+    if (blocks < 1) return fail(FWBF_E_UNSUPPORTED, "batched kernel does not fit on a compute unit");
+    if (blocks_per_cu > 0) blocks = std::min(blocks, blocks_per_cu);
+    const int64_t grid = std::min<int64_t>(total, (int64_t)blocks * cus);
+    hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, st, b.counter);
+    e = hipGetLastError();
+    if (e == hipSuccess)
+        e = dtype == FWBF_F32 ? launch_batched<FWBF_F32>(T, b, lds, (int)grid, st)
+            : dtype == FWBF_I8 ? launch_batched<FWBF_I8>(T, b, lds, (int)grid, st)
+                               : launch_batched<FWBF_I16>(T, b, lds, (int)grid, st);
+    return e == hipSuccess ? FWBF_OK : hip_fail(e, "batched decode launch");
 }

@@ -33,6 +33,8 @@ EXPORTS = [
     "fwbf_code_shifts", "fwbf_code_has_4cycle", "fwbf_code_free", "fwbf_code_info_positions",
     "fwbf_encode", "fwbf_channel", "fwbf_decode", "fwbf_count", "fwbf_last_error", "fwbf_version",
     "fwbf_scorer_size", "fwbf_decode_learned", "fwbf_scorer_grad", "fwbf_adam",
+    "fwbf_decode_batched", "fwbf_sweep_create", "fwbf_sweep_launch", "fwbf_sweep_counters",
+    "fwbf_sweep_free",
 ]
 
 
@@ -47,6 +49,12 @@ class Params(C.Structure):
                 ("groups", C.c_int32), ("lambda_", C.c_int32), ("max_iter", C.c_int32),
                 ("alpha", C.c_float), ("alpha_num", C.c_int32), ("alpha_den", C.c_int32),
                 ("threads_per_frame", C.c_int32), ("flags", C.c_uint32)]
+
+
+class BatchItem(C.Structure):
+    _fields_ = [("code", C.c_void_p), ("params", C.c_void_p), ("y_dev", C.c_void_p),
+                ("F", C.c_int64), ("y_stride", C.c_int64), ("z_dev", C.c_void_p),
+                ("iters_dev", C.c_void_p), ("ok_dev", C.c_void_p)]
 
 
 class LearnedParams(C.Structure):
@@ -92,6 +100,13 @@ def lib():
                                        i64, vp]
         L.fwbf_adam.argtypes = [vp, vp, vp, vp, i32, i32, C.c_float, C.c_float, C.c_float, C.c_float,
                                 vp]
+        L.fwbf_decode_batched.argtypes = [vp, i32, i32, i32, vp, C.c_size_t, vp]
+        L.fwbf_sweep_create.argtypes = [vp, C.POINTER(Params), vp, i32, i64, vp, i64, u64, C.c_float,
+                                        C.POINTER(vp)]
+        L.fwbf_sweep_launch.argtypes = [vp, vp]
+        L.fwbf_sweep_counters.argtypes = [vp, vp, vp]
+        L.fwbf_sweep_free.argtypes = [vp]
+        L.fwbf_sweep_free.restype = None
         _lib = L
     return _lib
 
@@ -333,3 +348,60 @@ def scorer_grad(records, n_tiles: int, lp: LearnedParams, scorer, pos_weight: fl
 def adam(params, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
     _check(lib().fwbf_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), params.numel(), step, lr,
                            beta1, beta2, eps, _stream()))
+
+
+# ---- mixed-code batch, graph sweep -----------------------------------------
+
+def decode_batched(jobs, threads_per_frame: int = 0, blocks_per_cu: int = 0, workspace=None):
+    """jobs: list of (code, y, DecodeParams); returns [(z, iters, ok)] per job.
+    One persistent launch claims frames of all jobs from a shared queue."""
+    torch = _torch()
+    keep, items, outs = [], [], []
+    for code, y, params in jobs:
+        F = y.shape[0]
+        z = torch.empty((F, (code.N + 31) // 32), dtype=torch.int32, device=y.device)
+        it = torch.empty(F, dtype=torch.int32, device=y.device)
+        ok = torch.empty(F, dtype=torch.uint8, device=y.device)
+        pc = params.c()
+        keep.append(pc)
+        items.append(BatchItem(code._h.value, C.addressof(pc), y.data_ptr(), F, y.stride(0),
+                               z.data_ptr(), it.data_ptr(), ok.data_ptr()))
+        outs.append((z, it, ok))
+    arr = (BatchItem * len(items))(*items)
+    if workspace is None:
+        workspace = torch.zeros(64, dtype=torch.int32, device=jobs[0][1].device)
+    _check(lib().fwbf_decode_batched(arr, len(items), threads_per_frame, blocks_per_cu,
+                                     _ptr(workspace), workspace.numel() * 4, _stream()))
+    return outs
+
+
+class Sweep:
+    """channel -> decode -> count for several noise levels, one HIP graph."""
+
+    def __init__(self, code: Code, params: DecodeParams, sigmas, frames_per_point: int, pool=None,
+                 seed: int = 1, scale: float = 1.0):
+        self.code, self.params = code, params
+        self.n_points = len(sigmas)
+        self._p = params.c()
+        sig = np.ascontiguousarray(sigmas, np.float32)
+        h = C.c_void_p()
+        self._pool = pool
+        _check(lib().fwbf_sweep_create(code._h, C.byref(self._p), _np_ptr(sig), self.n_points,
+                                       frames_per_point, _ptr(pool),
+                                       0 if pool is None else pool.shape[0], seed, scale,
+                                       C.byref(h)))
+        self._h = h
+
+    def launch(self):
+        _check(lib().fwbf_sweep_launch(self._h, _stream()))
+
+    def counters(self):
+        out = np.zeros((self.n_points, 7 + self.params.max_iter), np.int64)
+        _check(lib().fwbf_sweep_counters(self._h, _np_ptr(out), _stream()))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.fwbf_sweep_free(h)
+            self._h = None

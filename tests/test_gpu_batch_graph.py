@@ -1,0 +1,111 @@
+"""Mixed-code persistent launch, HIP-graph Eb/N0 sweep and autotuner.
+
+The batched launch must reproduce, frame for frame, what fwbf_decode gives on
+each code alone (and the oracle on a sample); every replay of the captured
+sweep must equal the same work launched eagerly (replays interleaved with
+eager work); the autotuner's choice must satisfy its frame-error
+constraint."""
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_util import assert_same, need_gpu, torch
+from paper_1206_3362_amd import autotune, fwbf, synth
+
+pytestmark = pytest.mark.gpu
+
+CODES = [((3, 6, 168, 2), 2048, 8), ((3, 6, 672, 3), 512, 32), ((4, 20, 400, 4), 256, 64)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _frames(code, F, seed, dtype, scale):
+    pool = torch.from_numpy(code.encode(seed, 0, 64).view(np.int32)).cuda()
+    eb = synth.uniform_frames(code.N, F, seed, 3.0, 6.0)
+    sig = torch.from_numpy(synth.sigma_for(eb, code.rate).astype(np.float32)).cuda()
+    return fwbf.channel(code.N, F, 0, pool, seed, 2, 0.0, dtype=dtype, scale=scale, sigma_per_frame=sig)
+
+
+@pytest.mark.parametrize("T", [0, 256])
+def test_mixed_code_batch_equals_per_code_decoding(T):
+    jobs, codes = [], []
+    for i, (spec, F, G) in enumerate(CODES):
+        code = fwbf.Code.from_seed(*spec)
+        y = _frames(code, F, 10 + i, torch.float32, 1.0)
+        jobs.append((code, y, fwbf.DecodeParams(dtype=fwbf.F32, groups=G, max_iter=100)))
+        codes.append(spec)
+    outs = fwbf.decode_batched(jobs, threads_per_frame=T)
+    torch.cuda.synchronize()
+    for (code, y, p), (z, it, ok), spec in zip(jobs, outs, codes):
+        print(f"batch item N={code.N} F={y.shape[0]}", flush=True)
+        zr, itr, okr = fwbf.decode(code, y, p)
+        torch.cuda.synchronize()
+        assert_same((z.cpu().numpy(), it.cpu().numpy(), ok.cpu().numpy()),
+                    (zr.cpu().numpy(), itr.cpu().numpy(), okr.cpu().numpy()), f"batch N={code.N}")
+        o = O.Code.from_seed(*spec)
+        yh = y[:32].cpu().numpy()
+        zo, ito, oko = O.decode(o, yh, G=p.groups, max_iter=100, alpha=0.2)
+        assert_same((z[:32].cpu().numpy().view(np.uint32), it[:32].cpu().numpy(), ok[:32].cpu().numpy()),
+                    (zo, ito, oko), f"oracle N={code.N}")
+
+
+def test_int8_batch_equals_fast_kernel():
+    jobs = []
+    for i, (spec, F, G) in enumerate([((3, 6, 31, 1), 700, 6), ((3, 6, 168, 2), 1500, 8)]):
+        code = fwbf.Code.from_seed(*spec)
+        y = _frames(code, F, 20 + i, torch.int8, 16.0)
+        jobs.append((code, y, fwbf.DecodeParams(dtype=fwbf.I8, groups=G, max_iter=80)))
+    outs = fwbf.decode_batched(jobs, blocks_per_cu=4)
+    for (code, y, p), (z, it, ok) in zip(jobs, outs):
+        zr, itr, okr = fwbf.decode(code, y, p)
+        torch.cuda.synchronize()
+        assert_same((z.cpu().numpy(), it.cpu().numpy(), ok.cpu().numpy()),
+                    (zr.cpu().numpy(), itr.cpu().numpy(), okr.cpu().numpy()), f"int8 batch N={code.N}")
+
+
+def test_graph_sweep_replays_equal_eager_launches():
+    code = fwbf.Code.from_seed(3, 6, 168, 2)
+    pool = torch.from_numpy(code.encode(3, 0, 128).view(np.int32)).cuda()
+    sig = synth.sigma_for(np.array([3.0, 4.0, 5.0, 6.0]), code.rate).astype(np.float32)
+    p = fwbf.DecodeParams(dtype=fwbf.I8, groups=8, max_iter=100)
+    F = 8192
+    sw = fwbf.Sweep(code, p, sig, F, pool=pool, seed=77, scale=16.0)
+    # the same work, launched eagerly
+    eager = []
+    for i, s in enumerate(sig):
+        y = fwbf.channel(code.N, F, 0, pool, 77, i, float(s), dtype=torch.int8, scale=16.0)
+        z, it, ok = fwbf.decode(code, y, p)
+        r = fwbf.count(code.N, z, pool, 0, it, ok, 100)
+        eager.append([r["bit_err"], r["frame_err"], r["undetected"], r["iter_sum"], r["frames"],
+                      r["syn_ok"]] + list(r["hist"]))
+    eager = np.array(eager)
+    for rep in range(3):
+        sw.launch()
+        c = sw.counters()
+        assert np.array_equal(c, eager), f"replay {rep}"
+        # unrelated eager work between replays
+        y = fwbf.channel(code.N, 1024, 5, pool, 9, 9, 0.7, dtype=torch.int8, scale=16.0)
+        fwbf.decode(code, y, p)
+        torch.cuda.synchronize()
+    assert eager[:, 1].tolist() == sorted(eager[:, 1].tolist(), reverse=True)  # FER falls with Eb/N0
+
+
+def test_autotuner_respects_fer_constraint(tmp_path):
+    code = fwbf.Code.from_seed(3, 6, 168, 2)
+    cache = str(tmp_path / "tune.json")
+    r = autotune.tune(code, 6.0, G_ref=8, Gs=(8, 16, 32), shapes=((0, 0), (128, 0)), frames=8192,
+                      cache=cache)
+    assert r["admissible"]
+    n = 8192
+    for row in r["table"]:
+        assert row["admissible"] == autotune.fer_admissible(round(row["fer"] * n), n,
+                                                            round(r["fer_ref"] * n), n)
+        if row["admissible"]:
+            assert row["gbps"] <= r["gbps"] + 1e-9
+    # cached
+    r2 = autotune.tune(code, 6.0, G_ref=8, Gs=(8, 16, 32), shapes=((0, 0), (128, 0)), frames=8192,
+                       cache=cache)
+    assert r2 == r
