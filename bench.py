@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")
     ap.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "traffic_decode_n1008_i8_4db.json"))
+    ap.add_argument("--learned", type=int, default=1, help="also time the learned decoder (1/0)")
+    ap.add_argument("--scorer", type=str,
+                    default=os.path.join(ROOT, "paper_1206_3362_amd", "scorer_n1008_g32_t16.npz"))
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (scales the HBM counters)")
     return ap.parse_args()
@@ -160,9 +163,53 @@ def main():
                      "bytes_per_frame": bytes_per_frame},
         "wall_s": round(wall, 3),
     }
+    if a.learned:
+        out["learned"] = learned_leg(code, ys, pool, params, a, N, F, ms_step, c)
     if a.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(code, ys[0], params, a, N)
     print(json.dumps(out), flush=True)
+
+
+def learned_leg(code, ys, pool, params, a, N, F, plain_ms, plain_counts):
+    """The learned decoder (checkpointed scorer, plain FWBF fallback) on the
+    same resident batches, same timing protocol."""
+    import numpy as np
+    import torch
+
+    from paper_1206_3362_amd import fwbf
+    d = np.load(a.scorer, allow_pickle=False)
+    cfg = dict((k, v) for k, v in d["config"])
+    lp = fwbf.LearnedParams(int(cfg["rounds"]), int(cfg["groups"]), int(cfg["topk"]), 16.0)
+    sc = torch.from_numpy(d["params"]).cuda()
+    z = torch.empty((F, (N + 31) // 32), dtype=torch.int32, device="cuda")
+    it = torch.empty(F, dtype=torch.int32, device="cuda")
+    ok = torch.empty(F, dtype=torch.uint8, device="cuda")
+    lok = torch.empty(F, dtype=torch.uint8, device="cuda")
+    counters = torch.zeros(7 + a.max_iter + lp.rounds, dtype=torch.int64, device="cuda")
+    for s in range(a.warmup):
+        fwbf.decode_learned_into(code, ys[s % a.batches], params, lp, sc, z, it, ok, lok)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for s in range(a.steps):
+        b = s % a.batches
+        fwbf.decode_learned_into(code, ys[b], params, lp, sc, z, it, ok, lok)
+        fwbf.count_into(N, z, pool, b * F, it, ok, a.max_iter + lp.rounds, counters)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / a.steps
+    cc = counters.cpu().numpy()
+    fer = cc[1] / cc[4]
+    pfer = plain_counts[1] / plain_counts[4]
+    gbps = F * N / (ms * 1e-3) / 1e9
+    pg = F * N / (plain_ms * 1e-3) / 1e9
+    return {"value": round(gbps, 3), "unit": "Gb/s", "ms_per_step": round(ms, 4), "fer": float(fer),
+            "ber": float(cc[0] / (cc[4] * N)), "plain_fer": float(pfer),
+            "goodput_gbps": round(gbps * (1 - fer), 3), "plain_goodput_gbps": round(pg * (1 - pfer), 3),
+            "learned_pass_only": float(lok.float().mean().item()),
+            "scorer": os.path.basename(a.scorer), "rounds": lp.rounds, "groups": lp.groups,
+            "topk": lp.topk}
 
 
 def kernel_sha():
