@@ -215,7 +215,7 @@ def learned_leg(code, ys, pool, params, a, N, F, plain_ms, plain_counts):
 def kernel_sha():
     import hashlib
     h = hashlib.sha256()
-    for name in ("decode.hip", "decode_fast.hip", "frames.h"):
+    for name in ("decode_fast.hip", "frames.h"):
         with open(os.path.join(ROOT, "paper_1206_3362_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

@@ -46,7 +46,7 @@ struct FastArgs {
     int aden, anum, idxb;
     uint32_t idxmask, bias, zero_val;
     // LDS offsets in bytes
-    int o_chk, o_chkp, o_y, o_z, o_syn, o_list, o_sh, lds_bytes;
+    int o_chk, o_chkp, o_y, o_z, o_syn, o_list, o_sh, o_slot, lds_bytes;
 };
 
 __device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t mag, uint32_t mask)
@@ -122,11 +122,17 @@ __global__ __launch_bounds__(64) void fast_kernel(FastArgs a)
     uint32_t *syn = (uint32_t *)(smem + a.o_syn);
     uint32_t *list = (uint32_t *)(smem + a.o_list);
     uint32_t *sh = (uint32_t *)(smem + a.o_sh);
+    uint16_t *slotof = (uint16_t *)(smem + a.o_slot);  // slot word of every bit (frame-independent)
 
     const uint32_t lane = threadIdx.x;
     const uint32_t Z = a.Z;
     const int N = a.N, M = a.M;
     for (int t = lane; t < DV * a.nb; t += 64) sh[t] = a.shift[t];
+    for (int n = lane; n < a.N; n += 64) {
+        const uint32_t gg = fdiv(n, a.magP, a.maskP);
+        const uint32_t pp = n - gg * a.p;
+        slotof[n] = (uint16_t)slot_addr(gg * a.L + pp / C, pp & (C - 1));
+    }
 
     // lane -> block layout
     const uint32_t g = lane >> a.logL;
@@ -233,10 +239,7 @@ __global__ __launch_bounds__(64) void fast_kernel(FastArgs a)
                         int d = par ? a.aden * (int)w : -a.aden * (int)w;
                         if (i == 0) d -= a.anum * (int)av[q];
                         const uint32_t n = nn[q];
-                        const uint32_t gg = fdiv(n, a.magP, a.maskP);
-                        const uint32_t pp = n - gg * a.p;
-                        const uint32_t ln = gg * a.L + pp / C;
-                        atomicAdd(&keys[slot_addr(ln, pp & (C - 1))], (uint32_t)d << a.idxb);
+                        atomicAdd(&keys[slotof[n]], (uint32_t)d << a.idxb);
                     }
                 }
                 const unsigned long long b = __ballot(valid && par);
@@ -333,10 +336,7 @@ __global__ __launch_bounds__(64) void fast_kernel(FastArgs a)
                             w = (a.imwbf && chkp[m] == (uint32_t)q) ? (cw >> 16) : (cw & 0xFFFF);
                         }
                         const int d = (e >> 31) ? 2 * a.aden * (int)w : -2 * a.aden * (int)w;
-                        const uint32_t gg = fdiv(nq, a.magP, a.maskP);
-                        const uint32_t pp = nq - gg * a.p;
-                        const uint32_t ln = gg * a.L + pp / C;
-                        atomicAdd(&keys[slot_addr(ln, pp & (C - 1))], (uint32_t)d << a.idxb);
+                        atomicAdd(&keys[slotof[nq]], (uint32_t)d << a.idxb);
                     }
                 }
                 __syncthreads();
@@ -468,6 +468,7 @@ int try_fast_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int
     a.o_syn = take(((c->M + 63) / 64) * 8, 8);
     a.o_list = take(4 * dv * 64, 4);
     a.o_sh = take(4 * dv * c->nb, 4);
+    a.o_slot = take(2 * c->N, 4);
     a.lds_bytes = (off + 15) / 16 * 16;
     if (a.lds_bytes > 64 * 1024) return 0;
     a.y = y; a.F = F; a.stride = stride;

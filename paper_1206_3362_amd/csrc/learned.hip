@@ -32,7 +32,7 @@ namespace {
 
 constexpr int H = 32;
 constexpr uint32_t NONE = 0xFFFFFFFFu;
-constexpr int SOFF = 2048;  // offset of S in a packed slot word (S + SOFF) << 4 | u
+constexpr int SOFF = 2048;  // slot word: (S + SOFF) << 12 | |y| << 4 | u
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -84,6 +84,36 @@ __device__ void load_net(Net &n, const float *p)
         n.w3[q] = p[O_W3 + row];
     }
     n.b3 = p[O_B3];
+}
+
+// decode-side network: MFMA weight operands in registers, biases and W3 in
+// LDS (read per row), to keep the kernel's register count low
+struct NetL {
+    bf16x4 w1;
+    bf16x4 w2[4];
+    const float *b1, *b2, *w3;  // LDS copies
+    float b3;
+};
+
+__device__ __forceinline__ float net_score(const NetL &n, bf16x4 x)
+{
+    const int l = threadIdx.x & 63;
+    f32x16 acc = {};
+    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(n.w1, x, acc, 0, 0, 0);
+    bf16x4 h1[4];
+    for (int c = 0; c < 4; c++) {
+        float h[4];
+        for (int u = 0; u < 4; u++) h[u] = fmaxf(acc[4 * c + u] + n.b1[row_of(4 * c + u, l)], 0.0f);
+        h1[c] = pack4(h[0], h[1], h[2], h[3]);
+    }
+    f32x16 acc2 = {};
+    for (int c = 0; c < 4; c++) acc2 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(n.w2[c], h1[c], acc2, 0, 0, 0);
+    float part = 0.0f;
+    for (int q = 0; q < 16; q++) {
+        const int row = row_of(q, l);
+        part = __builtin_fmaf(n.w3[row], fmaxf(acc2[q] + n.b2[row], 0.0f), part);
+    }
+    return part + __shfl_xor(part, 32, 64) + n.b3;
 }
 
 struct Act {
@@ -167,7 +197,7 @@ struct LearnArgs {
     uint32_t magZ, maskZ, magP, maskP;
     int p, L, logL, Geff, k, T;
     float A, dv;
-    int o_chk, o_y, o_z, o_syn, o_list, o_sh, o_cand, lds_bytes;
+    int o_chk, o_y, o_z, o_syn, o_list, o_sh, o_cand, o_slot, o_net, lds_bytes;
 };
 
 __device__ __forceinline__ uint32_t slot_chunk(uint32_t lane, uint32_t kk) { return (kk << 6) + (lane ^ ((kk & 15) << 2)); }
@@ -185,13 +215,38 @@ __global__ __launch_bounds__(64) void learned_kernel(LearnArgs a)
     uint32_t *list = (uint32_t *)(smem + a.o_list);
     uint32_t *sh = (uint32_t *)(smem + a.o_sh);
     uint4 *cand = (uint4 *)(smem + a.o_cand);  // 32 proposals: n, S+SOFF, u, a
+    uint16_t *slotof = (uint16_t *)(smem + a.o_slot);  // slot word of every bit
+    float *nbias = (float *)(smem + a.o_net);               // b1[32], b2[32], W3[32]
 
     const uint32_t lane = threadIdx.x;
     const uint32_t Z = a.Z;
     const int N = a.N, M = a.M;
     for (int t = lane; t < DV * a.nb; t += 64) sh[t] = a.shift[t];
-    Net net;
-    load_net(net, a.params);
+    for (int n = lane; n < a.N; n += 64) {
+        const uint32_t gg = fdiv(n, a.magP, a.maskP);
+        const uint32_t pp = n - gg * a.p;
+        slotof[n] = (uint16_t)slot_word(gg * a.L + pp / C, pp & (C - 1));
+    }
+    for (int t = lane; t < 32; t += 64) {
+        nbias[t] = a.params[O_B1 + t];
+        nbias[32 + t] = a.params[O_B2 + t];
+        nbias[64 + t] = a.params[O_W3 + t];
+    }
+    NetL net;
+    {
+        const int i = lane & 31, hi = lane >> 5;
+        const float *p = a.params;
+        net.w1 = hi == 0 ? pack4(p[O_W1 + i * 4 + 0], p[O_W1 + i * 4 + 1], p[O_W1 + i * 4 + 2], p[O_W1 + i * 4 + 3])
+                         : pack4(0.f, 0.f, 0.f, 0.f);
+        for (int c = 0; c < 4; c++) {
+            const float *r = p + O_W2 + i * H + 8 * c + 4 * hi;
+            net.w2[c] = pack4(r[0], r[1], r[2], r[3]);
+        }
+        net.b1 = nbias;
+        net.b2 = nbias + 32;
+        net.w3 = nbias + 64;
+        net.b3 = p[O_B3];
+    }
 
     const uint32_t g = lane >> a.logL;
     const bool lead = ((lane & (a.L - 1)) == 0) && (int)g < a.Geff;
@@ -207,15 +262,24 @@ __global__ __launch_bounds__(64) void learned_kernel(LearnArgs a)
         for (int w = lane; w < ((M + 63) >> 6) * 2; w += 64) syn[w] = 0;
         for (int w = lane; w < ((N + 63) >> 6) * 2; w += 64) zw[w] = 0;
         for (int n = lane; n < N; n += 64) yv[n] = yrow[n];
+        __syncthreads();
+        // slot words: S = 0, u = 0 and |y| of the slot's bit
+        uint64_t realm = 0;
 #pragma unroll
         for (int kk = 0; kk < C; kk += 4) {
             uint4 v;
             uint32_t *vp = (uint32_t *)&v;
 #pragma unroll
-            for (int u = 0; u < 4; u++) vp[u] = (uint32_t)SOFF << 4;
+            for (int u = 0; u < 4; u++) {
+                const uint32_t pos = pos0 + kk + u;
+                const uint32_t n = gp + pos;
+                const bool real = (int)g < a.Geff && (int)pos < a.p && (int)n < N;
+                const int yn = real ? (int)yv[n] : 0;
+                vp[u] = ((uint32_t)SOFF << 12) | ((uint32_t)(yn < 0 ? -yn : yn) << 4);
+                realm |= (uint64_t)real << (kk + u);
+            }
             ((uint4 *)slots)[slot_chunk(lane, kk >> 2)] = v;
         }
-        __syncthreads();
         for (int n0 = 0; n0 < N; n0 += 64) {
             const int n = n0 + (int)lane;
             const unsigned long long b = __ballot(n < N && yv[n] < 0);
@@ -224,16 +288,7 @@ __global__ __launch_bounds__(64) void learned_kernel(LearnArgs a)
                 zw[(n0 >> 5) + 1] = (uint32_t)(b >> 32);
             }
         }
-        // |y| of the slots of this lane
-        float amag[C];
-#pragma unroll
-        for (int kk = 0; kk < C; kk++) {
-            const uint32_t pos = pos0 + kk;
-            const uint32_t n = gp + pos;
-            const bool real = (int)g < a.Geff && (int)pos < a.p && (int)n < N;
-            const int v = real ? (int)yv[n] : 0;
-            amag[kk] = (float)(v < 0 ? -v : v);
-        }
+        __syncthreads();
         // check minima, syndrome, initial S and u pushed from the check side
         int weight = 0;
         for (int i = 0; i < DV; i++) {
@@ -262,11 +317,9 @@ __global__ __launch_bounds__(64) void learned_kernel(LearnArgs a)
 #pragma unroll
                     for (int q = 0; q < DC; q++) {
                         const uint32_t w = (pos == (uint32_t)q) ? m2 : m1;
-                        const int d = ((par ? (int)w : -(int)w) << 4) + (int)par;
+                        const int d = ((par ? (int)w : -(int)w) << 12) + (int)par;
                         const uint32_t n = nn[q];
-                        const uint32_t gg = fdiv(n, a.magP, a.maskP);
-                        const uint32_t pp = n - gg * a.p;
-                        atomicAdd(&slots[slot_word(gg * a.L + pp / C, pp & (C - 1))], (uint32_t)d);
+                        atomicAdd(&slots[slotof[n]], (uint32_t)d);
                     }
                 }
                 const unsigned long long b = __ballot(valid && par);
@@ -283,44 +336,33 @@ __global__ __launch_bounds__(64) void learned_kernel(LearnArgs a)
             if (weight == 0) { okf = 1; break; }
             if (t == a.T) break;
             const float al = a.params[O_AL + t], be = a.params[O_AL + a.T + t];
-            // metric E_t of this lane's slots, as order-preserving keys
-            uint32_t key[C];
-#pragma unroll
-            for (int kk = 0; kk < C; kk += 4) {
-                const uint4 v = ((const uint4 *)slots)[slot_chunk(lane, kk >> 2)];
-                const uint32_t vv[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                for (int u = 0; u < 4; u++) {
-                    const uint32_t pos = pos0 + kk + u;
-                    const bool real = (int)g < a.Geff && (int)pos < a.p && (int)(gp + pos) < N;
-                    const float S = (float)((int)(vv[u] >> 4) - SOFF);
-                    const float E = __builtin_fmaf(-al, amag[kk + u], be * S);
-                    key[kk + u] = real ? orderable(E) : 0u;
-                }
-            }
-            // k best per block (ties: lower index), each excluded before the next
+            // k best per block by E_t (ties: lower index); each chosen slot is
+            // excluded before the next pass
+            uint64_t excl = 0;
             for (int rk = 0; rk < a.k; rk++) {
                 unsigned long long best = 0;
 #pragma unroll
-                for (int kk = 0; kk < C; kk++) {
-                    const unsigned long long v = ((unsigned long long)key[kk] << 32) | (0xFFFFFFFFu - (pos0 + kk));
-                    best = umax64(best, v);
+                for (int kk = 0; kk < C; kk += 4) {
+                    const uint4 v = ((const uint4 *)slots)[slot_chunk(lane, kk >> 2)];
+                    const uint32_t vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        const float S = (float)((int)(vv[u] >> 12) - SOFF);
+                        const float E = __builtin_fmaf(-al, (float)((vv[u] >> 4) & 0xFFu), be * S);
+                        const bool live = ((realm & ~excl) >> (kk + u)) & 1;
+                        const unsigned long long key = live ? (((unsigned long long)orderable(E) << 32) |
+                                                               (0xFFFFFFFFu - (pos0 + kk + u)))
+                                                            : 0ull;
+                        best = umax64(best, key);
+                    }
                 }
                 best = group_max64(best, a.L);
                 const uint32_t bpos = 0xFFFFFFFFu - (uint32_t)best;
-                // the owner of the chosen slot excludes it
-                if ((int)g < a.Geff && bpos / C == (lane & (a.L - 1))) {
-#pragma unroll
-                    for (int kk = 0; kk < C; kk++)
-                        if ((uint32_t)kk == (bpos & (C - 1))) key[kk] = 0;
-                }
+                const bool real = (best >> 32) != 0;
+                if (real && (int)g < a.Geff && bpos / C == (lane & (a.L - 1))) excl |= 1ull << (bpos & (C - 1));
                 if (lead) {
-                    const uint32_t n = gp + bpos;
-                    const bool real = (best >> 32) != 0;
-                    uint32_t word = 0;
-                    if (real) word = slots[slot_word(g * a.L + bpos / C, bpos & (C - 1))];
-                    const int yvn = real ? (int)yv[n] : 0;
-                    cand[g * a.k + rk] = make_uint4(real ? n : NONE, word >> 4, word & 15u, (uint32_t)(yvn < 0 ? -yvn : yvn));
+                    const uint32_t word = real ? slots[slot_word(g * a.L + bpos / C, bpos & (C - 1))] : 0u;
+                    cand[g * a.k + rk] = make_uint4(real ? gp + bpos : NONE, word, 0, 0);
                 }
             }
             __syncthreads();
@@ -328,19 +370,19 @@ __global__ __launch_bounds__(64) void learned_kernel(LearnArgs a)
             const uint32_t j = lane & 31;
             const uint4 cj = j < (uint32_t)NC ? cand[j] : make_uint4(NONE, 0, 0, 0);
             const bool realc = cj.x != NONE;
+            const int cS = (int)(cj.y >> 12) - SOFF;
+            const uint32_t ca = (cj.y >> 4) & 0xFFu, cu = cj.y & 15u;
             bf16x4 x = pack4(0.f, 0.f, 0.f, 0.f);
             if (lane < 32 && realc) {
-                const float S = (float)((int)cj.y - SOFF);
-                const float E = __builtin_fmaf(-al, (float)cj.w, be * S);
-                x = pack4((float)cj.w / a.A, E / a.A, (float)cj.z / a.dv, (float)t / (float)a.T);
+                const float E = __builtin_fmaf(-al, (float)ca, be * (float)cS);
+                x = pack4((float)ca / a.A, E / a.A, (float)cu / a.dv, (float)t / (float)a.T);
             }
-            Act act;
-            const float score = net_forward(net, x, act);
+            const float score = net_score(net, x);
             if (a.rec && lane < 32 && j < (uint32_t)NC) {
                 fwbf_record r;
-                r.S = (int16_t)((int)cj.y - SOFF);
-                r.a = (uint8_t)cj.w;
-                r.u = (uint8_t)cj.z;
+                r.S = (int16_t)cS;
+                r.a = (uint8_t)ca;
+                r.u = (uint8_t)cu;
                 uint32_t lab = 0;
                 if (realc) {
                     const uint32_t zb = (zw[cj.x >> 5] >> (cj.x & 31)) & 1u;
@@ -405,10 +447,8 @@ __global__ __launch_bounds__(64) void learned_kernel(LearnArgs a)
                     const uint32_t nq = q * Z + addmod(r, sh[i * a.nb + q], Z);
                     const uint32_t cwd = chk[m];
                     const uint32_t w = (((cwd >> 16) & 0xFF) == (uint32_t)q) ? ((cwd >> 8) & 0xFF) : (cwd & 0xFF);
-                    const int d = (e >> 31) ? ((2 * (int)w) << 4) + 1 : -((2 * (int)w) << 4) - 1;
-                    const uint32_t gg = fdiv(nq, a.magP, a.maskP);
-                    const uint32_t pp = nq - gg * a.p;
-                    atomicAdd(&slots[slot_word(gg * a.L + pp / C, pp & (C - 1))], (uint32_t)d);
+                    const int d = (e >> 31) ? ((2 * (int)w) << 12) + 1 : -((2 * (int)w) << 12) - 1;
+                    atomicAdd(&slots[slotof[nq]], (uint32_t)d);
                 }
             }
             __syncthreads();
@@ -709,6 +749,8 @@ extern "C" int fwbf_decode_learned(const fwbf_code *code, const fwbf_params *pla
     a.o_list = take(4 * 3 * 64, 4);
     a.o_sh = take(4 * 3 * code->nb, 4);
     a.o_cand = take(16 * 32, 16);
+    a.o_slot = take(2 * code->N, 4);
+    a.o_net = take(4 * 96, 16);
     a.lds_bytes = (off + 15) / 16 * 16;
     if (a.lds_bytes > 64 * 1024) return fail(FWBF_E_UNSUPPORTED, "frame state exceeds 64 KiB of LDS");
     DeviceTables tb;
