@@ -42,6 +42,10 @@ def parse():
     ap.add_argument("--learned", type=int, default=1, help="also time the learned decoder (1/0)")
     ap.add_argument("--scorer", type=str,
                     default=os.path.join(ROOT, "paper_1206_3362_amd", "scorer_n1008_g32_t16.npz"))
+    ap.add_argument("--workload", default="n1008_i8",
+                    choices=["n1008_i8", "n186_f32_wbf", "mixed_f32", "n32400_i16", "sweep_n1008_i8"],
+                    help="n1008_i8: the headline workload; the others are further configurations "
+                         "measured with the same protocol (one JSON line each)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (scales the HBM counters)")
     return ap.parse_args()
@@ -68,6 +72,9 @@ def main():
               "(frames are independent; see the design notes for how it would shard).",
               file=sys.stderr)
         sys.exit(2)
+    if a.workload != "n1008_i8":
+        other_workload(a)
+        return
     import numpy as np
     import torch
 
@@ -210,6 +217,101 @@ def learned_leg(code, ys, pool, params, a, N, F, plain_ms, plain_counts):
             "learned_pass_only": float(lok.float().mean().item()),
             "scorer": os.path.basename(a.scorer), "rounds": lp.rounds, "groups": lp.groups,
             "topk": lp.topk}
+
+
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(steps):
+        fn()
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps
+
+
+def other_workload(a):
+    """Further configurations: same protocol (inputs resident, warm-up, events
+    around exactly `steps` steps), one JSON line each."""
+    import numpy as np
+    import torch
+
+    from paper_1206_3362_amd import fwbf, synth
+    dev = "cuda"
+    line = {"n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "data": "synthetic", "unit": "Gb/s"}
+    if a.workload == "n186_f32_wbf":
+        code = fwbf.Code.from_seed(3, 6, 31, 1)
+        F = 1000
+        y = fwbf.channel(code.N, F, 0, None, 2024, 0, float(synth.sigma_for(3.0, code.rate)))
+        p = fwbf.DecodeParams(dtype=fwbf.F32, weights=fwbf.WBF, groups=6, max_iter=50, alpha=0.2)
+        z, it, ok = fwbf.decode(code, y, p)
+        ms = _timed(lambda: fwbf.decode_into(code, y, p, z, it, ok), a.steps, a.warmup)
+        r = fwbf.count(code.N, z, None, 0, it, ok, 50)
+        line.update(metric="decoded Gb/s, plain FWBF + WBF, N=186 (3,6) QC, 3 dB, float32, G=6",
+                    value=round(F * code.N / (ms * 1e-3) / 1e9, 4), ms_per_step=round(ms, 4),
+                    dtype="f32", fer=r["frame_err"] / F, mean_iters=r["iter_sum"] / F,
+                    config={"workload": "N=186 (3,6) QC Z=31, all-zero codeword, 3 dB, f32, WBF, "
+                                        "alpha 0.2, G=6, K_max=50, 1000 frames", "frames": F})
+    elif a.workload == "mixed_f32":
+        specs = [((3, 6, 168, 2), 1 << 18, 8), ((3, 6, 672, 3), 1 << 16, 32), ((4, 20, 400, 4), 1 << 15, 64)]
+        jobs, bits = [], 0
+        for i, (spec, F, G) in enumerate(specs):
+            code = fwbf.Code.from_seed(*spec)
+            pool = torch.from_numpy(code.encode(31 + i, 0, 256).view(np.int32)).to(dev)
+            eb = synth.uniform_frames(code.N, F, 77 + i, 3.0, 6.0)
+            sig = torch.from_numpy(synth.sigma_for(eb, code.rate).astype(np.float32)).to(dev)
+            y = fwbf.channel(code.N, F, 0, pool, 500 + i, i, 0.0, sigma_per_frame=sig)
+            jobs.append((code, y, fwbf.DecodeParams(dtype=fwbf.F32, groups=G, max_iter=100)))
+            bits += F * code.N
+        ws = torch.zeros(64, dtype=torch.int32, device=dev)
+        ms = _timed(lambda: fwbf.decode_batched(jobs, workspace=ws), a.steps, a.warmup)
+        sep = _timed(lambda: [fwbf.decode(c, y, p) for c, y, p in jobs], a.steps, a.warmup)
+        line.update(metric="decoded Gb/s, mixed-code persistent batch (float32)",
+                    value=round(bits / (ms * 1e-3) / 1e9, 3), ms_per_step=round(ms, 4), dtype="f32",
+                    separate_launches_gbps=round(bits / (sep * 1e-3) / 1e9, 3),
+                    config={"workload": "N=1008/4032 (3,6) + N=8000 (4,20) QC, 2^18/2^16/2^15 frames, "
+                                        "Eb/N0 U[3,6] dB per frame, f32, G=8/32/64, one launch",
+                            "frames": sum(s[1] for s in specs)})
+    elif a.workload == "n32400_i16":
+        code = fwbf.Code.from_seed(3, 30, 1080, 5)
+        F = 1 << 15
+        pool = torch.from_numpy(code.encode(5, 0, 64).view(np.int32)).to(dev)
+        res = {}
+        for eb in (5.0, 6.0, 7.0):
+            y = fwbf.channel(code.N, F, 0, pool, 900, int(eb), float(synth.sigma_for(eb, code.rate)),
+                             dtype=torch.int16, scale=256.0)
+            p = fwbf.DecodeParams(dtype=fwbf.I16, groups=64, max_iter=100)
+            z, it, ok = fwbf.decode(code, y, p)
+            ms = _timed(lambda: fwbf.decode_into(code, y, p, z, it, ok), a.steps, a.warmup)
+            r = fwbf.count(code.N, z, pool, 0, it, ok, 100)
+            res[eb] = dict(gbps=round(F * code.N / (ms * 1e-3) / 1e9, 3), ms=round(ms, 4),
+                           fer=r["frame_err"] / F, ber=r["bit_err"] / (F * code.N))
+        line.update(metric="decoded Gb/s, plain FWBF, N=32400 (3,30) QC rate 0.9, int16",
+                    value=res[6.0]["gbps"], ms_per_step=res[6.0]["ms"], dtype="int32", points=res,
+                    config={"workload": "N=32400 (3,30) QC Z=1080 K=29162, int16 x256, G=64, K_max=100, "
+                                        "2^15 frames per point", "frames": F})
+    else:  # sweep_n1008_i8
+        code = fwbf.Code.from_seed(3, 6, 168, 2)
+        pool = torch.from_numpy(code.encode(1001, 0, 1024).view(np.int32)).to(dev)
+        ebs = np.arange(2.0, 6.01, 0.5)
+        F = 1 << 18
+        sw = fwbf.Sweep(code, fwbf.DecodeParams(dtype=fwbf.I8, groups=8, max_iter=100),
+                        synth.sigma_for(ebs, code.rate), F, pool=pool, seed=1100, scale=16.0)
+        ms = _timed(sw.launch, a.steps, a.warmup)
+        c = sw.counters()
+        line.update(metric="Eb/N0 sweep (channel+decode+count per point), one HIP graph, Gb/s",
+                    value=round(len(ebs) * F * code.N / (ms * 1e-3) / 1e9, 3), ms_per_step=round(ms, 4),
+                    dtype="int32",
+                    fer={f"{e:.1f}": float(c[k, 1] / c[k, 4]) for k, e in enumerate(ebs)},
+                    ber={f"{e:.1f}": float(c[k, 0] / (c[k, 4] * code.N)) for k, e in enumerate(ebs)},
+                    config={"workload": "N=1008 int8 G=8, 9 points 2..6 dB, 2^18 frames per point",
+                            "frames": int(len(ebs) * F)})
+    print(json.dumps(line), flush=True)
 
 
 def kernel_sha():
