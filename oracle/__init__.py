@@ -66,6 +66,9 @@ def lib():
         L.or_code_shifts.argtypes = [vp, vp]
         L.or_code_shifts.restype = None
         L.or_code_edges.argtypes = [vp]
+        L.or_code_n_entries.argtypes = [vp]
+        L.or_code_entries.argtypes = [vp, vp]
+        L.or_code_entries.restype = None
         L.or_code_rows.argtypes = [vp, vp, vp]
         L.or_code_rows.restype = None
         L.or_code_violates_rc.argtypes = [vp]
@@ -129,8 +132,18 @@ class Code:
         lib().or_code_shifts(self._h, _ptr(out))
         return out
 
+    def entries(self) -> np.ndarray:
+        """(block row, block column, shift) of every circulant permutation."""
+        n = lib().or_code_n_entries(self._h)
+        out = np.zeros((n, 3), np.int32)
+        lib().or_code_entries(self._h, _ptr(out))
+        return out
+
     def to_text(self) -> str:
-        rows = "\n".join(" ".join(str(int(v)) for v in r) for r in self.shifts)
+        cells = [[[] for _ in range(self.nb)] for _ in range(self.mb)]
+        for i, j, s in self.entries():
+            cells[i][j].append(int(s))
+        rows = "\n".join(" ".join(",".join(map(str, c)) if c else "-1" for c in r) for r in cells)
         return f"qc-ldpc v1\nZ {self.Z}\nbase {self.mb} {self.nb}\n{rows}\n"
 
     def rows(self):

@@ -57,7 +57,9 @@ enum { D_F32 = 0, D_I8 = 1, D_I16 = 2 };
 
 typedef struct {
     int Z, mb, nb;
-    int *shift; /* mb*nb, -1 = all-zero block */
+    int *shift; /* mb*nb: first shift of each block, -1 = all-zero block */
+    int nent;   /* circulant permutations: (block row, block column, shift) */
+    int *ent;
     int N, M;
     int *row_ptr, *row_bits; /* N(m), ascending bit index */
     int *col_ptr, *col_chks; /* M(n), ascending check index */
@@ -95,8 +97,10 @@ uint64_t or_splitmix64(uint64_t seed, uint64_t idx) { return sm64_at(seed, idx);
 /* ------------------------------------------------------------------------ */
 /* Code construction: QC description -> materialised Tanner adjacency.      */
 /* Block (i,j) with shift s >= 0 is the Z x Z permutation taking row r to   */
-/* column (r + s) mod Z; shift -1 is the zero block.  Section II defines    */
-/* M(n) and N(m) as the positions of ones in column n and row m of H.       */
+/* column (r + s) mod Z; shift -1 is the zero block; a list of distinct      */
+/* shifts is the sum of their permutations (a circulant of that weight).    */
+/* Section II defines M(n) and N(m) as the positions of ones in column n    */
+/* and row m of H.                                                          */
 /* ------------------------------------------------------------------------ */
 static int cmp_int(const void *a, const void *b)
 {
@@ -108,6 +112,7 @@ static void code_release(ocode *c)
 {
     if (!c) return;
     free(c->shift);
+    free(c->ent);
     free(c->row_ptr); free(c->row_bits);
     free(c->col_ptr); free(c->col_chks);
     free(c->rref); free(c->piv_col); free(c->info_pos);
@@ -115,28 +120,32 @@ static void code_release(ocode *c)
 }
 void or_code_free(ocode *c) { code_release(c); }
 
-static ocode *code_build(int mb, int nb, int Z, const int *shift)
+/* ent: nent triples (i, j, s) */
+static ocode *code_build(int mb, int nb, int Z, int nent, const int *ent)
 {
     ocode *c = (ocode *)calloc(1, sizeof(ocode));
     if (!c) return NULL;
     c->Z = Z; c->mb = mb; c->nb = nb;
     c->N = nb * Z; c->M = mb * Z;
+    c->nent = nent;
     c->shift = (int *)malloc(sizeof(int) * mb * nb);
+    c->ent = (int *)malloc(sizeof(int) * 3 * (nent ? nent : 1));
     c->row_ptr = (int *)calloc(c->M + 1, sizeof(int));
     c->col_ptr = (int *)calloc(c->N + 1, sizeof(int));
-    if (!c->shift || !c->row_ptr || !c->col_ptr) { code_release(c); return NULL; }
-    memcpy(c->shift, shift, sizeof(int) * mb * nb);
+    if (!c->shift || !c->ent || !c->row_ptr || !c->col_ptr) { code_release(c); return NULL; }
+    memcpy(c->ent, ent, sizeof(int) * 3 * nent);
+    for (int t = 0; t < mb * nb; t++) c->shift[t] = -1;
+    for (int e = nent - 1; e >= 0; e--) c->shift[ent[3 * e] * nb + ent[3 * e + 1]] = ent[3 * e + 2];
 
     /* count the ones of every row and column of H */
-    for (int i = 0; i < mb; i++)
-        for (int j = 0; j < nb; j++) {
-            if (shift[i * nb + j] < 0) continue;
-            for (int r = 0; r < Z; r++) {
-                int m = i * Z + r, n = j * Z + (r + shift[i * nb + j]) % Z;
-                c->row_ptr[m + 1]++;
-                c->col_ptr[n + 1]++;
-            }
+    for (int e = 0; e < nent; e++) {
+        int i = ent[3 * e], j = ent[3 * e + 1], sh = ent[3 * e + 2];
+        for (int r = 0; r < Z; r++) {
+            int m = i * Z + r, n = j * Z + (r + sh) % Z;
+            c->row_ptr[m + 1]++;
+            c->col_ptr[n + 1]++;
         }
+    }
     for (int m = 0; m < c->M; m++) c->row_ptr[m + 1] += c->row_ptr[m];
     for (int n = 0; n < c->N; n++) c->col_ptr[n + 1] += c->col_ptr[n];
     int E = c->row_ptr[c->M];
@@ -147,20 +156,35 @@ static ocode *code_build(int mb, int nb, int Z, const int *shift)
     if (!c->row_bits || !c->col_chks || !rfill || !cfill) {
         free(rfill); free(cfill); code_release(c); return NULL;
     }
-    for (int i = 0; i < mb; i++)
-        for (int j = 0; j < nb; j++) {
-            if (shift[i * nb + j] < 0) continue;
-            for (int r = 0; r < Z; r++) {
-                int m = i * Z + r, n = j * Z + (r + shift[i * nb + j]) % Z;
-                c->row_bits[c->row_ptr[m] + rfill[m]++] = n;
-                c->col_chks[c->col_ptr[n] + cfill[n]++] = m;
-            }
+    for (int e = 0; e < nent; e++) {
+        int i = ent[3 * e], j = ent[3 * e + 1], sh = ent[3 * e + 2];
+        for (int r = 0; r < Z; r++) {
+            int m = i * Z + r, n = j * Z + (r + sh) % Z;
+            c->row_bits[c->row_ptr[m] + rfill[m]++] = n;
+            c->col_chks[c->col_ptr[n] + cfill[n]++] = m;
         }
+    }
     free(rfill); free(cfill);
     for (int m = 0; m < c->M; m++)
         qsort(c->row_bits + c->row_ptr[m], c->row_ptr[m + 1] - c->row_ptr[m], sizeof(int), cmp_int);
     for (int n = 0; n < c->N; n++)
         qsort(c->col_chks + c->col_ptr[n], c->col_ptr[n + 1] - c->col_ptr[n], sizeof(int), cmp_int);
+    return c;
+}
+
+static ocode *code_build_single(int mb, int nb, int Z, const int *shift)
+{
+    int *ent = (int *)malloc(sizeof(int) * 3 * mb * nb);
+    if (!ent) return NULL;
+    int k = 0;
+    for (int i = 0; i < mb; i++)
+        for (int j = 0; j < nb; j++)
+            if (shift[i * nb + j] >= 0) {
+                ent[3 * k] = i; ent[3 * k + 1] = j; ent[3 * k + 2] = shift[i * nb + j];
+                k++;
+            }
+    ocode *c = code_build(mb, nb, Z, k, ent);
+    free(ent);
     return c;
 }
 
@@ -197,7 +221,8 @@ int or_code_violates_rc(const ocode *c)
 }
 
 /* Text description: "qc-ldpc v1", then "Z <int>", "base <mb> <nb>", then
- * mb rows of nb shifts (-1 = zero block).  '#' starts a comment. */
+ * mb rows of nb entries: -1 (zero block), a shift, or a comma-separated list
+ * of distinct shifts.  '#' starts a comment. */
 static int next_token(const char **p, char *tok, int cap)
 {
     const char *s = *p;
@@ -239,21 +264,40 @@ int or_code_from_text(const char *text, ocode **out)
     if (!next_token(&p, tok, sizeof tok) || strcmp(tok, "base")) return OR_EPARSE;
     if (!next_token(&p, tok, sizeof tok) || !parse_int(tok, &mb)) return OR_EPARSE;
     if (!next_token(&p, tok, sizeof tok) || !parse_int(tok, &nb)) return OR_EPARSE;
-    if (Z < 1 || mb < 1 || nb < 1 || Z > 65536 || mb > 256 || nb > 256 || Z * nb > (1L << 20))
+    if (Z < 1 || mb < 1 || nb < 1 || Z > 65536 || mb > 4096 || nb > 4096 || Z * nb > (1L << 20) ||
+        Z * mb > (1L << 20))
         return OR_EPARSE;
-    int *sh = (int *)malloc(sizeof(int) * mb * nb);
-    if (!sh) return OR_ENOMEM;
+    int cap = (int)(mb * nb) + 16, nent = 0;
+    int *ent = (int *)malloc(sizeof(int) * 3 * cap);
+    if (!ent) return OR_ENOMEM;
+    char big[4096];
     for (long t = 0; t < mb * nb; t++) {
-        long v;
-        if (!next_token(&p, tok, sizeof tok) || !parse_int(tok, &v) || v < -1 || v >= Z) {
-            free(sh);
-            return OR_EPARSE;
+        if (!next_token(&p, big, sizeof big)) { free(ent); return OR_EPARSE; }
+        if (!strcmp(big, "-1")) continue;
+        int first = nent;
+        char *q = big;
+        for (;;) {
+            char *comma = strchr(q, ',');
+            if (comma) *comma = 0;
+            long v;
+            if (!parse_int(q, &v) || v < 0 || v >= Z) { free(ent); return OR_EPARSE; }
+            for (int e = first; e < nent; e++)
+                if (ent[3 * e + 2] == v) { free(ent); return OR_EPARSE; } /* repeated shift */
+            if (nent == cap) {
+                cap *= 2;
+                int *ne = (int *)realloc(ent, sizeof(int) * 3 * cap);
+                if (!ne) { free(ent); return OR_ENOMEM; }
+                ent = ne;
+            }
+            ent[3 * nent] = (int)(t / nb); ent[3 * nent + 1] = (int)(t % nb); ent[3 * nent + 2] = (int)v;
+            nent++;
+            if (!comma) break;
+            q = comma + 1;
         }
-        sh[t] = (int)v;
     }
-    if (next_token(&p, tok, sizeof tok)) { free(sh); return OR_EPARSE; }
-    ocode *c = code_build((int)mb, (int)nb, (int)Z, sh);
-    free(sh);
+    if (next_token(&p, tok, sizeof tok)) { free(ent); return OR_EPARSE; }
+    ocode *c = code_build((int)mb, (int)nb, (int)Z, nent, ent);
+    free(ent);
     if (!c) return OR_ENOMEM;
     *out = c;
     return OR_OK;
@@ -272,7 +316,7 @@ int or_code_from_seed(int mb, int nb, int Z, uint64_t seed, int min_girth, ocode
     if (!sh) return OR_ENOMEM;
     for (int attempt = 0; attempt < 100000; attempt++) {
         for (int t = 0; t < mb * nb; t++) sh[t] = (int)(sm64_next(&st) % (uint64_t)Z);
-        ocode *c = code_build(mb, nb, Z, sh);
+        ocode *c = code_build_single(mb, nb, Z, sh);
         if (!c) { free(sh); return OR_ENOMEM; }
         if (min_girth < 6 || !or_code_violates_rc(c)) {
             free(sh);
@@ -290,6 +334,8 @@ void or_code_dims(const ocode *c, int *N, int *M, int *Z, int *mb, int *nb)
     *N = c->N; *M = c->M; *Z = c->Z; *mb = c->mb; *nb = c->nb;
 }
 void or_code_shifts(const ocode *c, int *out) { memcpy(out, c->shift, sizeof(int) * c->mb * c->nb); }
+int or_code_n_entries(const ocode *c) { return c->nent; }
+void or_code_entries(const ocode *c, int *out) { memcpy(out, c->ent, sizeof(int) * 3 * c->nent); }
 int or_code_edges(const ocode *c) { return c->row_ptr[c->M]; }
 /* row-major materialised adjacency: for every check, its bits */
 void or_code_rows(const ocode *c, int *row_ptr, int *row_bits)

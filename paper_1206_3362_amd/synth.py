@@ -102,3 +102,44 @@ def subnormal_frames(N, F, seed, flip_frac=0.08):
     bits = rng.integers(1, 1 << 23, (F, N), dtype=np.uint32)
     sign = (rng.random((F, N)) < flip_frac).astype(np.uint32) << 31
     return (bits | sign).view(np.float32)
+
+
+# --------------------------------------------------------------------------
+# Type-I two-dimensional Euclidean-geometry cyclic codes (the codes of the
+# paper's Section V).  The points of EG(2, 2^s) other than the origin are the
+# nonzero elements alpha^e of GF(2^(2s)); the lines not through the origin
+# are the cyclic shifts (multiplication by alpha^i) of one such line, and H
+# lists their incidence vectors: an n x n circulant, n = 2^(2s) - 1, with
+# row and column weight 2^s.  In the QC text this is Z = n, a 1 x 1 base and
+# one block holding 2^s shifts (the exponents of the line's points).
+# --------------------------------------------------------------------------
+# primitive polynomials of degree 2s (bit i = coefficient of x^i)
+EG_PRIMITIVE = {2: 0x13, 3: 0x43, 4: 0x11D, 5: 0x409}
+
+
+def eg_line_exponents(s):
+    """Exponents e (alpha^e) of the points of the line {1 + b alpha : b in GF(2^s)}."""
+    m = 2 * s
+    n = (1 << m) - 1
+    exp = np.zeros(n, np.int64)
+    x = 1
+    for i in range(n):
+        exp[i] = x
+        x <<= 1
+        if x >> m:
+            x ^= EG_PRIMITIVE[s]
+    log = {int(v): i for i, v in enumerate(exp)}
+    if len(log) != n:
+        raise ValueError("polynomial is not primitive")
+    q = 1 << s
+    # GF(2^s) inside GF(2^(2s)): 0 and the powers alpha^(k (q + 1))
+    sub_logs = [k * (q + 1) % n for k in range(q - 1)]
+    pts = [1] + [1 ^ int(exp[(lb + 1) % n]) for lb in sub_logs]
+    return sorted(log[p] for p in pts)
+
+
+def eg_code_text(s):
+    """QC description of the (2^(2s) - 1)-bit EG code (s = 4: EG(255,175), s = 5: EG(1023,781))."""
+    n = (1 << (2 * s)) - 1
+    return (f"qc-ldpc v1\n# type-I 2-D Euclidean geometry code over GF(2^{s})\n"
+            f"Z {n}\nbase 1 1\n" + ",".join(map(str, eg_line_exponents(s))) + "\n")

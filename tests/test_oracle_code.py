@@ -128,3 +128,64 @@ def test_encoder_large_code_rank(ocodes):
     for f in range(2):
         par = np.add.reduceat(cw[f, rb], rp[:-1]) % 2
         assert (par == 0).all()
+
+
+def _perm(Z, s):
+    P = np.zeros((Z, Z), np.uint8)
+    P[np.arange(Z), (np.arange(Z) + s) % Z] = 1
+    return P
+
+
+def test_multi_shift_blocks_are_sums_of_permutations():
+    txt = "qc-ldpc v1\nZ 7\nbase 2 2\n0,1,3 2\n-1 4,6\n"
+    c = O.Code.from_text(txt)
+    Z = 7
+    want = np.zeros((14, 14), np.uint8)
+    want[:7, :7] = _perm(Z, 0) + _perm(Z, 1) + _perm(Z, 3)
+    want[:7, 7:] = _perm(Z, 2)
+    want[7:, 7:] = _perm(Z, 4) + _perm(Z, 6)
+    assert (c.dense() == want).all()
+    assert sorted(map(tuple, c.entries().tolist())) == [(0, 0, 0), (0, 0, 1), (0, 0, 3), (0, 1, 2),
+                                                        (1, 1, 4), (1, 1, 6)]
+    assert (O.Code.from_text(c.to_text()).dense() == want).all()
+    # {0,1,3} is a perfect difference set mod 7: no difference repeats, so
+    # the weight-3 circulant has no 4-cycle; {0,1,2} repeats the difference 1
+    assert not O.Code.from_text("qc-ldpc v1\nZ 7\nbase 1 1\n0,1,3\n").violates_rc()
+    assert O.Code.from_text("qc-ldpc v1\nZ 7\nbase 1 1\n0,1,2\n").violates_rc()
+
+
+@pytest.mark.parametrize("bad", ["0,0", "0,7", "0,", ",1", "1,-1"])
+def test_multi_shift_rejects_malformed(bad):
+    with pytest.raises(O.OracleError, match="parse"):
+        O.Code.from_text(f"qc-ldpc v1\nZ 7\nbase 1 1\n{bad}\n")
+
+
+@pytest.mark.parametrize("s", [2, 3, 4, 5])
+def test_euclidean_geometry_codes(s):
+    """Type-I 2-D EG codes over GF(2^s) (the codes of Section V): length
+    n = 4^s - 1, row and column weight 2^s, RC constraint (two lines meet in
+    at most one point), cyclic H, and the closed-form rank n - k = 3^s - 1
+    (Lin & Costello, Error Control Coding, 2nd ed., Ch. 17), which gives the
+    (255,175) and (1023,781) codes named in the paper for s = 4 and 5."""
+    from paper_1206_3362_amd import synth
+    c = O.Code.from_text(synth.eg_code_text(s))
+    n = 4 ** s - 1
+    assert (c.N, c.M) == (n, n)
+    assert c.K == n - (3 ** s - 1)
+    if s == 4:
+        assert c.K == 175
+    if s == 5:
+        assert c.K == 781
+    H = c.dense()
+    assert (H.sum(0) == 2 ** s).all() and (H.sum(1) == 2 ** s).all()
+    for i in range(0, n, max(1, n // 17)):
+        assert (H[i] == np.roll(H[0], i)).all()
+    Hf = H.astype(np.float32)
+    G = Hf @ Hf.T
+    np.fill_diagonal(G, 0)
+    assert G.max() <= 1
+    assert not c.violates_rc()
+    # the line's points lie outside the subfield line through the origin:
+    # no point is zero, all 2^s exponents are distinct
+    ex = synth.eg_line_exponents(s)
+    assert len(set(ex)) == 2 ** s and ex[0] == 0

@@ -229,3 +229,68 @@ def test_count_accounting():
     assert r["bit_err"] == 2 and r["frame_err"] == 2 and r["undetected"] == 1
     assert r["iter_sum"] == 110 and r["frames"] == 4
     assert r["hist"][0] == 1 and r["hist"][3] == 1 and r["hist"][100] == 1 and r["hist"][7] == 1
+
+
+def _max_per_group(pat, N, G):
+    p = -(-N // G)
+    cnt = np.zeros(-(-N // p), np.int64)
+    for e in pat:
+        cnt[e // p] += 1
+    return int(cnt.max())
+
+
+@pytest.mark.parametrize("s", [4, 5])
+@pytest.mark.parametrize("dtype,A", [(np.float32, 1.0), (np.int8, 16)])
+def test_eg_error_patterns_closed_form(s, dtype, A):
+    """EG codes (column weight dv = 2^s, RC constraint), uniform magnitude A,
+    e <= dv/2 hard-decision errors, 0 <= alpha < 2.  Each error bit has at
+    least dv - (e - 1) unsatisfied checks and every other bit at most e
+    (RC), and every check weight equals A, so in eq. (1)
+      error bit: E >= A(2(dv - e + 1) - dv - alpha) >= A(2 - alpha) > 0,
+      other bit: E <= A(2e - dv - alpha) <= -A alpha <= 0.
+    Every block holding an error therefore flips one error per round and no
+    other block flips: the decoder reaches the codeword after exactly
+    max over blocks of (errors in the block) rounds (Section III); the single
+    global choice takes e rounds and top-lambda ceil(e / lambda)."""
+    from paper_1206_3362_amd import synth as S
+    c = O.Code.from_text(S.eg_code_text(s))
+    N, dv = c.N, 2 ** s
+    rng = np.random.default_rng(s)
+    pats = [sorted(rng.choice(N, size=e, replace=False).tolist())
+            for e in range(1, dv // 2 + 1) for _ in range(6)]
+    y = S.error_pattern_frames(N, pats, A, dtype)
+    f = dtype == np.float32
+    for w, al, an, ad in [(O.WBF, 0.0, 0, 1), (O.MWBF, 1.0, 1, 1), (O.IMWBF, 1.0, 1, 1), (O.IMWBF, 1.5, 3, 2)]:
+        kw = dict(weights=w, alpha=al, alpha_num=an, alpha_den=ad, max_iter=dv)
+        for G in (1, 11, 33, N):
+            z, it, ok = O.decode(c, y, G=G, **kw)
+            assert (O.unpack(z, N) == 0).all() and (ok == 1).all()
+            assert it.tolist() == [_max_per_group(p, N, G) for p in pats], (w, G)
+        z, it, ok = O.decode(c, y, select=O.SINGLE, **kw)
+        assert (ok == 1).all() and it.tolist() == [len(p) for p in pats]
+        z, it, ok = O.decode(c, y, select=O.TOPL, lam=5, **kw)
+        assert (ok == 1).all() and it.tolist() == [-(-len(p) // 5) for p in pats]
+
+
+# Tab. 1 of the paper: averaged iterations on EG(1023,781), K_max = 10
+TAB1 = {11: (1.0, {3.5: 7.37, 4.0: 6.06, 4.5: 5.12}),   # p = 93
+        33: (1.5, {3.5: 5.60, 4.0: 4.19, 4.5: 3.64})}   # p = 31
+
+
+@pytest.mark.parametrize("G", [11, 33])
+def test_table1_statistical(G):
+    """Averaged iterations of FWBF on EG(1023,781) against the values printed
+    in Tab. 1 (3.5 to 4.5 dB; float inputs, IMWBF metric).  Two readings make
+    the comparison: an iteration is a pass of Step 1 (a syndrome evaluation),
+    so a frame that stops on a zero syndrome after r flip rounds counts
+    min(r + 1, K_max) and every other frame K_max; alpha, which the paper
+    does not give, is the one value per row that fits it (1.0 for p=93, 1.5
+    for p=31).  2000 frames per point (standard error about 0.03)."""
+    c = O.Code.from_text(synth.eg_code_text(5))
+    al, pts = TAB1[G]
+    for eb, want in pts.items():
+        y = synth.awgn_frames(c.N, 2000, synth.sigma_for(eb, c.K / c.N), int(eb * 10) + G, None,
+                              np.float32)
+        z, it, ok = O.decode(c, y, G=G, max_iter=10, alpha=al, weights=O.IMWBF)
+        passes = np.where(ok == 1, np.minimum(it + 1, 10), 10)
+        assert abs(passes.mean() - want) < 0.2, (G, eb, passes.mean(), want)
