@@ -1,6 +1,7 @@
 // Host side of libfwbf.so: QC-LDPC code objects (Section II of the paper:
 // H, M(n), N(m), the RC constraint), the seeded base draw, GF(2) rank and the
 // systematic encoder, error reporting.
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -61,7 +62,13 @@ bool base_has_4cycle(int mb, int nb, int Z, const int *s)
     return false;
 }
 
-int make_code(int mb, int nb, int Z, const std::vector<int> &shift, fwbf_code **out)
+// A block may hold several distinct shifts (a circulant of that weight).
+// cells[i * nb + j] lists the shifts of block (i, j); an empty list is the
+// zero block.  Within a block the kernels' tables list the shifts in
+// descending order, so that for bit c of a block column the checks of one
+// block row come in ascending order after a rotation: those with shift <= c
+// first, then the wrapped ones (row (c - s) mod Z).
+int make_code(int mb, int nb, int Z, std::vector<std::vector<int>> cells, fwbf_code **out)
 {
     if (Z < 1 || Z > 65535 || mb < 1 || nb < 1 || (long)nb * Z > 65535 || (long)mb * Z > 65535)
         return fail(FWBF_E_INVALID, "code dimensions out of range (Z <= 65535, N, M <= 65535)");
@@ -69,41 +76,83 @@ int make_code(int mb, int nb, int Z, const std::vector<int> &shift, fwbf_code **
     if (!c) return fail(FWBF_E_NOMEM, "out of host memory");
     c->Z = Z; c->mb = mb; c->nb = nb;
     c->N = nb * Z; c->M = mb * Z;
-    c->shift = shift;
+    c->shift.assign((size_t)mb * nb, -1);
     c->coldeg.assign(nb, 0);
     c->rowdeg.assign(mb, 0);
+    std::vector<int> cdeg(nb, 0), rdeg(mb, 0);
     for (int i = 0; i < mb; i++)
-        for (int j = 0; j < nb; j++)
-            if (shift[i * nb + j] >= 0) { c->coldeg[j]++; c->rowdeg[i]++; }
-    for (int j = 0; j < nb; j++) c->dv_max = std::max<int>(c->dv_max, c->coldeg[j]);
-    for (int i = 0; i < mb; i++) c->dc_max = std::max<int>(c->dc_max, c->rowdeg[i]);
+        for (int j = 0; j < nb; j++) {
+            auto &v = cells[(size_t)i * nb + j];
+            std::sort(v.begin(), v.end(), [](int x, int y) { return x > y; });
+            if (v.size() > 1) c->multi = true;
+            if (!v.empty()) c->shift[(size_t)i * nb + j] = v[0];
+            cdeg[j] += (int)v.size();
+            rdeg[i] += (int)v.size();
+        }
+    for (int j = 0; j < nb; j++) c->dv_max = std::max(c->dv_max, cdeg[j]);
+    for (int i = 0; i < mb; i++) c->dc_max = std::max(c->dc_max, rdeg[i]);
     if (c->dv_max > 64 || c->dc_max > 64 || c->dv_max == 0) {
         delete c;
-        return fail(FWBF_E_UNSUPPORTED, "base rows and columns must have at most 64 nonzero blocks");
+        return fail(FWBF_E_UNSUPPORTED, "column and row weights must be at most 64 (and some column nonzero)");
     }
+    for (int j = 0; j < nb; j++) c->coldeg[j] = (uint8_t)cdeg[j];
+    for (int i = 0; i < mb; i++) c->rowdeg[i] = (uint8_t)rdeg[i];
+    c->cells = cells;
     c->row.assign((size_t)mb * c->dc_max, 0);
     c->col.assign((size_t)nb * c->dv_max, 0);
-    std::vector<int> qpos((size_t)mb * nb, -1);
+    std::vector<int> qpos((size_t)mb * nb, -1);  // row-list position of a block's first shift
     for (int i = 0; i < mb; i++) {
         int q = 0;
         for (int j = 0; j < nb; j++) {
-            int s = shift[i * nb + j];
-            if (s < 0) continue;
-            qpos[i * nb + j] = q;
-            c->row[(size_t)i * c->dc_max + q++] = ((uint32_t)j << 16) | (uint32_t)s;
+            const auto &v = cells[(size_t)i * nb + j];
+            if (!v.empty()) qpos[(size_t)i * nb + j] = q;
+            for (int s : v) c->row[(size_t)i * c->dc_max + q++] = ((uint32_t)j << 16) | (uint32_t)s;
         }
     }
     for (int j = 0; j < nb; j++) {
         int t = 0;
         for (int i = 0; i < mb; i++) {
-            int s = shift[i * nb + j];
-            if (s < 0) continue;
-            c->col[(size_t)j * c->dv_max + t++] =
-                ((uint32_t)i << 24) | ((uint32_t)qpos[i * nb + j] << 16) | (uint32_t)s;
+            const auto &v = cells[(size_t)i * nb + j];
+            for (size_t u = 0; u < v.size(); u++)
+                c->col[(size_t)j * c->dv_max + t++] =
+                    ((uint32_t)i << 24) | ((uint32_t)(qpos[(size_t)i * nb + j] + u) << 16) | (uint32_t)v[u];
         }
     }
     *out = c;
     return FWBF_OK;
+}
+
+int make_code(int mb, int nb, int Z, const std::vector<int> &shift, fwbf_code **out)
+{
+    std::vector<std::vector<int>> cells((size_t)mb * nb);
+    for (size_t t = 0; t < cells.size(); t++)
+        if (shift[t] >= 0) cells[t].push_back(shift[t]);
+    return make_code(mb, nb, Z, std::move(cells), out);
+}
+
+// 4-cycle test on the expanded graph: two checks sharing two bits.  Every
+// pair of bits of every check is listed once and the list is searched for a
+// repeat (used for bases with multi-shift blocks, where cycles can also lie
+// inside one block row).
+bool expanded_has_4cycle(const fwbf_code *c)
+{
+    std::vector<uint64_t> pairs;
+    std::vector<int> bits;
+    for (int i = 0; i < c->mb; i++)
+        for (int r = 0; r < c->Z; r++) {
+            bits.clear();
+            for (int q = 0; q < c->rowdeg[i]; q++) {
+                const uint32_t e = c->row[(size_t)i * c->dc_max + q];
+                bits.push_back((int)(e >> 16) * c->Z + (r + (int)(e & 0xFFFF)) % c->Z);
+            }
+            for (size_t a = 0; a < bits.size(); a++)
+                for (size_t b = a + 1; b < bits.size(); b++) {
+                    const uint64_t lo = std::min(bits[a], bits[b]), hi = std::max(bits[a], bits[b]);
+                    pairs.push_back(lo << 32 | hi);
+                }
+        }
+    std::sort(pairs.begin(), pairs.end());
+    return std::adjacent_find(pairs.begin(), pairs.end()) != pairs.end();
 }
 
 // tokenizer for the description text
@@ -274,16 +323,30 @@ int fwbf_code_from_text(const char *text, fwbf_code **out)
     if (Z < 1 || Z > 65535 || mb < 1 || nb < 1 || mb > 4096 || nb > 4096 || nb * Z > 65535 ||
         mb * Z > 65535)
         return fail(FWBF_E_PARSE, "dimensions out of range");
-    std::vector<int> sh((size_t)mb * nb);
+    std::vector<std::vector<int>> cells((size_t)mb * nb);
     for (long t = 0; t < mb * nb; t++) {
-        long v;
-        if (!lx.integer(v)) return fail(FWBF_E_PARSE, "expected " + std::to_string(mb * nb) + " shifts");
-        if (v < -1 || v >= Z) return fail(FWBF_E_PARSE, "shift out of range [-1, Z)");
-        sh[t] = (int)v;
+        std::string tok;
+        if (!lx.next(tok)) return fail(FWBF_E_PARSE, "expected " + std::to_string(mb * nb) + " blocks");
+        if (tok == "-1") continue;
+        size_t at = 0;
+        for (;;) {
+            const size_t comma = tok.find(',', at);
+            const std::string part = tok.substr(at, comma == std::string::npos ? std::string::npos : comma - at);
+            char *end = nullptr;
+            const long v = strtol(part.c_str(), &end, 10);
+            if (part.empty() || *end != 0) return fail(FWBF_E_PARSE, "bad block '" + tok + "'");
+            if (v < 0 || v >= Z) return fail(FWBF_E_PARSE, "shift out of range [0, Z) in '" + tok + "'");
+            auto &cell = cells[(size_t)t];
+            if (std::find(cell.begin(), cell.end(), (int)v) != cell.end())
+                return fail(FWBF_E_PARSE, "repeated shift in '" + tok + "'");
+            cell.push_back((int)v);
+            if (comma == std::string::npos) break;
+            at = comma + 1;
+        }
     }
     std::string extra;
     if (lx.next(extra)) return fail(FWBF_E_PARSE, "trailing text '" + extra + "'");
-    return make_code((int)mb, (int)nb, (int)Z, sh, out);
+    return make_code((int)mb, (int)nb, (int)Z, std::move(cells), out);
 }
 
 int fwbf_code_from_seed(int mb, int nb, int Z, uint64_t seed, int min_girth, fwbf_code **out)
@@ -309,7 +372,12 @@ int fwbf_code_to_text(const fwbf_code *c, char *buf, size_t cap, size_t *needed)
     std::ostringstream os;
     os << "qc-ldpc v1\nZ " << c->Z << "\nbase " << c->mb << " " << c->nb << "\n";
     for (int i = 0; i < c->mb; i++) {
-        for (int j = 0; j < c->nb; j++) os << (j ? " " : "") << c->shift[i * c->nb + j];
+        for (int j = 0; j < c->nb; j++) {
+            const auto &v = c->cells[(size_t)i * c->nb + j];
+            os << (j ? " " : "");
+            if (v.empty()) os << -1;
+            for (size_t u = 0; u < v.size(); u++) os << (u ? "," : "") << v[u];
+        }
         os << "\n";
     }
     std::string s = os.str();
@@ -341,6 +409,8 @@ int fwbf_code_shifts(const fwbf_code *c, int *mb, int *nb, int *Z, int *shifts)
     if (mb) *mb = c->mb;
     if (nb) *nb = c->nb;
     if (Z) *Z = c->Z;
+    if (shifts && c->multi)
+        return fail(FWBF_E_UNSUPPORTED, "the base has blocks with several shifts (use fwbf_code_to_text)");
     if (shifts) memcpy(shifts, c->shift.data(), sizeof(int) * c->shift.size());
     return FWBF_OK;
 }
@@ -348,6 +418,7 @@ int fwbf_code_shifts(const fwbf_code *c, int *mb, int *nb, int *Z, int *shifts)
 int fwbf_code_has_4cycle(const fwbf_code *c)
 {
     if (!c) return fail(FWBF_E_INVALID, "null code");
+    if (c->multi) return expanded_has_4cycle(c) ? 1 : 0;
     return base_has_4cycle(c->mb, c->nb, c->Z, c->shift.data()) ? 1 : 0;
 }
 

@@ -69,6 +69,7 @@ struct DecodeArgs {
     // |y| staged in LDS only while the check minima are computed (it then
     // shares memory with the slots) and read from global memory afterwards
     int mag_alias;
+    int multi;  // some block holds several shifts
 };
 
 __device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t mag, uint32_t mask)
@@ -174,14 +175,32 @@ __device__ __forceinline__ uint32_t metric_val(const DecodeArgs &a, const Lds &s
     const typename T::Chk *chk = (const typename T::Chk *)s.chk;
     if constexpr (T::isf) {
         float S = 0.0f;
-        for (int t = 0; t < deg; t++) {
-            const uint32_t e = ce[t];
+        auto term = [&](uint32_t e) {
             int r = c - (int)(e & 0xFFFF);
             r += (r < 0) ? a.Z : 0;
             const uint32_t m = (e >> 24) * a.Z + r;
             const float w = weight_f(chk[m], s.chkp[m], (e >> 16) & 0xFF, imwbf);
-            const float term = ((s.syn[m >> 5] >> (m & 31)) & 1) ? w : -w;
-            S = (t == 0) ? term : S + term;
+            return ((s.syn[m >> 5] >> (m & 31)) & 1) ? w : -w;
+        };
+        if (!a.multi) {
+            for (int t = 0; t < deg; t++) S = (t == 0) ? term(ce[t]) : S + term(ce[t]);
+        } else {
+            // the shifts of one block row are listed in descending order:
+            // start at the first shift <= c (row c - s), then wrap
+            int t0 = 0, cnt = 0;
+            while (t0 < deg) {
+                const uint32_t i = ce[t0] >> 24;
+                int t1 = t0 + 1;
+                while (t1 < deg && (ce[t1] >> 24) == i) t1++;
+                int u = t0;
+                while (u < t1 && (int)(ce[u] & 0xFFFF) > c) u++;
+                for (int v = 0; v < t1 - t0; v++, cnt++) {
+                    int x = u + v;
+                    x -= (x >= t1) ? t1 - t0 : 0;
+                    S = (cnt == 0) ? term(ce[x]) : S + term(ce[x]);
+                }
+                t0 = t1;
+            }
         }
         return orderable(__builtin_fmaf(-a.alpha, magnitude<DT>(a, s, n), S));
     } else {
@@ -732,6 +751,8 @@ int prepare_decode(const fwbf_code *c, const fwbf_params *p, DecodeArgs *out, in
 int try_fast_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int64_t F, int64_t stride,
                     uint32_t *z, int32_t *iters, uint8_t *ok, hipStream_t st, const uint32_t *shift_dev,
                     const uint8_t *skip, int iters_add);
+int try_cyclic_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int64_t F, int64_t stride,
+                      uint32_t *z, int32_t *iters, uint8_t *ok, hipStream_t st);
 
 int prepare_decode(const fwbf_code *c, const fwbf_params *p, DecodeArgs *out, int *T_out, bool force_key64)
 {
@@ -758,6 +779,7 @@ int prepare_decode(const fwbf_code *c, const fwbf_params *p, DecodeArgs *out, in
     a.anum = p->weights == FWBF_WBF ? 0 : p->alpha_num;
     a.aden = p->alpha_den;
     a.flags = p->flags;
+    a.multi = c->multi ? 1 : 0;
 
     int T = p->threads_per_frame;
     if (T == 0) T = c->N <= 2048 ? 64 : c->N <= 4096 ? 128 : c->N <= 16384 ? 256 : 1024;
@@ -856,6 +878,8 @@ extern "C" int fwbf_decode(const fwbf_code *code, const fwbf_params *params, con
     int rc = device_tables(const_cast<fwbf_code *>(code), &t);
     if (rc) return rc;
     if (!(params->flags & FWBF_FLAG_GENERIC_KERNEL)) {
+        rc = try_cyclic_decode(code, params, y_dev, F, y_stride, z_dev, iters_dev, ok_dev, (hipStream_t)stream);
+        if (rc != 0) return rc < 0 ? rc : FWBF_OK;
         rc = try_fast_decode(code, params, y_dev, F, y_stride, z_dev, iters_dev, ok_dev, (hipStream_t)stream,
                              t.shift, nullptr, 0);
         if (rc != 0) return rc < 0 ? rc : FWBF_OK;

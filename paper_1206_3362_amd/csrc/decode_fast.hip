@@ -419,7 +419,7 @@ int try_fast_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int
     if (p->select == FWBF_TOPL) return 0;
     if (p->threads_per_frame != 0 && p->threads_per_frame != 64) return 0;
     const int dv = c->mb, dc = c->nb;
-    if (!(dv == 3 && dc == 6)) return 0;
+    if (c->multi || !(dv == 3 && dc == 6)) return 0;
     for (int v : c->shift)
         if (v < 0) return 0;
     FastArgs a;

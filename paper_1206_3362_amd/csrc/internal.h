@@ -19,9 +19,11 @@ int fail(int code, const std::string &msg);
 int hip_fail(hipError_t e, const char *what);
 
 // Compact adjacency of the QC base, used by the kernels.
-//   col entry (block column j, t-th nonzero block): (i << 24) | (q << 16) | s
-//     where q is the position of block column j in row i's list.
-//   row entry (block row i, q-th nonzero block):   (j << 16) | s
+//   col entry (block column j, t-th circulant permutation): (i << 24) | (q << 16) | s
+//     where q is the position of the same permutation in row i's list.
+//   row entry (block row i, q-th circulant permutation):   (j << 16) | s
+// A block with several shifts contributes one entry per shift, listed in
+// descending shift order; blocks come in ascending block row / column order.
 struct DeviceTables {
     uint32_t *col = nullptr;  // nb * dv_max
     uint32_t *row = nullptr;  // mb * dc_max
@@ -35,7 +37,9 @@ struct DeviceTables {
 struct fwbf_code {
     int Z = 0, mb = 0, nb = 0, N = 0, M = 0;
     int dv_max = 0, dc_max = 0;
-    std::vector<int> shift;  // mb * nb, -1 = zero block
+    std::vector<int> shift;  // mb * nb: the block's largest shift, -1 = zero block
+    std::vector<std::vector<int>> cells;  // mb * nb shift lists, descending
+    bool multi = false;  // some block holds more than one shift
     std::vector<uint32_t> col, row;
     std::vector<uint8_t> coldeg, rowdeg;
 

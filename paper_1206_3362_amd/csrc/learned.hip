@@ -711,7 +711,8 @@ extern "C" int fwbf_decode_learned(const fwbf_code *code, const fwbf_params *pla
     if (rc) return rc;
     if (!code || !plain) return fail(FWBF_E_INVALID, "null code or params");
     if (plain->dtype != FWBF_I8) return fail(FWBF_E_UNSUPPORTED, "the learned decoder takes int8 inputs");
-    if (code->mb != 3 || code->nb != 6) return fail(FWBF_E_UNSUPPORTED, "the learned decoder covers (3,6) base matrices");
+    if (code->mb != 3 || code->nb != 6 || code->multi)
+        return fail(FWBF_E_UNSUPPORTED, "the learned decoder covers (3,6) base matrices of single shifts");
     for (int v : code->shift)
         if (v < 0) return fail(FWBF_E_UNSUPPORTED, "the learned decoder needs a full base (no zero blocks)");
     if (plain->select != FWBF_GROUPS || plain->threads_per_frame != 0)

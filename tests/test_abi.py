@@ -73,6 +73,36 @@ def test_text_roundtrip_and_parse_errors():
     assert e.value.code == fwbf.E_INVALID
 
 
+@pytest.mark.parametrize("s", [2, 3, 4, 5])
+def test_multi_shift_eg_codes_match_oracle(s):
+    """Blocks holding several shifts (the EG codes of Section V): dimensions,
+    rank, info set, encoder and the 4-cycle test agree with the oracle."""
+    from paper_1206_3362_amd import synth
+    txt = synth.eg_code_text(s)
+    g, o = fwbf.Code.from_text(txt), O.Code.from_text(txt)
+    assert (g.N, g.M, g.K, g.dv_max, g.dc_max) == (o.N, o.M, o.K, 2 ** s, 2 ** s)
+    assert not g.has_4cycle()
+    assert np.array_equal(g.info_positions(), o.info_positions())
+    assert np.array_equal(g.encode(11, 0, 8), o.encode(11, 0, 8))
+    assert (O.Code.from_text(g.text()).dense() == o.dense()).all()
+    with pytest.raises(fwbf.FwbfError) as e:
+        g.shifts()
+    assert e.value.code == fwbf.E_UNSUPPORTED
+
+
+def test_multi_shift_four_cycles_and_parse_errors():
+    for txt in ["qc-ldpc v1\nZ 7\nbase 1 1\n0,1,3\n", "qc-ldpc v1\nZ 7\nbase 1 1\n0,1,2\n",
+                "qc-ldpc v1\nZ 7\nbase 2 2\n0,1,3 2\n-1 4,6\n",
+                "qc-ldpc v1\nZ 9\nbase 2 2\n0,3 1\n2 5,8\n"]:
+        g, o = fwbf.Code.from_text(txt), O.Code.from_text(txt)
+        assert g.has_4cycle() == o.violates_rc(), txt
+        assert (O.Code.from_text(g.text()).dense() == o.dense()).all()
+    for bad in ["0,0", "0,7", "0,", ",1", "1,-1"]:
+        with pytest.raises(fwbf.FwbfError) as e:
+            fwbf.Code.from_text(f"qc-ldpc v1\nZ 7\nbase 1 1\n{bad}\n")
+        assert e.value.code == fwbf.E_PARSE
+
+
 def _decode_rc(code, F=1, **kw):
     p = fwbf.DecodeParams(**kw).c()
     L = fwbf.lib()

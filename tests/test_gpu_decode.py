@@ -173,3 +173,91 @@ def test_large_codes(codes, name, dt, G, F, ebn0):
     for sel in (dict(select=0, groups=G), dict(select=0, groups=1)):
         a, b = run_both(codes, name, y, max_iter=100, **sel)
         assert_same(a, b, f"{name} {sel}")
+
+
+@pytest.fixture(scope="module")
+def eg():
+    need_gpu()
+    from paper_1206_3362_amd import fwbf
+    cache = {}
+
+    def get(s):
+        if s not in cache:
+            t = synth.eg_code_text(s)
+            cache[s] = (fwbf.Code.from_text(t), O.Code.from_text(t))
+        return cache[s]
+    return get
+
+
+EG_SELECTS = [dict(select=0, groups=11), dict(select=0, groups=33), dict(select=0, groups=1),
+              dict(select=0, groups=1023), dict(select=1), dict(select=2, lam=10)]
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.int8, np.int16])
+@pytest.mark.parametrize("sel", EG_SELECTS, ids=lambda s: "-".join(f"{k}{v}" for k, v in s.items()))
+def test_eg1023_parity(eg, dt, sel):
+    """EG(1023,781) (one 1023 x 1023 circulant of weight 32, Section V),
+    random codewords at 3.0 and 4.5 dB, K_max = 10 as in Tab. 1, every
+    weight variant: bit-exact with the oracle."""
+    g, o = eg(5)
+    F = 512
+    pool = o.encode(seed=21, first=0, count=64)
+    cb = O.unpack(pool[np.arange(F) % 64], g.N)
+    for ebn0 in (3.0, 4.5):
+        y = synth.awgn_frames(g.N, F, synth.sigma_for(ebn0, g.rate), int(ebn0 * 10) + 5, cb, dt)
+        for w in (0, 1, 2):
+            kw = dict(weights=w, alpha=0.4, alpha_num=2, alpha_den=5, max_iter=10, **sel)
+            print(f"case eg1023 dtype={np.dtype(dt).name} ebn0={ebn0} {kw}", flush=True)
+            assert_same(gpu_decode(g, y, **kw), oracle_decode(o, y, **kw), f"eg1023 {ebn0} {kw}")
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.int8])
+def test_eg255_parity_and_error_patterns(eg, dt):
+    """EG(255,175): noisy frames at 3.5 dB with up to 100 rounds, plus frames
+    of up to 8 uniform-magnitude errors (decoded in max-errors-per-block
+    rounds, a closed form the oracle is pinned to)."""
+    g, o = eg(4)
+    rng = np.random.default_rng(4)
+    F = 1024
+    y = synth.awgn_frames(g.N, F, synth.sigma_for(3.5, g.rate), 35, None, dt)
+    pats = [sorted(rng.choice(g.N, size=1 + f % 8, replace=False).tolist()) for f in range(256)]
+    ye = synth.error_pattern_frames(g.N, pats, 1.0 if dt == np.float32 else 16, dt)
+    for G in (1, 5, 16, 255):
+        for w in (0, 2):
+            kw = dict(weights=w, groups=G, alpha=1.0, alpha_num=1, alpha_den=1, max_iter=100)
+            print(f"case eg255 dtype={np.dtype(dt).name} {kw}", flush=True)
+            assert_same(gpu_decode(g, y, **kw), oracle_decode(o, y, **kw), f"eg255 {kw}")
+            a = gpu_decode(g, ye, **kw)
+            assert_same(a, oracle_decode(o, ye, **kw), f"eg255 patterns {kw}")
+            assert (a[2] == 1).all()
+
+
+def _cyclic_text(N, W, seed):
+    rng = np.random.default_rng(seed)
+    sh = sorted(rng.choice(N, size=W, replace=False).tolist())
+    return f"qc-ldpc v1\nZ {N}\nbase 1 1\n{','.join(map(str, sh))}\n"
+
+
+@pytest.mark.parametrize("text", [synth.eg_code_text(2), synth.eg_code_text(3), _cyclic_text(2047, 9, 1),
+                                  _cyclic_text(1500, 5, 2), _cyclic_text(130, 64, 3)],
+                         ids=["eg15", "eg63", "cyc2047w9", "cyc1500w5", "cyc130w64"])
+@pytest.mark.parametrize("dt", [np.float32, np.int8, np.int16])
+def test_cyclic_kernel_shapes(text, dt):
+    """Single-circulant codes of several lengths (1 to 32 windows of 64 bits,
+    ragged last window) and weights 4 to 64: the cyclic kernel and the
+    generic kernel both match the oracle bit for bit, for block counts 1, 7
+    and N (one bit per block) and the single global choice."""
+    need_gpu()
+    from paper_1206_3362_amd import fwbf
+    g, o = fwbf.Code.from_text(text), O.Code.from_text(text)
+    F = 384
+    rate = max(o.K, 1) / o.N
+    y = synth.awgn_frames(g.N, F, synth.sigma_for(4.0, rate), g.N, None, dt)
+    for sel in (dict(select=0, groups=1), dict(select=0, groups=7), dict(select=0, groups=g.N),
+                dict(select=1)):
+        for w in (0, 2):
+            kw = dict(weights=w, alpha=0.6, alpha_num=3, alpha_den=5, max_iter=25, **sel)
+            print(f"case N={g.N} W={g.dv_max} dtype={np.dtype(dt).name} {kw}", flush=True)
+            want = oracle_decode(o, y, **kw)
+            assert_same(gpu_decode(g, y, **kw), want, f"cyclic {kw}")
+            assert_same(gpu_decode(g, y, flags=fwbf.FLAG_GENERIC_KERNEL, **kw), want, f"generic {kw}")
