@@ -43,7 +43,8 @@ def parse():
     ap.add_argument("--scorer", type=str,
                     default=os.path.join(ROOT, "paper_1206_3362_amd", "scorer_n1008_g32_t16.npz"))
     ap.add_argument("--workload", default="n1008_i8",
-                    choices=["n1008_i8", "n186_f32_wbf", "mixed_f32", "n32400_i16", "sweep_n1008_i8"],
+                    choices=["n1008_i8", "n186_f32_wbf", "mixed_f32", "n32400_i16", "sweep_n1008_i8",
+                             "eg1023_tab1"],
                     help="n1008_i8: the headline workload; the others are further configurations "
                          "measured with the same protocol (one JSON line each)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -295,6 +296,8 @@ def other_workload(a):
                     value=res[6.0]["gbps"], ms_per_step=res[6.0]["ms"], dtype="int32", points=res,
                     config={"workload": "N=32400 (3,30) QC Z=1080 K=29162, int16 x256, G=64, K_max=100, "
                                         "2^15 frames per point", "frames": F})
+    elif a.workload == "eg1023_tab1":
+        eg1023_tab1(a, line)
     else:  # sweep_n1008_i8
         code = fwbf.Code.from_seed(3, 6, 168, 2)
         pool = torch.from_numpy(code.encode(1001, 0, 1024).view(np.int32)).to(dev)
@@ -312,6 +315,63 @@ def other_workload(a):
                     config={"workload": "N=1008 int8 G=8, 9 points 2..6 dB, 2^18 frames per point",
                             "frames": int(len(ebs) * F)})
     print(json.dumps(line), flush=True)
+
+
+# averaged rounds printed in Tab. 1 (K_max = 10, EG(1023,781), 3.0/3.5/4.0/4.5 dB)
+TAB1 = {"MLP-WBF": [8.86, 6.20, 4.54, 3.83], "FWBF p=93": [9.29, 7.37, 6.06, 5.12],
+        "FWBF p=31": [8.62, 5.60, 4.19, 3.64]}
+
+
+def eg1023_tab1(a, line):
+    """Tab. 1 of the paper on the EG(1023,781) code: averaged rounds of FWBF
+    with blocks of p=93 (G=11) and p=31 (G=33) bits, K_max=10, float32
+    BPSK/AWGN, IMWBF metric with alpha swept (the paper does not state it),
+    plus the top-lambda choice (lambda=10) in the MLP-WBF row's place."""
+    import numpy as np
+    import torch
+
+    from paper_1206_3362_amd import fwbf, synth
+    code = fwbf.Code.from_text(synth.eg_code_text(5))
+    N, F = code.N, 1 << 16
+    pool = torch.from_numpy(code.encode(1023, 0, 1024).view(np.int32)).to("cuda")
+    ebs = (3.0, 3.5, 4.0, 4.5)
+    alphas = (0.0, 0.1, 0.2, 0.3, 0.5, 0.8, 1.0, 1.5, 2.0)
+    rows = {}
+    timed = None
+    for k, eb in enumerate(ebs):
+        y = fwbf.channel(N, F, 0, pool, 1300, k, float(synth.sigma_for(eb, code.rate)))
+        cases = [(f"FWBF p={-(-N // G)}", dict(groups=G), al) for G in (11, 33) for al in alphas]
+        cases += [("top-lambda 10", dict(select=fwbf.TOPL, lam=10), al) for al in alphas]
+        for name, sel, al in cases:
+            p = fwbf.DecodeParams(dtype=fwbf.F32, weights=fwbf.IMWBF, max_iter=10, alpha=al, **sel)
+            z, it, ok = fwbf.decode(code, y, p)
+            r = fwbf.count(N, z, pool, 0, it, ok, 10)
+            h = r["hist"]
+            # syndrome evaluations (Step 1 passes): rounds + 1 for a frame
+            # that stops on a zero syndrome before K_max, K_max otherwise
+            passes = float(sum(h[i] * (i + 1) for i in range(10)) + h[10] * 10) / F
+            rows.setdefault(name, {}).setdefault(f"{al:g}", []).append(
+                dict(iters=round(r["iter_sum"] / F, 3), passes=round(passes, 3),
+                     fer=round(r["frame_err"] / F, 5), ber=float(r["bit_err"] / (F * N))))
+            if name == "FWBF p=31" and al == 0.2 and eb == 4.0:
+                timed = (y, p, z, it, ok)
+    y, p, z, it, ok = timed
+    ms = _timed(lambda: fwbf.decode_into(code, y, p, z, it, ok), a.steps, a.warmup)
+    best = {}
+    for name, by_alpha in rows.items():
+        ref = TAB1["MLP-WBF" if name.startswith("top") else name]
+        for count in ("iters", "passes"):
+            err = {al: float(np.sqrt(np.mean([(v[count] - r) ** 2 for v, r in zip(vals, ref)])))
+                   for al, vals in by_alpha.items()}
+            al = min(err, key=err.get)
+            best[f"{name} ({count})"] = dict(alpha=float(al), avg=[v[count] for v in by_alpha[al]],
+                                             paper=ref, rms_diff=round(err[al], 3))
+    line.update(metric="decoded Gb/s, FWBF on EG(1023,781), p=31, alpha 0.2, 4 dB, float32, K_max=10",
+                value=round(F * N / (ms * 1e-3) / 1e9, 3), ms_per_step=round(ms, 4), dtype="f32",
+                tab1_best_alpha=best, tab1_sweep=rows, ebn0=list(ebs),
+                config={"workload": "EG(1023,781) type-I 2-D Euclidean geometry code, random "
+                                    "codewords, BPSK/AWGN 3.0-4.5 dB, f32, IMWBF, K_max=10, "
+                                    "2^16 frames per point", "frames": F})
 
 
 def kernel_sha():
