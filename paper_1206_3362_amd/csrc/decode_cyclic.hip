@@ -6,14 +6,21 @@
 //
 //   - lane l owns bits n = 64 j + l (j < CW): 64 consecutive bits per step
 //     gather from 64 consecutive checks, so the LDS reads never conflict;
-//   - every round recomputes all metrics of eq. (1) (with W ~ sqrt(N) a
-//     round's flips touch nearly every bit anyway);
-//   - each check keeps its two smallest reliabilities with the syndrome bit
-//     in the entry itself (float inputs: as the sign of both, so a term of
-//     eq. (1) is a plain read); a flip toggles its checks with an LDS xor
-//     that returns the old entry, which also updates the unsatisfied count;
-//   - float sums follow ascending check order as the oracle does: bit n
-//     starts at the first shift <= n in a doubled shift table;
+//     the CW bits of a lane advance together, one term of eq. (1) per step;
+//   - every round recomputes all metrics (with W ~ sqrt(N) a round's flips
+//     touch nearly every bit anyway);
+//   - each check keeps its smallest reliability as a float whose sign is the
+//     syndrome bit (set = satisfied), so a term of eq. (1) is a plain read
+//     and a flip toggles a check with one LDS xor that returns the old
+//     entry (which also updates the unsatisfied count);
+//   - float inputs: the entry holds the signed first and second minima and
+//     the index of the bit holding the minimum; sums follow ascending check
+//     order as the oracle does (bit n starts at the first shift <= n, read
+//     from a doubled table of signed offsets that also removes the wrap);
+//   - integer inputs: magnitudes are small integers, exact as floats in any
+//     order, so the IMWBF exclusion becomes a per-bit correction
+//     sum over the checks whose minimum the bit holds of sign * (m2 - m1),
+//     updated with an LDS add whenever such a check toggles;
 //   - the block maximum is a prefix maximum over the 64 lanes of keys
 //     (block << 43 | metric << 11 | 2047 - n): the block index in the top
 //     bits turns the plain scan into a segmented one, and the last lane of
@@ -30,6 +37,7 @@ namespace fwbf {
 namespace {
 
 constexpr uint32_t NONE = 0xFFFFFFFFu;
+constexpr uint32_t SIGN = 0x80000000u;
 constexpr int WMAX = 64;
 
 struct CycArgs {
@@ -38,14 +46,17 @@ struct CycArgs {
     uint32_t *z;
     int32_t *iters;
     uint8_t *ok;
-    int N, W, nwin;
+    int N, W, nwin, Nx;  // Nx = N + 64 CW: length of the doubled arrays
     int p, Geff;
-    uint32_t magP, maskP;
+    uint32_t magP, maskP, magW, maskW;
+    // 32-bit keys (integer metrics): block << (vb + pb) | metric << pb | pmask - pos
+    int key32, vb, pb;
     int single, imwbf, max_iter, cycle_exit;
     float alpha;
     int aden, anum;
     uint32_t bias, zero_val;
-    int o_y, o_ent, o_q, o_z, o_shl, o_gmax, o_prv, lds_bytes;
+    // LDS offsets in bytes (the check entries sit at offset 0)
+    int o_am, o_tab, o_info, o_corr, o_y, o_z, o_gmax, o_prv, o_list, o_shl, lds_bytes;
     uint16_t sh[WMAX];  // descending
 };
 
@@ -82,144 +93,213 @@ __device__ __forceinline__ unsigned long long scan_max(unsigned long long v)
     return v;
 }
 
+__device__ __forceinline__ uint32_t scan_max32(uint32_t v)
+{
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, true));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, true));
+    return v;
+}
+
 __device__ __forceinline__ int wave_sum(int v)
 {
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
     return v;
 }
 
-// Check entries.  f32: {ws1, ws2} bit patterns, the signed weights of the
-// term of eq. (1) (negative = satisfied check), argmin list position in a
-// byte array.  i16: {m1 | m2 << 16, q | s << 31}.  i8: m1 | m2 << 8 | q << 16
-// | s << 31.
-template <int DT> struct CT;
-template <> struct CT<FWBF_F32> {
-    using Y = float;
-    using E = unsigned long long;
-    static constexpr E TOGGLE = 0x8000000080000000ull;
-    static constexpr bool isf = true;
-};
-template <> struct CT<FWBF_I16> {
-    using Y = int16_t;
-    using E = unsigned long long;
-    static constexpr E TOGGLE = 1ull << 63;
-    static constexpr bool isf = false;
-};
-template <> struct CT<FWBF_I8> {
-    using Y = int8_t;
-    using E = uint32_t;
-    static constexpr E TOGGLE = 1u << 31;
-    static constexpr bool isf = false;
-};
-
-// syndrome bit of a check entry (float entries: a clear sign bit)
-template <int DT>
-__device__ __forceinline__ bool unsat(typename CT<DT>::E e)
-{
-    if constexpr (DT == FWBF_I8) return e >> 31;
-    else if constexpr (DT == FWBF_I16) return e >> 63;
-    else return !(e >> 63);
-}
+// Y: input type; K: staged value (float: y itself; integer: the check-minimum
+// key |y| << 7 | [y < 0] << 6, to which the member position t is or-ed)
+template <int DT> struct CY;
+template <> struct CY<FWBF_F32> { using Y = float; using K = float; };
+template <> struct CY<FWBF_I16> { using Y = int16_t; using K = uint32_t; };
+template <> struct CY<FWBF_I8> { using Y = int8_t; using K = uint16_t; };
 
 template <int DT, int CW>
 __global__ __launch_bounds__(64) void cyclic_kernel(CycArgs a)
 {
-    using T = CT<DT>;
-    using Y = typename T::Y;
-    using E = typename T::E;
+    using Y = typename CY<DT>::Y;
+    using K = typename CY<DT>::K;
+    constexpr bool ISF = DT == FWBF_F32;
     extern __shared__ __align__(16) unsigned char smem[];
-    Y *yv = (Y *)(smem + a.o_y);
-    E *ent = (E *)(smem + a.o_ent);
-    uint8_t *qa = smem + a.o_q;
+    // check entries at offset 0.  float: {ws1, ws2} per check; integer:
+    // ws1 per check, stored for every index i < Nx as check i mod N so that
+    // n + N - s needs no wrap and step j of a lane is an immediate offset
+    unsigned long long *ent = (unsigned long long *)smem;
+    uint32_t *ws = (uint32_t *)smem;
+    uint16_t *am = (uint16_t *)(smem + a.o_am);      // float: bit holding the minimum
+    int32_t *tab = (int32_t *)(smem + a.o_tab);      // float: -s_t, then N - s_t
+    uint32_t *info = (uint32_t *)(smem + a.o_info);  // integer IMWBF: bit | (m2 - m1) << 16
+    float *corr = (float *)(smem + a.o_corr);        // integer IMWBF: per-bit correction
+    K *yv = (K *)(smem + a.o_y);                     // staged y_(i mod N) for i < Nx
     uint32_t *zw = (uint32_t *)(smem + a.o_z);
-    uint16_t *shl = (uint16_t *)(smem + a.o_shl);
     unsigned long long *gmax = (unsigned long long *)(smem + a.o_gmax);
     uint32_t *prv = (uint32_t *)(smem + a.o_prv);
+    uint32_t *gmax32 = (uint32_t *)gmax;
+    uint32_t *list = (uint32_t *)(smem + a.o_list);  // bits flipped this round
+    uint16_t *shl = (uint16_t *)(smem + a.o_shl);    // s_t
 
     const int lane = threadIdx.x;
-    const int N = a.N, W = a.W, nwin = a.nwin;
-    for (int t = lane; t < 2 * W; t += 64) shl[t] = a.sh[t < W ? t : t - W];
-    // rotation start of every owned bit: the number of shifts above n
+    const int N = a.N, W = a.W, nwin = a.nwin, Nx = a.Nx;
+    const bool icorr = !ISF && a.imwbf;
+    const int shv = lane < W ? (int)a.sh[lane] : 0;  // s_t in lane t (read back with readlane)
+    if constexpr (ISF)
+        for (int t = lane; t < 2 * W; t += 64) tab[t] = t < W ? -(int)a.sh[t] : N - (int)a.sh[t - W];
+    // owned bits (tail lanes address bit N - 1 and drop the result), and for
+    // float inputs the rotation start: the number of shifts above n
+    int nc[CW];
     uint32_t ust[CW];
 #pragma unroll
     for (int j = 0; j < CW; j++) {
-        const int n = 64 * j + lane;
+        nc[j] = min(64 * j + lane, N - 1);
         uint32_t u = 0;
-        if constexpr (T::isf)
-            for (int t = 0; t < W; t++) u += (int)a.sh[t] > n;
+        if constexpr (ISF)
+            for (int t = 0; t < W; t++) u += __builtin_amdgcn_readlane(shv, t) > nc[j];
         ust[j] = u;
+    }
+    for (int t = lane; t < W; t += 64) shl[t] = a.sh[t];
+    // frame-independent part of every key, and which lanes end a block
+    // segment inside their window (bit j of lastm)
+    // (32-bit keys: block << (vb + pb) | pmask - pos; 64-bit keys: the block)
+    uint32_t kc[CW];
+    uint32_t lastm = 0;
+#pragma unroll
+    for (int j = 0; j < CW; j++) {
+        const int n = 64 * j + lane;
+        kc[j] = 0;
+        if (j < nwin && n < N) {
+            const uint32_t g = fdiv(n, a.magP, a.maskP);
+            if (a.key32) kc[j] = ((uint32_t)g << (a.vb + a.pb)) | (((1u << a.pb) - 1) - (n - g * a.p));
+            else kc[j] = g;
+            const bool last = lane == 63 || n + 1 >= N || fdiv(n + 1, a.magP, a.maskP) != g;
+            lastm |= (uint32_t)last << j;
+        }
     }
     const int NW = (N + 31) >> 5;
 
     const FrameRange fr = xcd_frames(a.F);
-    for (int64_t f = fr.first; f < fr.end; f += fr.step) {
-        const Y *yrow = (const Y *)a.y + f * a.stride;
-        __syncthreads();
-        // ---- received values, z_0 = [y < 0] (Section III, Initialization) --
-        float yabs[CW];
+    // received values of the next frame, loaded while the current one decodes
+    Y ynext[CW];
+    auto prefetch = [&](int64_t ff) {
+        const Y *yr = (const Y *)a.y + ff * a.stride;
 #pragma unroll
         for (int j = 0; j < CW; j++) {
             const int n = 64 * j + lane;
-            Y v = (Y)0;
-            if (j < nwin && n < N) v = yrow[n];
+            ynext[j] = (j < nwin && n < N) ? yr[n] : (Y)0;
+        }
+    };
+    constexpr bool PF = CW <= 16;  // register budget
+    if (PF && fr.first < fr.end) prefetch(fr.first);
+    for (int64_t f = fr.first; f < fr.end; f += fr.step) {
+        Y ycur[CW];
+        if (PF) {
+#pragma unroll
+            for (int j = 0; j < CW; j++) ycur[j] = ynext[j];
+            if (f + fr.step < fr.end) prefetch(f + fr.step);
+        } else {
+            prefetch(f);
+#pragma unroll
+            for (int j = 0; j < CW; j++) ycur[j] = ynext[j];
+        }
+        __syncthreads();
+        // ---- received values, z_0 = [y < 0] (Section III, Initialization) --
+#pragma unroll
+        for (int j = 0; j < CW; j++) {
+            const int n = 64 * j + lane;
+            const Y v = ycur[j];
             if (j < nwin) {
-                if (n < N) yv[n] = v;
+                K kv;
+                if constexpr (ISF) kv = v;
+                else kv = (K)(((uint32_t)(v < 0 ? -(int)v : (int)v) << 7) | ((uint32_t)(v < 0) << 6));
+                if (n < N)
+                    for (int i = n; i < Nx; i += N) yv[i] = kv;
                 const unsigned long long b = __ballot(v < (Y)0);
                 if (lane == 0) { zw[2 * j] = (uint32_t)b; zw[2 * j + 1] = (uint32_t)(b >> 32); }
             }
-            if constexpr (T::isf) yabs[j] = fabsf((float)v);
-            else yabs[j] = (float)(v < 0 ? -(int)v : (int)v);
         }
         for (int g = lane; g < a.Geff; g += 64) { gmax[g] = 0; prv[g] = NONE; }
+        if (icorr)
+            for (int n = lane; n < N; n += 64) corr[n] = 0.0f;
         __syncthreads();
 
         // ---- check minima and the syndrome s_0 ---------------------------
+        // check m = 64 j + lane holds bits m + s_t (< Nx, no wrap needed);
+        // four windows at a time
         int weight = 0;
-        for (int j = 0; j < nwin; j++) {
-            const int m = 64 * j + lane;
-            const bool valid = m < N;
-            uint32_t par = 0, q = 0;
-            if constexpr (T::isf) {
-                float m1 = __builtin_inff(), m2 = __builtin_inff();
-                if (valid) {
-                    for (int t = 0; t < W; t++) {
-                        int n = m + (int)a.sh[t];
-                        n -= n >= N ? N : 0;
-                        const float v = yv[n];
+        for (int j0 = 0; j0 < nwin; j0 += 4) {
+            float m1[4], m2[4];
+            uint32_t q[4], par[4];
+            if constexpr (ISF) {
+                unsigned long long pm[4];
+#pragma unroll
+                for (int jj = 0; jj < 4; jj++) { m1[jj] = __builtin_inff(); m2[jj] = __builtin_inff(); q[jj] = 0; pm[jj] = 0; }
+                for (int t = 0; t < W; t++) {
+                    const int base = lane + __builtin_amdgcn_readlane(shv, t) + 64 * j0;
+#pragma unroll
+                    for (int jj = 0; jj < 4; jj++) {
+                        const float v = yv[base + 64 * jj];
                         const float av = fabsf(v);
-                        par ^= (uint32_t)(v < 0.0f);
-                        const bool lt = av < m1;
-                        m2 = lt ? m1 : fminf(m2, av);
-                        q = lt ? (uint32_t)t : q;
-                        m1 = lt ? av : m1;
+                        pm[jj] ^= __ballot(v < 0.0f);
+                        q[jj] = av < m1[jj] ? (uint32_t)t : q[jj];
+                        m2[jj] = __builtin_amdgcn_fmed3f(m1[jj], m2[jj], av);  // m1 <= m2
+                        m1[jj] = fminf(m1[jj], av);
                     }
-                    const uint32_t sg = par ? 0u : 0x80000000u;
-                    const uint32_t b1 = __float_as_uint(m1) | sg;
-                    const uint32_t b2 = a.imwbf ? (__float_as_uint(m2) | sg) : b1;
-                    ent[m] = ((unsigned long long)b2 << 32) | b1;
-                    qa[m] = (uint8_t)q;
                 }
+#pragma unroll
+                for (int jj = 0; jj < 4; jj++) par[jj] = (uint32_t)(pm[jj] >> lane) & 1u;
             } else {
-                uint32_t m1 = 0xFFFFFFFFu, m2 = 0xFFFFFFFFu;
-                if (valid) {
-                    for (int t = 0; t < W; t++) {
-                        int n = m + (int)a.sh[t];
-                        n -= n >= N ? N : 0;
-                        const int v = (int)yv[n];
-                        const uint32_t av = (uint32_t)(v < 0 ? -v : v);
-                        par ^= (uint32_t)(v < 0);
-                        const bool lt = av < m1;
-                        m2 = lt ? m1 : min(m2, av);
-                        q = lt ? (uint32_t)t : q;
-                        m1 = lt ? av : m1;
+                // key | t: the minimum key gives m1 and its position; the
+                // second smallest key gives m2 (median of m1, m2, key)
+                uint32_t k1[4], k2[4], px[4];
+#pragma unroll
+                for (int jj = 0; jj < 4; jj++) { k1[jj] = 0xFFFFFFFFu; k2[jj] = 0xFFFFFFFFu; px[jj] = 0; }
+                for (int t = 0; t < W; t++) {
+                    const int base = lane + __builtin_amdgcn_readlane(shv, t) + 64 * j0;
+#pragma unroll
+                    for (int jj = 0; jj < 4; jj++) {
+                        const uint32_t kv = yv[base + 64 * jj];
+                        px[jj] ^= kv;
+                        const uint32_t key = kv | (uint32_t)t;
+                        k2[jj] = max(k1[jj], min(k2[jj], key));
+                        k1[jj] = min(k1[jj], key);
                     }
-                    if constexpr (DT == FWBF_I8)
-                        ent[m] = m1 | (m2 << 8) | (q << 16) | (par << 31);
-                    else
-                        ent[m] = ((unsigned long long)(q | (par << 31)) << 32) | (m1 | (m2 << 16));
+                }
+#pragma unroll
+                for (int jj = 0; jj < 4; jj++) {
+                    m1[jj] = (float)(k1[jj] >> 7);
+                    m2[jj] = (float)(k2[jj] >> 7);
+                    q[jj] = k1[jj] & 63u;
+                    par[jj] = (px[jj] >> 6) & 1u;
                 }
             }
-            weight += __popcll(__ballot(valid && par));
+#pragma unroll
+            for (int jj = 0; jj < 4; jj++) {
+                const int j = j0 + jj;
+                const int m = 64 * j + lane;
+                const bool valid = m < N;
+                // bit holding the minimum (the permute runs with every lane active)
+                int an = m + __builtin_amdgcn_ds_bpermute(4 * (int)q[jj], shv);
+                an -= an >= N ? N : 0;
+                if (valid) {
+                    const uint32_t sg = par[jj] ? 0u : SIGN;
+                    const uint32_t b1 = __float_as_uint(m1[jj]) | sg;
+                    if constexpr (ISF) {
+                        const uint32_t b2 = a.imwbf ? (__float_as_uint(m2[jj]) | sg) : b1;
+                        ent[m] = ((unsigned long long)b2 << 32) | b1;
+                        am[m] = (uint16_t)an;
+                    } else {
+                        for (int i = m; i < Nx; i += N) ws[i] = b1;
+                        if (icorr) {
+                            const uint32_t d = (uint32_t)(m2[jj] - m1[jj]);
+                            info[m] = (uint32_t)an | (d << 16);
+                            if (d) atomicAdd(&corr[an], par[jj] ? (float)d : -(float)d);
+                        }
+                    }
+                }
+                weight += __popcll(__ballot(valid && par[jj]));
+            }
         }
         __syncthreads();
 
@@ -228,72 +308,81 @@ __global__ __launch_bounds__(64) void cyclic_kernel(CycArgs a)
             okf = weight == 0;
         } else {
             for (;;) {
-                // ---- Step 2: metrics of eq. (1), block maxima ---------------
+                // ---- Step 2: metrics of eq. (1) of every owned bit -----------
+                float S[CW];
+                if constexpr (ISF) {
+#pragma unroll
+                    for (int j = 0; j < CW; j++) S[j] = 0.0f;
+                    for (int v = 0; v < W; v++) {
+#pragma unroll
+                        for (int j = 0; j < CW; j++) {
+                            const int m = nc[j] + tab[ust[j] + v];
+                            const unsigned long long e = ent[m];
+                            const uint32_t bits = am[m] == (uint32_t)nc[j] ? (uint32_t)(e >> 32) : (uint32_t)e;
+                            const float term = __uint_as_float(bits);
+                            S[j] = v == 0 ? term : S[j] + term;
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < CW; j++) S[j] = icorr ? corr[nc[j]] : 0.0f;
+                    for (int t = 0; t < W; t++) {
+                        const int base = lane + N - __builtin_amdgcn_readlane(shv, t);
+#pragma unroll
+                        for (int j = 0; j < CW; j++) S[j] += __uint_as_float(ws[base + 64 * j]);
+                    }
+                }
+                // ---- block maxima ------------------------------------------
 #pragma unroll
                 for (int j = 0; j < CW; j++) {
-                    if (j >= nwin) break;
-                    const int n = 64 * j + lane;
-                    unsigned long long key = 0;
-                    uint32_t g = 0;
-                    if (n < N) {
-                        uint32_t val;
-                        if constexpr (T::isf) {
-                            float S = 0.0f;
-                            const uint32_t u = ust[j];
-                            for (int v = 0; v < W; v++) {
-                                const uint32_t idx = u + v;
-                                int m = n - (int)shl[idx];
-                                m += m < 0 ? N : 0;
-                                const E e = ent[m];
-                                uint32_t bits = (uint32_t)e;
-                                if (a.imwbf) {
-                                    const uint32_t t = idx - (idx >= (uint32_t)W ? W : 0);
-                                    bits = qa[m] == t ? (uint32_t)(e >> 32) : bits;
-                                }
-                                const float term = __uint_as_float(bits);
-                                S = v == 0 ? term : S + term;
-                            }
-                            val = orderable(__builtin_fmaf(-a.alpha, yabs[j], S));
-                        } else {
-                            int S = 0;
-                            for (int t = 0; t < W; t++) {
-                                int m = n - (int)a.sh[t];
-                                m += m < 0 ? N : 0;
-                                const E e = ent[m];
-                                int w;
-                                if constexpr (DT == FWBF_I8) {
-                                    const uint32_t qq = (e >> 16) & 0x3F;
-                                    w = (int)((a.imwbf && qq == (uint32_t)t) ? (e >> 8) & 0xFF : e & 0xFF);
-                                } else {
-                                    const uint32_t lo = (uint32_t)e, qq = (uint32_t)(e >> 32) & 0x3F;
-                                    w = (int)((a.imwbf && qq == (uint32_t)t) ? lo >> 16 : lo & 0xFFFF);
-                                }
-                                S += unsat<DT>(e) ? w : -w;
-                            }
-                            val = (uint32_t)(a.aden * S - a.anum * (int)yabs[j] + (int)a.bias);
-                        }
-                        g = fdiv(n, a.magP, a.maskP);
-                        key = ((unsigned long long)g << 43) | ((unsigned long long)val << 11) | (uint32_t)(2047 - n);
+                    const bool valid = 64 * j + lane < N;
+                    const K yn = yv[64 * j + lane];  // |y_n| from the staged frame
+                    uint32_t val;
+                    if constexpr (ISF) val = orderable(__builtin_fmaf(-a.alpha, fabsf(yn), S[j]));
+                    else val = (uint32_t)(__mul24(a.aden, (int)S[j]) - __mul24(a.anum, (int)((uint32_t)yn >> 7)) + (int)a.bias);
+                    const bool last = (lastm >> j) & 1;
+                    if (!ISF && a.key32) {
+                        const uint32_t key = valid ? (kc[j] | (val << a.pb)) : 0u;
+                        const uint32_t best = scan_max32(key);
+                        if (last) atomicMax(&gmax32[kc[j] >> (a.vb + a.pb)], best);
+                    } else {
+                        const unsigned long long key =
+                            valid ? (((unsigned long long)kc[j] << 43) | ((unsigned long long)val << 11) |
+                                     (uint32_t)(2047 - 64 * j - lane))
+                                  : 0ull;
+                        const unsigned long long best = scan_max(key);
+                        if (last) atomicMax(&gmax[kc[j]], best);
                     }
-                    const unsigned long long best = scan_max(key);
-                    // last lane of its block segment inside this window
-                    const bool last = n < N && (lane == 63 || n + 1 >= N || fdiv(n + 1, a.magP, a.maskP) != g);
-                    if (last) atomicMax(&gmax[g], best);
                 }
                 __syncthreads();
 
-                // ---- choose at most one bit per block ----------------------
-                int any = 0, dif = 0;
-                for (int g = lane; g < a.Geff; g += 64) {
-                    const unsigned long long key = gmax[g];
-                    gmax[g] = 0;
-                    const uint32_t val = (uint32_t)(key >> 11);
-                    const uint32_t n = 2047u - (uint32_t)(key & 2047u);
-                    const bool flip = a.single || val > a.zero_val;
-                    const uint32_t cur = flip ? n : NONE;
-                    dif |= cur != prv[g];
-                    any |= flip;
-                    prv[g] = cur;
+                // ---- choose at most one bit per block; list the flips ------
+                int any = 0, dif = 0, nflip = 0;
+                for (int g0 = 0; g0 < a.Geff; g0 += 64) {
+                    const int g = g0 + lane;
+                    uint32_t cur = NONE;
+                    if (g < a.Geff) {
+                        uint32_t val, n;
+                        if (!ISF && a.key32) {
+                            const uint32_t key = gmax32[g];
+                            gmax32[g] = 0;
+                            val = (key >> a.pb) & ((1u << a.vb) - 1);
+                            n = (uint32_t)g * a.p + (((1u << a.pb) - 1) - (key & ((1u << a.pb) - 1)));
+                        } else {
+                            const unsigned long long key = gmax[g];
+                            gmax[g] = 0;
+                            val = (uint32_t)(key >> 11);
+                            n = 2047u - (uint32_t)(key & 2047u);
+                        }
+                        const bool flip = a.single || val > a.zero_val;
+                        cur = flip ? n : NONE;
+                        dif |= cur != prv[g];
+                        any |= flip;
+                        prv[g] = cur;
+                    }
+                    const unsigned long long fm = __ballot(cur != NONE);
+                    if (cur != NONE) list[nflip + __popcll(fm & ((1ull << lane) - 1))] = cur;
+                    nflip += __popcll(fm);
                 }
                 const bool anyf = __ballot(any) != 0, diff = __ballot(dif) != 0;
                 if (a.cycle_exit) {
@@ -314,17 +403,34 @@ __global__ __launch_bounds__(64) void cyclic_kernel(CycArgs a)
                     }
                 }
                 // ---- flip; toggle the checks of every flipped bit -----------
-                int delta = 0;
-                for (int g = lane; g < a.Geff; g += 64) {
-                    const uint32_t n = prv[g];
-                    if (n == NONE) continue;
+                // (one (bit, check) pair per lane and step)
+                __syncthreads();
+                for (int i = lane; i < nflip; i += 64) {
+                    const uint32_t n = list[i];
                     atomicXor(&zw[n >> 5], 1u << (n & 31));
-                    for (int t = 0; t < W; t++) {
-                        int m = (int)n - (int)a.sh[t];
-                        m += m < 0 ? N : 0;
-                        const E old = atomicXor(&ent[m], T::TOGGLE);
-                        delta += unsat<DT>(old) ? -1 : 1;
+                }
+                int delta = 0;
+                const int ntask = nflip * W;
+                for (int id = lane; id < ntask; id += 64) {
+                    const uint32_t fi = fdiv((uint32_t)id, a.magW, a.maskW);
+                    const uint32_t n = list[fi];
+                    int m = (int)n - (int)shl[id - (int)fi * W];
+                    m += m < 0 ? N : 0;
+                    bool was_unsat;
+                    if constexpr (ISF) {
+                        const unsigned long long old = atomicXor(&ent[m], ((unsigned long long)SIGN << 32) | SIGN);
+                        was_unsat = !((uint32_t)old & SIGN);
+                    } else {
+                        const uint32_t old = atomicXor(&ws[m], SIGN);
+                        for (int i = m + N; i < Nx; i += N) atomicXor(&ws[i], SIGN);
+                        was_unsat = !(old & SIGN);
+                        if (icorr) {
+                            const uint32_t inf = info[m];
+                            const float d2 = (float)(2u * (inf >> 16));
+                            if (inf >> 16) atomicAdd(&corr[inf & 0xFFFFu], was_unsat ? -d2 : d2);
+                        }
                     }
+                    delta += was_unsat ? -1 : 1;
                 }
                 weight += wave_sum(delta);
                 k += 1;
@@ -403,6 +509,8 @@ int try_cyclic_decode(const fwbf_code *c, const fwbf_params *p, const void *y, i
     a.alpha = p->weights == FWBF_WBF ? 0.0f : p->alpha;
     a.aden = p->alpha_den;
     a.anum = p->weights == FWBF_WBF ? 0 : p->alpha_num;
+    if (W <= 1) { a.magW = 0; a.maskW = 0xFFFFFFFFu; }
+    else { a.magW = (uint32_t)(((1ULL << 32) + W - 1) / W); a.maskW = 0; }
     if (p->dtype == FWBF_F32) {
         a.bias = 0;
         a.zero_val = 0x80000000u;  // orderable(+0)
@@ -414,21 +522,32 @@ int try_cyclic_decode(const fwbf_code *c, const fwbf_params *p, const void *y, i
         while ((1LL << (vb - 1)) <= maxE) vb++;
         a.bias = 1u << (vb - 1);
         a.zero_val = a.bias;
+        int gbits = 0, pbits = 0;
+        while ((1 << gbits) < a.Geff) gbits++;
+        while ((1 << pbits) < a.p) pbits++;
+        a.vb = vb;
+        a.pb = pbits;
+        a.key32 = gbits + vb + pbits <= 32 && vb + pbits < 32;  // the block index is key >> (vb + pb)
     }
     // shifts of the single block, descending
     const auto &cell = c->cells[0];
     for (int t = 0; t < W; t++) a.sh[t] = (uint16_t)cell[t];
-    const int esz = p->dtype == FWBF_I8 ? 1 : p->dtype == FWBF_I16 ? 2 : 4;
-    const int entsz = p->dtype == FWBF_I8 ? 4 : 8;
+    const int esz = p->dtype == FWBF_I8 ? 2 : 4;  // staged value per bit
+    const bool isf = p->dtype == FWBF_F32, icorr = !isf && a.imwbf;
     int off = 0;
     auto take = [&](int bytes, int align) { off = (off + align - 1) / align * align; int o = off; off += bytes; return o; };
-    a.o_y = take(esz * c->N, 16);
-    a.o_ent = take(entsz * c->N, 8);
-    a.o_q = take(p->dtype == FWBF_F32 ? c->N : 0, 4);
+    a.Nx = c->N + 64 * CW;
+    take(isf ? 8 * c->N : 4 * a.Nx, 16);  // check entries at offset 0
+    a.o_am = take(isf ? 2 * c->N : 0, 4);
+    a.o_tab = take(isf ? 8 * W : 0, 4);
+    a.o_info = take(icorr ? 4 * c->N : 0, 4);
+    a.o_corr = take(icorr ? 4 * c->N : 0, 4);
+    a.o_y = take(esz * a.Nx, 16);
     a.o_z = take(8 * a.nwin, 8);
-    a.o_shl = take(4 * W, 4);
     a.o_gmax = take(8 * a.Geff, 8);
     a.o_prv = take(4 * a.Geff, 4);
+    a.o_list = take(4 * a.Geff, 4);
+    a.o_shl = take(2 * W, 4);
     a.lds_bytes = (off + 15) / 16 * 16;
     if (a.lds_bytes > 64 * 1024) return 0;
     a.y = y; a.F = F; a.stride = stride;
