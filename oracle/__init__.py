@@ -24,7 +24,7 @@ _SRC = os.path.join(_HERE, "fwbf_oracle.c")
 _LIB = os.path.join(_HERE, "_fwbf_oracle.so")
 
 WBF, MWBF, IMWBF = 0, 1, 2
-GROUPS, SINGLE, TOPL = 0, 1, 2
+GROUPS, SINGLE, TOPL, STRIDED = 0, 1, 2, 3
 F32, I8, I16 = 0, 1, 2
 _NP = {F32: np.float32, I8: np.int8, I16: np.int16}
 
@@ -86,6 +86,7 @@ def lib():
         L.or_channel.argtypes = [i32, i64, i64, vp, i64, u64, C.c_uint32, C.c_double, C.c_double,
                                  i32, vp, vp]
         L.or_count.argtypes = [i32, i64, i64, vp, vp, i64, vp, vp, i32, vp, vp]
+        L.or_decode_minsum.argtypes = [vp, i32, C.c_float, i32, vp, i64, i64, vp, vp, vp, i32]
         _lib = L
     return _lib
 
@@ -225,6 +226,23 @@ def decode(code: Code, y: np.ndarray, *, weights=IMWBF, select=GROUPS, G=8, lam=
     nt = threads or min(os.cpu_count() or 1, 16)
     _check(lib().or_decode(code._h, weights, select, G, lam, max_iter, alpha, alpha_num, alpha_den,
                            dt, _ptr(y), F, N, _ptr(z), _ptr(it), _ptr(ok), nt), "decode")
+    return z, it, ok
+
+
+def decode_minsum(code: Code, y: np.ndarray, *, offset=False, c=0.75, max_iter=20, threads=None):
+    """Flooding min-sum BP over float frames y[F][N]: normalised (R = c*min)
+    or offset (R = max(min - c, 0)); returns (z packed, iterations, ok)."""
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    if y.ndim == 1:
+        y = y[None]
+    F, N = y.shape
+    assert N == code.N
+    z = np.zeros((F, (N + 31) // 32), np.uint32)
+    it = np.zeros(F, np.int32)
+    ok = np.zeros(F, np.uint8)
+    nt = threads or min(os.cpu_count() or 1, 16)
+    _check(lib().or_decode_minsum(code._h, int(bool(offset)), c, max_iter, _ptr(y), F, N, _ptr(z),
+                                  _ptr(it), _ptr(ok), nt), "decode_minsum")
     return z, it, ok
 
 

@@ -25,6 +25,8 @@
  *   - z_0,n = 1 iff y_n < 0 (Section III, Initialization; sgn(0) taken as +);
  *   - blocks: p = ceil(N/G), block g covers [g p, min(N,(g+1)p)), the short
  *     last block stands for the paper's "null" metric padding (footnote 1);
+ *     the strided variant takes block g = {n : n mod G = g} instead (the
+ *     blocks an interleaver of depth G would make contiguous, Section III);
  *   - all blocks choose from the same syndrome (one syndrome per round);
  *   - ties are broken by the lowest bit index;
  *   - GROUPS/TOPL flip only if the metric is > 0 (Section III, Step 2),
@@ -52,7 +54,7 @@
 #define OR_ENOMEM (-4)
 
 enum { W_WBF = 0, W_MWBF = 1, W_IMWBF = 2 };
-enum { S_GROUPS = 0, S_SINGLE = 1, S_TOPL = 2 };
+enum { S_GROUPS = 0, S_SINGLE = 1, S_TOPL = 2, S_STRIDED = 3 };
 enum { D_F32 = 0, D_I8 = 1, D_I16 = 2 };
 
 typedef struct {
@@ -627,6 +629,13 @@ static void decode_frame(const ocode *c, const oparams *P, int dtype, const void
                     if (better(w, isf, n, b)) b = n;
                 if (positive(w, isf, b)) w->flip[nf++] = b;
             }
+        } else if (P->select == S_STRIDED) {
+            for (int g = 0; g < P->G; g++) {
+                int b = g;
+                for (int n = g + P->G; n < N; n += P->G)
+                    if (better(w, isf, n, b)) b = n;
+                if (positive(w, isf, b)) w->flip[nf++] = b;
+            }
         } else if (P->select == S_SINGLE) {
             int b = 0;
             for (int n = 1; n < N; n++)
@@ -662,8 +671,8 @@ static int params_valid(const ocode *c, const oparams *P, int dtype)
 {
     if (dtype < D_F32 || dtype > D_I16) return 0;
     if (P->weights < W_WBF || P->weights > W_IMWBF) return 0;
-    if (P->select < S_GROUPS || P->select > S_TOPL) return 0;
-    if (P->select == S_GROUPS && (P->G < 1 || P->G > c->N)) return 0;
+    if (P->select < S_GROUPS || P->select > S_STRIDED) return 0;
+    if ((P->select == S_GROUPS || P->select == S_STRIDED) && (P->G < 1 || P->G > c->N)) return 0;
     if (P->select == S_TOPL && P->lambda < 1) return 0;
     if (P->max_iter < 0) return 0;
     if (dtype != D_F32 && P->alpha_den < 1) return 0;
@@ -844,4 +853,136 @@ int or_count(int N, int64_t F, int64_t f0, const uint32_t *z, const uint32_t *po
         if (it >= 0 && it <= max_iter) hist[it] += 1;
     }
     return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Min-sum belief propagation: the BP reference decoder the paper compares  */
+/* FWBF with (Section I names normalised and offset min-sum; Section V      */
+/* reports BP 0.5 dB ahead of FWBF).  The paper gives no equations for it;  */
+/* this is the textbook flooding schedule, float32, written out literally:  */
+/*   iteration i >= 1, every edge (m, n):                                   */
+/*     Q_{n,m} = P_n - R_{m,n}       (P, R of iteration i-1; R = 0, P = L)  */
+/*     R_{m,n} = s * c * min |Q_{n',m}|   over n' in N(m)\n, s = product of */
+/*               the signs of those Q (sign -1 iff Q < 0)                    */
+/*       normalised: c * min (one float product), offset: max(min - c, 0)   */
+/*     P_n = L_n + sum_{m in M(n)} R_{m,n}, in ascending m                  */
+/*     z_n = [P_n < 0]; stop on a zero syndrome or after K_max iterations.  */
+/* L_n = y_n (the channel LLR up to a positive factor, which min-sum does   */
+/* not need).  Iterations are counted like the flip rounds of FWBF: 0 when  */
+/* z_0 = [y < 0] already satisfies H.                                       */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const ocode *c;
+    int offset, max_iter;
+    float cst;
+    const float *y;
+    int64_t f0, f1, stride;
+    uint32_t *z;
+    int32_t *iters;
+    uint8_t *ok;
+    int rc;
+} msjob;
+
+static int ms_syndrome_zero(const ocode *c, const uint8_t *z)
+{
+    for (int m = 0; m < c->M; m++) {
+        int x = 0;
+        for (int t = c->row_ptr[m]; t < c->row_ptr[m + 1]; t++) x ^= z[c->row_bits[t]];
+        if (x) return 0;
+    }
+    return 1;
+}
+
+static void *ms_worker(void *arg)
+{
+    msjob *j = (msjob *)arg;
+    const ocode *c = j->c;
+    const int N = c->N, M = c->M, E = c->row_ptr[M];
+    float *L = (float *)malloc(sizeof(float) * N), *P = (float *)malloc(sizeof(float) * N);
+    float *R = (float *)malloc(sizeof(float) * (E ? E : 1)), *Rn = (float *)malloc(sizeof(float) * (E ? E : 1));
+    float *Q = (float *)malloc(sizeof(float) * (E ? E : 1));
+    uint8_t *z = (uint8_t *)malloc(N);
+    /* edge index of (m, n) seen from the bit side: for bit n, its checks in
+       ascending order and the edge of each */
+    int *bedge = (int *)malloc(sizeof(int) * (E ? E : 1));
+    if (!L || !P || !R || !Rn || !Q || !z || !bedge) { j->rc = OR_ENOMEM; goto out; }
+    for (int n = 0; n < N; n++)
+        for (int u = c->col_ptr[n]; u < c->col_ptr[n + 1]; u++) {
+            int m = c->col_chks[u], e = -1;
+            for (int t = c->row_ptr[m]; t < c->row_ptr[m + 1]; t++)
+                if (c->row_bits[t] == n) e = t;
+            bedge[u] = e;
+        }
+    for (int64_t f = j->f0; f < j->f1; f++) {
+        const float *y = j->y + f * j->stride;
+        for (int n = 0; n < N; n++) { L[n] = y[n]; P[n] = y[n]; z[n] = y[n] < 0.0f; }
+        for (int e = 0; e < E; e++) R[e] = 0.0f;
+        int it = 0, okf = ms_syndrome_zero(c, z);
+        while (!okf && it < j->max_iter) {
+            for (int m = 0; m < M; m++) {
+                for (int t = c->row_ptr[m]; t < c->row_ptr[m + 1]; t++) Q[t] = P[c->row_bits[t]] - R[t];
+                for (int t = c->row_ptr[m]; t < c->row_ptr[m + 1]; t++) {
+                    float mn = INFINITY;
+                    int neg = 0;
+                    for (int u = c->row_ptr[m]; u < c->row_ptr[m + 1]; u++) {
+                        if (u == t) continue;
+                        float a = fabsf(Q[u]);
+                        if (a < mn) mn = a;
+                        neg ^= Q[u] < 0.0f;
+                    }
+                    if (c->row_ptr[m + 1] - c->row_ptr[m] < 2) mn = 0.0f;
+                    float mag;
+                    if (j->offset) { mag = mn - j->cst; if (!(mag > 0.0f)) mag = 0.0f; }
+                    else mag = j->cst * mn;
+                    Rn[t] = neg ? -mag : mag;
+                }
+            }
+            for (int e = 0; e < E; e++) R[e] = Rn[e];
+            for (int n = 0; n < N; n++) {
+                float s = L[n];
+                for (int u = c->col_ptr[n]; u < c->col_ptr[n + 1]; u++) s = s + R[bedge[u]];
+                P[n] = s;
+                z[n] = s < 0.0f;
+            }
+            it++;
+            okf = ms_syndrome_zero(c, z);
+        }
+        int NW = (N + 31) / 32;
+        uint32_t *zo = j->z + f * NW;
+        for (int t = 0; t < NW; t++) zo[t] = 0;
+        for (int n = 0; n < N; n++)
+            if (z[n]) zo[n / 32] |= 1u << (n % 32);
+        j->iters[f] = it;
+        j->ok[f] = (uint8_t)okf;
+    }
+out:
+    free(L); free(P); free(R); free(Rn); free(Q); free(z); free(bedge);
+    return NULL;
+}
+
+/* offset = 0: normalised min-sum with factor cst; 1: offset min-sum */
+int or_decode_minsum(const ocode *c, int offset, float cst, int max_iter, const float *y, int64_t F,
+                     int64_t stride, uint32_t *z, int32_t *iters, uint8_t *ok, int nthreads)
+{
+    if (!c || (!y && F > 0) || F < 0 || stride < c->N || max_iter < 0 || (offset != 0 && offset != 1) ||
+        !(cst >= 0.0f))
+        return OR_EINVAL;
+    if (F == 0) return OR_OK;
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > F) nthreads = (int)F;
+    msjob *jobs = (msjob *)calloc(nthreads, sizeof(msjob));
+    pthread_t *th = (pthread_t *)calloc(nthreads, sizeof(pthread_t));
+    if (!jobs || !th) { free(jobs); free(th); return OR_ENOMEM; }
+    for (int t = 0; t < nthreads; t++) {
+        jobs[t] = (msjob){c, offset, max_iter, cst, y, F * t / nthreads, F * (t + 1) / nthreads, stride, z,
+                          iters, ok, 0};
+        pthread_create(&th[t], NULL, ms_worker, &jobs[t]);
+    }
+    int rc = OR_OK;
+    for (int t = 0; t < nthreads; t++) {
+        pthread_join(th[t], NULL);
+        if (jobs[t].rc) rc = jobs[t].rc;
+    }
+    free(jobs); free(th);
+    return rc;
 }

@@ -294,3 +294,45 @@ def test_table1_statistical(G):
         z, it, ok = O.decode(c, y, G=G, max_iter=10, alpha=al, weights=O.IMWBF)
         passes = np.where(ok == 1, np.minimum(it + 1, 10), 10)
         assert abs(passes.mean() - want) < 0.2, (G, eb, passes.mean(), want)
+
+
+def _permuted_code_text(H, perm):
+    """H with column perm[i] moved to position i, as a Z = 1 description."""
+    Hp = H[:, perm]
+    rows = "\n".join(" ".join("0" if v else "-1" for v in r) for r in Hp)
+    return f"qc-ldpc v1\nZ 1\nbase {Hp.shape[0]} {Hp.shape[1]}\n{rows}\n"
+
+
+@pytest.mark.parametrize("G", [2, 6, 31])
+@pytest.mark.parametrize("dtype", [np.float32, np.int8])
+def test_strided_blocks_equal_contiguous_blocks_of_permuted_code(ocodes, G, dtype):
+    """Block g = {n : n mod G = g} of a code is block g of the code whose
+    columns are reordered so that each residue class is contiguous (G
+    divides N, so all blocks have p = N/G bits).  The order within a block
+    is kept, so lowest-index ties agree, and the check order (the float sum
+    order) is untouched: strided decoding must equal contiguous decoding of
+    the permuted code on the permuted frame, bit for bit (Section III)."""
+    c = ocodes("n186")
+    N = c.N
+    assert N % G == 0
+    perm = np.array([g + G * pos for g in range(G) for pos in range(N // G)])
+    cp = O.Code.from_text(_permuted_code_text(c.dense(), perm))
+    y = synth.awgn_frames(N, 300, synth.sigma_for(3.0, 0.5), 9, None, dtype)
+    for w, a, an, ad in VARIANTS:
+        kw = dict(weights=w, alpha=a, alpha_num=an, alpha_den=ad, max_iter=30, G=G)
+        zs, its, oks = O.decode(c, y, select=O.STRIDED, **kw)
+        zp, itp, okp = O.decode(cp, y[:, perm], select=O.GROUPS, **kw)
+        bits = np.zeros((y.shape[0], N), np.uint8)
+        bits[:, perm] = O.unpack(zp, N)
+        assert (O.unpack(zs, N) == bits).all() and (its == itp).all() and (oks == okp).all()
+
+
+def test_strided_special_cases(ocodes):
+    """G = 1 and G = N give the same blocks either way."""
+    c = ocodes("n1008")
+    y = synth.awgn_frames(c.N, 64, synth.sigma_for(4.0, 0.5), 3, None, np.int8)
+    for G in (1, c.N):
+        a = O.decode(c, y, select=O.STRIDED, G=G, max_iter=40)
+        b = O.decode(c, y, select=O.GROUPS, G=G, max_iter=40)
+        for u, v in zip(a, b):
+            assert (u == v).all()
