@@ -42,10 +42,12 @@ enum { FWBF_F32 = 0, FWBF_I8 = 1, FWBF_I16 = 2 };
  * minimum, minus alpha|y_n|), IMWBF (minimum over N(m)\n, eq. (1)) */
 enum { FWBF_WBF = 0, FWBF_MWBF = 1, FWBF_IMWBF = 2 };
 /* bit choice: GROUPS = FWBF (at most one flip per block, if its metric is
- * > 0; Section III, Step 2), SINGLE = largest metric flipped unconditionally
- * (IMWBF rule after eq. (1)), TOPL = the lambda largest positive metrics
- * (the multi-bit choice of MLP-WBF, Section III) */
-enum { FWBF_GROUPS = 0, FWBF_SINGLE = 1, FWBF_TOPL = 2 };
+ * > 0; Section III, Step 2; block g = bits [g p, (g+1) p)), SINGLE = largest
+ * metric flipped unconditionally (IMWBF rule after eq. (1)), TOPL = the
+ * lambda largest positive metrics (the multi-bit choice of MLP-WBF,
+ * Section III), STRIDED = GROUPS with block g = {n : n mod G = g} (the
+ * blocks that an interleaver of depth G makes contiguous, Section III) */
+enum { FWBF_GROUPS = 0, FWBF_SINGLE = 1, FWBF_TOPL = 2, FWBF_STRIDED = 3 };
 
 /* flags */
 #define FWBF_FLAG_NO_CYCLE_EXIT 1u /* run every round up to max_iter even after
@@ -59,8 +61,9 @@ typedef struct fwbf_code fwbf_code;
 typedef struct {
     int32_t dtype;     /* FWBF_F32 / FWBF_I8 / FWBF_I16 */
     int32_t weights;   /* FWBF_WBF / FWBF_MWBF / FWBF_IMWBF */
-    int32_t select;    /* FWBF_GROUPS / FWBF_SINGLE / FWBF_TOPL */
-    int32_t groups;    /* G: number of blocks, p = ceil(N/G), 1 <= G <= N */
+    int32_t select;    /* FWBF_GROUPS / FWBF_SINGLE / FWBF_TOPL / FWBF_STRIDED */
+    int32_t groups;    /* G: number of blocks (GROUPS, STRIDED), 1 <= G <= N;
+                          block length p = ceil(N/G) */
     int32_t lambda;    /* TOPL: flips per round, >= 1 */
     int32_t max_iter;  /* K_max: maximum number of flip rounds, >= 0 */
     float alpha;       /* F32: alpha of eq. (1) (ignored for WBF) */
@@ -147,6 +150,30 @@ int fwbf_channel(int N, int64_t F, int64_t f0, const uint32_t *pool_dev, int64_t
 int fwbf_decode(const fwbf_code *code, const fwbf_params *params, const void *y_dev, int64_t F,
                 int64_t y_stride, uint32_t *z_dev, int32_t *iters_dev, uint8_t *ok_dev,
                 void *stream);
+
+/* ---- min-sum belief propagation (the BP reference of Sections I, V) ----- */
+
+/* Flooding min-sum with R_{m,n} = (product of the other members' signs of
+ * Q) r(minimum of the other members' |Q|), Q_{n,m} = P_n - R_{m,n},
+ * P_n = y_n + sum over M(n) of R_{m,n} in ascending check order, z = [P < 0];
+ * r(x) = c x (offset = 0, normalised) or max(x - c, 0) (offset = 1).
+ * The paper names BP and its normalised and offset forms without equations;
+ * this is the textbook schedule, single precision. */
+typedef struct {
+    int32_t offset;            /* 0: normalised, 1: offset */
+    float c;                   /* normalisation factor or offset, finite, >= 0 */
+    int32_t max_iter;          /* iterations, >= 0 */
+    int32_t threads_per_frame; /* 0 = automatic; else 64, 128, 256, 512 or 1024 */
+} fwbf_minsum_params;
+
+/* Decode F float frames y_dev[F][y_stride]: z_dev[F][ceil(N/32)] packed hard
+ * decisions, iters_dev[F] iterations run (0 when [y < 0] satisfies H),
+ * ok_dev[F] = 1 iff the final syndrome is zero.  Any code (the kernels keep
+ * one frame per workgroup in LDS: FWBF_E_UNSUPPORTED beyond 160 KiB).
+ * Stream-ordered; F = 0 is a no-op. */
+int fwbf_decode_minsum(const fwbf_code *code, const fwbf_minsum_params *params, const float *y_dev,
+                       int64_t F, int64_t y_stride, uint32_t *z_dev, int32_t *iters_dev, uint8_t *ok_dev,
+                       void *stream);
 
 /* One decode job of a mixed-code batch (buffers as for fwbf_decode). */
 typedef struct {

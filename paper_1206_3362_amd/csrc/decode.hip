@@ -69,8 +69,16 @@ struct DecodeArgs {
     // |y| staged in LDS only while the check minima are computed (it then
     // shares memory with the slots) and read from global memory afterwards
     int mag_alias;
-    int multi;  // some block holds several shifts
+    int multi;    // some block holds several shifts
+    int strided;  // block g = {n : n mod G = g}: bit n = pos G + g
+    uint32_t magG, maskG;
 };
+
+// bit of position pos in block g, and block / position of bit n
+__device__ __forceinline__ uint32_t bit_of(const DecodeArgs &a, uint32_t g, uint32_t pos)
+{
+    return a.strided ? pos * (uint32_t)a.Geff + g : g * (uint32_t)a.p + pos;
+}
 
 __device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t mag, uint32_t mask)
 {
@@ -348,7 +356,7 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
             const int s0 = (pi * T + tid) * a.C;
             for (int kk = 0; kk < a.C; kk++) {
                 const int pos = pos0 + kk;
-                const int n = g * a.p + pos;
+                const int n = (int)bit_of(a, g, pos);
                 uint32_t key = 0;
                 if (g < a.Geff && pos < a.p && n < N) {
                     const uint32_t v = metric_val<DT>(a, s, n, imwbf);
@@ -379,7 +387,7 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
                             const uint32_t val = (uint32_t)(best >> 32);
                             const uint32_t pos = 0xFFFFFFFFu - (uint32_t)best;
                             const bool flip = (a.select == FWBF_SINGLE) || val > a.zero_val;
-                            s.win[g] = flip ? (uint32_t)(g * a.p) + pos : NONE;
+                            s.win[g] = flip ? bit_of(a, g, pos) : NONE;
                         }
                     } else if (lane == 0 && g < a.Geff) {
                         atomicMax(&s.gb[g], best);
@@ -393,7 +401,7 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
                         const uint32_t val = (uint32_t)(best >> 32);
                         const uint32_t pos = 0xFFFFFFFFu - (uint32_t)best;
                         const bool flip = (a.select == FWBF_SINGLE) || val > a.zero_val;
-                        s.win[g] = flip ? (uint32_t)(g * a.p) + pos : NONE;
+                        s.win[g] = flip ? bit_of(a, g, pos) : NONE;
                     }
                 }
             } else {
@@ -522,8 +530,10 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
                 int cc = r + (int)(e & 0xFFFF);
                 cc -= (cc >= a.Z) ? a.Z : 0;
                 const uint32_t n = (e >> 16) * a.Z + cc;
-                const uint32_t g = fdiv(n, a.magP, a.maskP);
-                const uint32_t slot = g * a.Lc + (n - g * a.p);
+                uint32_t g, pos;
+                if (a.strided) { pos = fdiv(n, a.magG, a.maskG); g = n - pos * a.Geff; }
+                else { g = fdiv(n, a.magP, a.maskP); pos = n - g * a.p; }
+                const uint32_t slot = g * a.Lc + pos;
                 if constexpr (Tt::isf) {
                     s.keys[slot] = metric_val<DT>(a, s, n, imwbf);  // KEY32 is never used for float
                 } else {
@@ -759,8 +769,8 @@ int prepare_decode(const fwbf_code *c, const fwbf_params *p, DecodeArgs *out, in
     if (!c || !p) return fail(FWBF_E_INVALID, "null code or params");
     if (p->dtype < FWBF_F32 || p->dtype > FWBF_I16) return fail(FWBF_E_INVALID, "unknown dtype");
     if (p->weights < FWBF_WBF || p->weights > FWBF_IMWBF) return fail(FWBF_E_INVALID, "unknown weights");
-    if (p->select < FWBF_GROUPS || p->select > FWBF_TOPL) return fail(FWBF_E_INVALID, "unknown select");
-    if (p->select == FWBF_GROUPS && (p->groups < 1 || p->groups > c->N))
+    if (p->select < FWBF_GROUPS || p->select > FWBF_STRIDED) return fail(FWBF_E_INVALID, "unknown select");
+    if ((p->select == FWBF_GROUPS || p->select == FWBF_STRIDED) && (p->groups < 1 || p->groups > c->N))
         return fail(FWBF_E_INVALID, "groups must be in [1, N]");
     if (p->select == FWBF_TOPL && (p->lambda < 1 || p->lambda > 64))
         return fail(FWBF_E_INVALID, "lambda must be in [1, 64]");
@@ -786,9 +796,10 @@ int prepare_decode(const fwbf_code *c, const fwbf_params *p, DecodeArgs *out, in
     if (T != 64 && T != 128 && T != 256 && T != 512 && T != 1024)
         return fail(FWBF_E_INVALID, "threads_per_frame must be 0, 64, 128, 256, 512 or 1024");
 
-    const int G = p->select == FWBF_GROUPS ? p->groups : 1;
+    const int G = (p->select == FWBF_GROUPS || p->select == FWBF_STRIDED) ? p->groups : 1;
     a.p = (c->N + G - 1) / G;
-    a.Geff = (c->N + a.p - 1) / a.p;
+    a.strided = p->select == FWBF_STRIDED;
+    a.Geff = a.strided ? G : (c->N + a.p - 1) / a.p;  // strided: every residue class is nonempty
     Plan pl = plan_layout(a.Geff, a.p, T);
     if (pl.cost < 0) return fail(FWBF_E_UNSUPPORTED, "block too long for threads_per_frame (use more threads)");
     if (p->select == FWBF_TOPL && pl.P != 1) return fail(FWBF_E_UNSUPPORTED, "top-lambda layout");
@@ -817,6 +828,7 @@ int prepare_decode(const fwbf_code *c, const fwbf_params *p, DecodeArgs *out, in
     }
     magic(a.Z, &a.magZ, &a.maskZ);
     magic(a.p, &a.magP, &a.maskP);
+    magic(a.Geff, &a.magG, &a.maskG);
     magic(a.dcmax, &a.magD, &a.maskD);
 
     // LDS layout; |y| gets its own array when everything fits, else it

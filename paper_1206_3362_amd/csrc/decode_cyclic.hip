@@ -489,7 +489,7 @@ int try_cyclic_decode(const fwbf_code *c, const fwbf_params *p, const void *y, i
     if (c->mb != 1 || c->nb != 1 || c->N > 2048) return 0;
     const int W = c->dv_max;
     if (W < 2 || W > WMAX) return 0;
-    if (p->select == FWBF_TOPL) return 0;
+    if (p->select == FWBF_TOPL || p->select == FWBF_STRIDED) return 0;  // contiguous blocks only
     if (p->threads_per_frame != 0 && p->threads_per_frame != 64) return 0;
     CycArgs a;
     memset(&a, 0, sizeof a);

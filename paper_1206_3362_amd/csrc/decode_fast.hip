@@ -40,7 +40,8 @@ struct FastArgs {
     const uint8_t *skip;    // optional: frames with skip[f] != 0 are left untouched
     int iters_add;          // add the rounds to iters[f] instead of storing them
     int N, M, Z, nb;
-    uint32_t magZ, maskZ, magP, maskP;
+    uint32_t magZ, maskZ, magP, maskP, magG, maskG;
+    int strided;  // block g = {n : n mod G = g}: bit n = pos G + g
     int p, L, logL, Geff, Lc;
     int single, imwbf, max_iter, cycle_exit, vec_ok;
     int aden, anum, idxb;
@@ -129,8 +130,9 @@ __global__ __launch_bounds__(64) void fast_kernel(FastArgs a)
     const int N = a.N, M = a.M;
     for (int t = lane; t < DV * a.nb; t += 64) sh[t] = a.shift[t];
     for (int n = lane; n < a.N; n += 64) {
-        const uint32_t gg = fdiv(n, a.magP, a.maskP);
-        const uint32_t pp = n - gg * a.p;
+        uint32_t gg, pp;
+        if (a.strided) { pp = fdiv(n, a.magG, a.maskG); gg = n - pp * a.Geff; }
+        else { gg = fdiv(n, a.magP, a.maskP); pp = n - gg * a.p; }
         slotof[n] = (uint16_t)slot_addr(gg * a.L + pp / C, pp & (C - 1));
     }
 
@@ -139,6 +141,8 @@ __global__ __launch_bounds__(64) void fast_kernel(FastArgs a)
     const bool lead = ((lane & (a.L - 1)) == 0) && (int)g < a.Geff;
     const uint32_t pos0 = (lane & (a.L - 1)) * C;
     const uint32_t gp = g * a.p;
+    // bit at position pos of this lane's block
+    auto bit_at = [&](uint32_t pos) { return a.strided ? pos * (uint32_t)a.Geff + g : gp + pos; };
     const int NW = (N + 31) >> 5;
 
     const FrameRange fr = xcd_frames(a.F);
@@ -179,7 +183,7 @@ __global__ __launch_bounds__(64) void fast_kernel(FastArgs a)
 #pragma unroll
             for (int u = 0; u < 4; u++) {
                 const uint32_t pos = pos0 + kk + u;
-                const bool real = (int)g < a.Geff && (int)pos < a.p && (int)(gp + pos) < N;
+                const bool real = (int)g < a.Geff && (int)pos < a.p && (int)bit_at(pos) < N;
                 vp[u] = real ? ((a.bias << a.idxb) | (a.idxmask - pos)) : 0u;
             }
             ((uint4 *)keys)[chunk_of(lane, kk >> 2)] = v;
@@ -265,7 +269,7 @@ __global__ __launch_bounds__(64) void fast_kernel(FastArgs a)
                 }
                 best = group_max(best, a.L);
                 const uint32_t val = best >> a.idxb;
-                const uint32_t n = gp + (a.idxmask - (best & a.idxmask));
+                const uint32_t n = bit_at(a.idxmask - (best & a.idxmask));
                 const bool flip = lead && (a.single || val > a.zero_val);
                 const uint32_t cur = flip ? n : NONE;
                 const unsigned long long fmask = __ballot(flip);
@@ -424,9 +428,10 @@ int try_fast_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int
         if (v < 0) return 0;
     FastArgs a;
     memset(&a, 0, sizeof a);
-    const int G = p->select == FWBF_GROUPS ? p->groups : 1;
+    const int G = (p->select == FWBF_GROUPS || p->select == FWBF_STRIDED) ? p->groups : 1;
     a.p = (c->N + G - 1) / G;
-    a.Geff = (c->N + a.p - 1) / a.p;
+    a.strided = p->select == FWBF_STRIDED;
+    a.Geff = a.strided ? G : (c->N + a.p - 1) / a.p;
     // smallest C with Geff * L <= 64 lanes, L = 2^ceil(log2(ceil(p / C)))
     int C = 0, L = 0;
     for (int cc : {4, 8, 16, 32, 64}) {
@@ -441,6 +446,7 @@ int try_fast_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int
     a.N = c->N; a.M = c->M; a.Z = c->Z; a.nb = c->nb;
     magic_c(c->Z, &a.magZ, &a.maskZ);
     magic_c(a.p, &a.magP, &a.maskP);
+    magic_c(a.Geff, &a.magG, &a.maskG);
     a.single = p->select == FWBF_SINGLE;
     a.imwbf = p->weights == FWBF_IMWBF;
     a.max_iter = p->max_iter;

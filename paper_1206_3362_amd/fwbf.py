@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libfwbf.so")
 
 F32, I8, I16 = 0, 1, 2
 WBF, MWBF, IMWBF = 0, 1, 2
-GROUPS, SINGLE, TOPL = 0, 1, 2
+GROUPS, SINGLE, TOPL, STRIDED = 0, 1, 2, 3
 FLAG_NO_CYCLE_EXIT = 1
 FLAG_GENERIC_KERNEL = 2
 
@@ -34,7 +34,7 @@ EXPORTS = [
     "fwbf_encode", "fwbf_channel", "fwbf_decode", "fwbf_count", "fwbf_last_error", "fwbf_version",
     "fwbf_scorer_size", "fwbf_decode_learned", "fwbf_scorer_grad", "fwbf_adam",
     "fwbf_decode_batched", "fwbf_sweep_create", "fwbf_sweep_launch", "fwbf_sweep_counters",
-    "fwbf_sweep_free",
+    "fwbf_sweep_free", "fwbf_decode_minsum",
 ]
 
 
@@ -49,6 +49,11 @@ class Params(C.Structure):
                 ("groups", C.c_int32), ("lambda_", C.c_int32), ("max_iter", C.c_int32),
                 ("alpha", C.c_float), ("alpha_num", C.c_int32), ("alpha_den", C.c_int32),
                 ("threads_per_frame", C.c_int32), ("flags", C.c_uint32)]
+
+
+class MinsumParams(C.Structure):
+    _fields_ = [("offset", C.c_int32), ("c", C.c_float), ("max_iter", C.c_int32),
+                ("threads_per_frame", C.c_int32)]
 
 
 class BatchItem(C.Structure):
@@ -92,6 +97,7 @@ def lib():
         L.fwbf_channel.argtypes = [i32, i64, i64, vp, i64, u64, C.c_uint32, C.c_float, vp,
                                    C.c_float, i32, vp, i64, vp]
         L.fwbf_decode.argtypes = [vp, C.POINTER(Params), vp, i64, i64, vp, vp, vp, vp]
+        L.fwbf_decode_minsum.argtypes = [vp, C.POINTER(MinsumParams), vp, i64, i64, vp, vp, vp, vp]
         L.fwbf_count.argtypes = [i32, i64, i64, vp, vp, i64, vp, vp, i32, vp, vp]
         L.fwbf_scorer_size.argtypes = [i32]
         L.fwbf_decode_learned.argtypes = [vp, C.POINTER(Params), C.POINTER(LearnedParams), vp, vp, i64,
@@ -262,6 +268,30 @@ def decode(code: Code, y, params: DecodeParams | None = None, **kw):
     it = torch.empty(F, dtype=torch.int32, device=dev)
     ok = torch.empty(F, dtype=torch.uint8, device=dev)
     decode_into(code, y, params, z, it, ok)
+    return z, it, ok
+
+
+def decode_minsum_into(code: Code, y, z, iters, ok, *, offset: bool = False, c: float = 0.75,
+                       max_iter: int = 20, threads_per_frame: int = 0):
+    """Min-sum BP over float frames y[F][stride] into preallocated outputs."""
+    p = MinsumParams(int(bool(offset)), c, max_iter, threads_per_frame)
+    F = y.shape[0]
+    stride = y.stride(0) if y.dim() == 2 else code.N
+    _check(lib().fwbf_decode_minsum(code._h, C.byref(p), _ptr(y), F, stride, _ptr(z), _ptr(iters),
+                                    _ptr(ok), _stream()))
+
+
+def decode_minsum(code: Code, y, **kw):
+    """Returns (z packed int32 [F][ceil(N/32)], iterations int32 [F], ok uint8 [F])."""
+    torch = _torch()
+    if y.dtype != torch.float32:
+        raise FwbfError(E_INVALID, "min-sum takes float32 frames")
+    F = y.shape[0]
+    dev = y.device
+    z = torch.empty((F, (code.N + 31) // 32), dtype=torch.int32, device=dev)
+    it = torch.empty(F, dtype=torch.int32, device=dev)
+    ok = torch.empty(F, dtype=torch.uint8, device=dev)
+    decode_minsum_into(code, y, z, it, ok, **kw)
     return z, it, ok
 
 

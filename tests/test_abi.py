@@ -132,3 +132,16 @@ def test_channel_and_count_validation_without_gpu():
     assert L.fwbf_channel(8, 0, 0, None, 0, 1, 0, 1.0, None, 1.0, 0, None, 8, None) == fwbf.OK
     assert L.fwbf_count(8, 1, 0, None, None, 0, None, None, -1, None, None) == fwbf.E_INVALID
     assert L.fwbf_count(8, 0, 0, None, None, 0, None, None, 10, None, None) == fwbf.OK
+
+
+def test_minsum_rejects_bad_arguments():
+    g = fwbf.Code.from_seed(*CODES["n186"])
+    L = fwbf.lib()
+    for off, c, it in [(2, 0.75, 10), (0, -1.0, 10), (0, float("nan"), 10), (0, 0.75, -1)]:
+        p = fwbf.MinsumParams(off, c, it, 0)
+        rc = L.fwbf_decode_minsum(g._h, C.byref(p), None, 1, g.N, None, None, None, None)
+        assert rc == fwbf.E_INVALID, (off, c, it)
+    p = fwbf.MinsumParams(0, 0.75, 10, 0)
+    assert L.fwbf_decode_minsum(g._h, C.byref(p), None, 0, g.N, None, None, None, None) == fwbf.OK
+    assert L.fwbf_decode_minsum(g._h, C.byref(p), None, 1, g.N - 1, None, None, None, None) == fwbf.E_INVALID
+    assert L.fwbf_decode_minsum(g._h, C.byref(p), None, 1, g.N, None, None, None, None) == fwbf.E_INVALID

@@ -261,3 +261,31 @@ def test_cyclic_kernel_shapes(text, dt):
             want = oracle_decode(o, y, **kw)
             assert_same(gpu_decode(g, y, **kw), want, f"cyclic {kw}")
             assert_same(gpu_decode(g, y, flags=fwbf.FLAG_GENERIC_KERNEL, **kw), want, f"generic {kw}")
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.int8, np.int16])
+@pytest.mark.parametrize("G", [7, 8, 126, 1008])
+def test_strided_blocks_n1008(codes, dt, G):
+    """Strided blocks (block g = {n : n mod G = g}): the specialised and the
+    general kernel against the oracle, with G dividing N or not."""
+    from paper_1206_3362_amd import fwbf
+    g, o = codes("n1008")
+    F = 1024
+    pool = o.encode(seed=5, first=0, count=64)
+    cb = O.unpack(pool[np.arange(F) % 64], g.N)
+    y = synth.awgn_frames(g.N, F, synth.sigma_for(4.0, g.rate), G, cb, dt)
+    kw = dict(select=fwbf.STRIDED, groups=G, weights=2, alpha=0.2, alpha_num=1, alpha_den=5, max_iter=100)
+    print(f"case n1008 strided dtype={np.dtype(dt).name} G={G}", flush=True)
+    want = oracle_decode(o, y, **kw)
+    assert_same(gpu_decode(g, y, **kw), want, f"strided {kw}")
+    assert_same(gpu_decode(g, y, flags=fwbf.FLAG_GENERIC_KERNEL, **kw), want, f"strided generic {kw}")
+
+
+def test_strided_blocks_eg255(eg):
+    from paper_1206_3362_amd import fwbf
+    g, o = eg(4)
+    y = synth.awgn_frames(g.N, 512, synth.sigma_for(3.5, g.rate), 12, None, np.float32)
+    for G in (5, 16, 100):
+        kw = dict(select=fwbf.STRIDED, groups=G, weights=2, alpha=1.0, max_iter=20)
+        print(f"case eg255 strided G={G}", flush=True)
+        assert_same(gpu_decode(g, y, **kw), oracle_decode(o, y, **kw), f"eg255 strided {kw}")
