@@ -44,7 +44,7 @@ def parse():
                     default=os.path.join(ROOT, "paper_1206_3362_amd", "scorer_n1008_g32_t16.npz"))
     ap.add_argument("--workload", default="n1008_i8",
                     choices=["n1008_i8", "n186_f32_wbf", "mixed_f32", "n32400_i16", "sweep_n1008_i8",
-                             "eg1023_tab1"],
+                             "eg1023", "eg1023_tab1", "eg255_delay", "strided_n1008", "minsum_eg255"],
                     help="n1008_i8: the headline workload; the others are further configurations "
                          "measured with the same protocol (one JSON line each)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -296,8 +296,14 @@ def other_workload(a):
                     value=res[6.0]["gbps"], ms_per_step=res[6.0]["ms"], dtype="int32", points=res,
                     config={"workload": "N=32400 (3,30) QC Z=1080 K=29162, int16 x256, G=64, K_max=100, "
                                         "2^15 frames per point", "frames": F})
-    elif a.workload == "eg1023_tab1":
-        eg1023_tab1(a, line)
+    elif a.workload == "minsum_eg255":
+        minsum_eg255(a, line)
+    elif a.workload == "strided_n1008":
+        strided_n1008(a, line)
+    elif a.workload == "eg255_delay":
+        eg255_delay(a, line)
+    elif a.workload in ("eg1023", "eg1023_tab1"):
+        eg1023_tab1(a, line, sweep=a.workload == "eg1023_tab1")
     else:  # sweep_n1008_i8
         code = fwbf.Code.from_seed(3, 6, 168, 2)
         pool = torch.from_numpy(code.encode(1001, 0, 1024).view(np.int32)).to(dev)
@@ -322,7 +328,7 @@ TAB1 = {"MLP-WBF": [8.86, 6.20, 4.54, 3.83], "FWBF p=93": [9.29, 7.37, 6.06, 5.1
         "FWBF p=31": [8.62, 5.60, 4.19, 3.64]}
 
 
-def eg1023_tab1(a, line):
+def eg1023_tab1(a, line, sweep=True):
     """Tab. 1 of the paper on the EG(1023,781) code: averaged rounds of FWBF
     with blocks of p=93 (G=11) and p=31 (G=33) bits, K_max=10, float32
     BPSK/AWGN, IMWBF metric with alpha swept (the paper does not state it),
@@ -335,13 +341,16 @@ def eg1023_tab1(a, line):
     N, F = code.N, 1 << 16
     pool = torch.from_numpy(code.encode(1023, 0, 1024).view(np.int32)).to("cuda")
     ebs = (3.0, 3.5, 4.0, 4.5)
-    alphas = (0.0, 0.1, 0.2, 0.3, 0.5, 0.8, 1.0, 1.5, 2.0)
+    alphas = (0.0, 0.1, 0.2, 0.3, 0.5, 0.8, 1.0, 1.5, 2.0) if sweep else (1.5,)
     rows = {}
     timed = None
-    for k, eb in enumerate(ebs):
+    for eb in (ebs if sweep else (4.0,)):
+        k = ebs.index(eb)
         y = fwbf.channel(N, F, 0, pool, 1300, k, float(synth.sigma_for(eb, code.rate)))
-        cases = [(f"FWBF p={-(-N // G)}", dict(groups=G), al) for G in (11, 33) for al in alphas]
-        cases += [("top-lambda 10", dict(select=fwbf.TOPL, lam=10), al) for al in alphas]
+        cases = [(f"FWBF p={-(-N // G)}", dict(groups=G), al) for G in ((11, 33) if sweep else (33,))
+                 for al in alphas]
+        if sweep:
+            cases += [("top-lambda 10", dict(select=fwbf.TOPL, lam=10), al) for al in alphas]
         for name, sel, al in cases:
             p = fwbf.DecodeParams(dtype=fwbf.F32, weights=fwbf.IMWBF, max_iter=10, alpha=al, **sel)
             z, it, ok = fwbf.decode(code, y, p)
@@ -353,12 +362,19 @@ def eg1023_tab1(a, line):
             rows.setdefault(name, {}).setdefault(f"{al:g}", []).append(
                 dict(iters=round(r["iter_sum"] / F, 3), passes=round(passes, 3),
                      fer=round(r["frame_err"] / F, 5), ber=float(r["bit_err"] / (F * N))))
-            if name == "FWBF p=31" and al == 0.2 and eb == 4.0:
+            if name == "FWBF p=31" and al == 1.5 and eb == 4.0:
                 timed = (y, p, z, it, ok)
     y, p, z, it, ok = timed
     ms = _timed(lambda: fwbf.decode_into(code, y, p, z, it, ok), a.steps, a.warmup)
+    # the same point with int8 inputs (scale 16, alpha 3/2)
+    yq = fwbf.channel(N, F, 0, pool, 1300, 2, float(synth.sigma_for(4.0, code.rate)), dtype=torch.int8,
+                      scale=16.0)
+    pq = fwbf.DecodeParams(dtype=fwbf.I8, weights=fwbf.IMWBF, groups=33, max_iter=10, alpha_num=3, alpha_den=2)
+    zq, iq, oq = fwbf.decode(code, yq, pq)
+    ms8 = _timed(lambda: fwbf.decode_into(code, yq, pq, zq, iq, oq), a.steps, a.warmup)
+    r8 = fwbf.count(N, zq, pool, 0, iq, oq, 10)
     best = {}
-    for name, by_alpha in rows.items():
+    for name, by_alpha in (rows.items() if sweep else ()):
         ref = TAB1["MLP-WBF" if name.startswith("top") else name]
         for count in ("iters", "passes"):
             err = {al: float(np.sqrt(np.mean([(v[count] - r) ** 2 for v, r in zip(vals, ref)])))
@@ -366,12 +382,153 @@ def eg1023_tab1(a, line):
             al = min(err, key=err.get)
             best[f"{name} ({count})"] = dict(alpha=float(al), avg=[v[count] for v in by_alpha[al]],
                                              paper=ref, rms_diff=round(err[al], 3))
-    line.update(metric="decoded Gb/s, FWBF on EG(1023,781), p=31, alpha 0.2, 4 dB, float32, K_max=10",
+    line.update(metric="decoded Gb/s, FWBF on EG(1023,781), p=31, alpha 1.5, 4 dB, float32, K_max=10",
                 value=round(F * N / (ms * 1e-3) / 1e9, 3), ms_per_step=round(ms, 4), dtype="f32",
-                tab1_best_alpha=best, tab1_sweep=rows, ebn0=list(ebs),
+                int8_gbps=round(F * N / (ms8 * 1e-3) / 1e9, 3), int8_ms=round(ms8, 4),
+                int8_fer=r8["frame_err"] / F, int8_mean_rounds=r8["iter_sum"] / F,
+                tab1_best_alpha=best or None, tab1_sweep=rows, ebn0=list(ebs) if sweep else [4.0],
                 config={"workload": "EG(1023,781) type-I 2-D Euclidean geometry code, random "
                                     "codewords, BPSK/AWGN 3.0-4.5 dB, f32, IMWBF, K_max=10, "
                                     "2^16 frames per point", "frames": F})
+
+
+def _ebn0_at(ebs, bers, target):
+    """Eb/N0 where log10(BER) crosses the target (linear interpolation)."""
+    import numpy as np
+    lb = np.log10(np.maximum(np.asarray(bers, float), 1e-12))
+    for i in range(len(ebs) - 1):
+        if lb[i] >= np.log10(target) > lb[i + 1]:
+            t = (lb[i] - np.log10(target)) / (lb[i] - lb[i + 1])
+            return round(float(ebs[i] + t * (ebs[i + 1] - ebs[i])), 3)
+    return None
+
+
+def minsum_eg255(a, line):
+    """BER of min-sum BP against FWBF on EG(255,175) (code 1 of Section V,
+    where the paper puts BP 0.5 dB ahead of FWBF at BER 1e-4), float32,
+    2^18 random codewords per point; the Eb/N0 at BER 1e-4 of each decoder,
+    and both decoders' throughput at 4 dB."""
+    import numpy as np
+    import torch
+
+    from paper_1206_3362_amd import fwbf, synth
+    code = fwbf.Code.from_text(synth.eg_code_text(4))
+    N, F = code.N, 1 << 18
+    pool = torch.from_numpy(code.encode(255, 0, 4096).view(np.int32)).to("cuda")
+    ebs = [3.0 + 0.25 * i for i in range(11)]
+    decs = {f"min-sum c={c}": ("ms", dict(c=c, max_iter=50)) for c in (0.625, 0.75, 1.0)}
+    decs.update({f"FWBF p={-(-N // G)} alpha={al}": ("fwbf", dict(groups=G, alpha=al))
+                 for G in (5, 16) for al in (1.0, 2.0)})
+    ber = {k: [] for k in decs}
+    fer = {k: [] for k in decs}
+    rounds = {k: [] for k in decs}
+    timing = {}
+    for k_eb, eb in enumerate(ebs):
+        y = fwbf.channel(N, F, 0, pool, 2550, k_eb, float(synth.sigma_for(eb, code.rate)))
+        for name, (kind, kw) in decs.items():
+            if kind == "ms":
+                run = lambda: fwbf.decode_minsum(code, y, **kw)
+                K = kw["max_iter"]
+            else:
+                p = fwbf.DecodeParams(dtype=fwbf.F32, weights=fwbf.IMWBF, max_iter=10, **kw)
+                run = lambda: fwbf.decode(code, y, p)
+                K = 10
+            z, it, ok = run()
+            r = fwbf.count(N, z, pool, 0, it, ok, K)
+            ber[name].append(r["bit_err"] / (F * N))
+            fer[name].append(r["frame_err"] / F)
+            rounds[name].append(round(r["iter_sum"] / F, 3))
+            if eb == 4.0:
+                ms = _timed(run, a.steps, a.warmup)
+                timing[name] = round(F * N / (ms * 1e-3) / 1e9, 3)
+    at = {k: _ebn0_at(ebs, v, 1e-4) for k, v in ber.items()}
+    best_ms = min((v, k) for k, v in at.items() if k.startswith("min") and v is not None)
+    best_fw = min((v, k) for k, v in at.items() if k.startswith("FWBF") and v is not None)
+    line.update(metric="decoded Gb/s, min-sum BP (c=0.75, 50 iterations) on EG(255,175), 4 dB, float32",
+                value=timing["min-sum c=0.75"], ms_per_step=None, dtype="f32", gbps_at_4db=timing,
+                ebn0_at_ber_1e4=at, gap_db=round(best_fw[0] - best_ms[0], 3),
+                best={"min-sum": best_ms[1], "FWBF": best_fw[1]}, paper_gap_db=0.5,
+                ebn0=ebs, ber=ber, fer=fer, mean_iterations=rounds,
+                config={"workload": "EG(255,175), random codewords, BPSK/AWGN 3.0-5.5 dB step 0.25, f32, "
+                                    "FWBF IMWBF K_max=10, min-sum flooding 50 iterations, 2^18 frames per point",
+                        "frames": F})
+
+
+def strided_n1008(a, line):
+    """Contiguous blocks (Section III) against strided blocks
+    (g = n mod G, what an interleaver of depth G makes contiguous) on the
+    N=1008 code, int8, at equal K_max: FER, mean rounds and decoded Gb/s per
+    Eb/N0, for G = 8 and 32."""
+    import numpy as np
+    import torch
+
+    from paper_1206_3362_amd import fwbf, synth
+    code = fwbf.Code.from_seed(3, 6, 168, 2)
+    N, F = code.N, 1 << 18
+    pool = torch.from_numpy(code.encode(1001, 0, 1024).view(np.int32)).to("cuda")
+    res = {}
+    for eb in (3.0, 4.0, 5.0, 6.0):
+        y = fwbf.channel(N, F, 0, pool, 1500, int(eb), float(synth.sigma_for(eb, code.rate)),
+                         dtype=torch.int8, scale=16.0)
+        for G in (8, 32):
+            for sel, name in ((fwbf.GROUPS, "contiguous"), (fwbf.STRIDED, "strided")):
+                p = fwbf.DecodeParams(dtype=fwbf.I8, select=sel, groups=G, max_iter=100)
+                z, it, ok = fwbf.decode(code, y, p)
+                ms = _timed(lambda: fwbf.decode_into(code, y, p, z, it, ok), a.steps, a.warmup)
+                r = fwbf.count(N, z, pool, 0, it, ok, 100)
+                fe = r["frame_err"]
+                res.setdefault(f"{eb:.0f}dB", {})[f"G{G} {name}"] = dict(
+                    fer=round(fe / F, 5), fer_3sigma=round(3 * np.sqrt(max(fe, 1) * (1 - fe / F)) / F, 5),
+                    mean_rounds=round(r["iter_sum"] / F, 3), gbps=round(F * N / (ms * 1e-3) / 1e9, 2))
+    v = res["4dB"]["G8 strided"]
+    line.update(metric="decoded Gb/s, plain FWBF, strided blocks, N=1008 int8, 4 dB, G=8",
+                value=v["gbps"], ms_per_step=None, dtype="int32", points=res,
+                config={"workload": "N=1008 (3,6) QC int8 x16, K_max=100, 2^18 frames per point, "
+                                    "contiguous vs strided blocks", "frames": F})
+
+
+def eg255_delay(a, line):
+    """Per-round cost of FWBF on EG(255,175) next to the clock model of
+    Section IV (FWBF: 20 clocks per bit choice with 16 units; MLP-WBF: 24
+    lambda).  At -6 dB, with the repeated-state exit switched off, frames run
+    K rounds unless they land on some codeword; the time difference between
+    K = 41 and K = 1, divided by the difference of the rounds actually run,
+    is the cost of one round.  One frame alone gives the latency of a round
+    (one wave, cycles at 2.4 GHz); 2^16 frames give its throughput."""
+    import numpy as np
+    import torch
+
+    from paper_1206_3362_amd import delay, fwbf, synth
+    code = fwbf.Code.from_text(synth.eg_code_text(4))
+    N = code.N
+    out = {}
+    for F in (1, 1 << 16):
+        y = fwbf.channel(N, F, 0, None, 77, 0, float(synth.sigma_for(-6.0, code.rate)))
+        ms, rnd = {}, {}
+        for K in (1, 41):
+            p = fwbf.DecodeParams(dtype=fwbf.F32, weights=fwbf.IMWBF, groups=16, max_iter=K, alpha=1.0,
+                                  flags=fwbf.FLAG_NO_CYCLE_EXIT)
+            z, it, ok = fwbf.decode(code, y, p)
+            reps = [_timed(lambda: fwbf.decode_into(code, y, p, z, it, ok), max(a.steps, 5), a.warmup)
+                    for _ in range(3)]
+            ms[K] = float(np.median(reps))
+            rnd[K] = float(it.double().mean())
+        per_round_ns = (ms[41] - ms[1]) * 1e6 / (rnd[41] - rnd[1])
+        out[F] = dict(ms_k1=round(ms[1], 5), ms_k41=round(ms[41], 5), mean_rounds_k41=round(rnd[41], 3),
+                      per_round_ns=round(per_round_ns, 2))
+    lat_ns = out[1]["per_round_ns"]
+    thr_ns = out[1 << 16]["per_round_ns"] / (1 << 16)
+    line.update(metric="bit-choice round cost, FWBF on EG(255,175), float32, G=16 (p=16)",
+                value=round(1e3 / thr_ns, 3), unit="M frame-rounds/s", higher_is_better=True,
+                ms_per_step=out[1 << 16]["ms_k41"], dtype="f32",
+                one_frame_round_ns=lat_ns, one_frame_round_cycles=round(lat_ns * 2.4, 1),
+                chip_ns_per_frame_round=round(thr_ns, 5),
+                model_clocks={"fwbf_eq3": delay.fwbf_delay(255, 16),
+                              "mlp_wbf_eq2_lambda10": delay.mlp_wbf_delay(255, 16, 10),
+                              "metric_units_16": delay.metric_clocks(255, 16)},
+                raw=out,
+                config={"workload": "EG(255,175), -2 dB (no frame decodes), repeated-state exit off, "
+                                    "K = 1 and 41 rounds, 1 frame and 2^16 frames", "frames": 1 << 16})
 
 
 def kernel_sha():
