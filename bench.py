@@ -271,10 +271,13 @@ def other_workload(a):
             bits += F * code.N
         ws = torch.zeros(64, dtype=torch.int32, device=dev)
         ms = _timed(lambda: fwbf.decode_batched(jobs, workspace=ws), a.steps, a.warmup)
+        ms256 = _timed(lambda: fwbf.decode_batched(jobs, threads_per_frame=256, workspace=ws), a.steps,
+                       a.warmup)
         sep = _timed(lambda: [fwbf.decode(c, y, p) for c, y, p in jobs], a.steps, a.warmup)
         line.update(metric="decoded Gb/s, mixed-code persistent batch (float32)",
                     value=round(bits / (ms * 1e-3) / 1e9, 3), ms_per_step=round(ms, 4), dtype="f32",
                     separate_launches_gbps=round(bits / (sep * 1e-3) / 1e9, 3),
+                    one_width_256_gbps=round(bits / (ms256 * 1e-3) / 1e9, 3),
                     config={"workload": "N=1008/4032 (3,6) + N=8000 (4,20) QC, 2^18/2^16/2^15 frames, "
                                         "Eb/N0 U[3,6] dB per frame, f32, G=8/32/64, one launch",
                             "frames": sum(s[1] for s in specs)})

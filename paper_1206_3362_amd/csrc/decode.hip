@@ -259,14 +259,31 @@ __device__ __forceinline__ unsigned long long thread_best(const DecodeArgs &a, c
     }
 }
 
-template <int DT, bool KEY32, int T>
+// Barrier of one frame's threads: the workgroup, or (WAVE) the single
+// wavefront that decodes the frame alone inside a larger workgroup (LDS
+// operations of one wavefront complete in issue order; the wave barrier
+// keeps the compiler from moving memory operations across it).
+template <bool WAVE>
+__device__ __forceinline__ void frame_sync()
+{
+    if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+template <int DT, bool KEY32, int T, bool WAVE = false>
 __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
 {
+    static_assert(!WAVE || T == 64, "a frame decoded by one wavefront has 64 threads");
     using Tt = Tr<DT>;
     using Y = typename Tt::Y;
     using Mag = typename Tt::Mag;
     using Chk = typename Tt::Chk;
-    const int tid = threadIdx.x, lane = tid & 63;
+    const int tid = WAVE ? (int)(threadIdx.x & 63) : (int)threadIdx.x, lane = tid & 63;
     const bool imwbf = a.weights == FWBF_IMWBF;
     const int N = a.N, M = a.M;
     Mag *mag = (Mag *)s.mag;
@@ -292,7 +309,7 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
     }
     for (int w = tid; w < (Mr >> 5); w += T) s.tog[w] = 0;
     if (tid == 0) { s.ctl[CTL_FLAGS] = 0; s.ctl[CTL_WEIGHT] = 0; }
-    __syncthreads();
+    frame_sync<WAVE>();
 
     // ---- check minima (weights) and the syndrome s_0 (Step 1 at k=0) -----
     for (int m = tid; m < Mr; m += T) {
@@ -342,7 +359,7 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
             if (b) atomicAdd(&s.ctl[CTL_WEIGHT], __popcll(b));
         }
     }
-    __syncthreads();
+    frame_sync<WAVE>();
 
     int k = 0, okf = 0;
     const int weight0 = s.ctl[CTL_WEIGHT];
@@ -368,7 +385,7 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
         for (int u = tid; u < a.W; u += T) s.prv[u] = NONE;
         if (tid < 2) s.gb[tid] = 0;
         for (int u = tid; u < a.Geff && a.L > 64; u += T) s.gb[u] = 0;
-        __syncthreads();
+        frame_sync<WAVE>();
 
         for (;;) {
             // ---- Step 2: choose at most one bit per block ------------------
@@ -394,7 +411,7 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
                     }
                 }
                 if (a.L > 64) {
-                    __syncthreads();
+                    frame_sync<WAVE>();
                     for (int g = tid; g < a.Geff; g += T) {
                         const unsigned long long best = s.gb[g];
                         s.gb[g] = 0;
@@ -415,7 +432,7 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
                         best = o > best ? o : best;
                     }
                     if (lane == 0) atomicMax(&s.gb[t & 1], best);
-                    __syncthreads();
+                    frame_sync<WAVE>();
                     best = s.gb[t & 1];
                     const uint32_t val = (uint32_t)(best >> 32);
                     const uint32_t pos = 0xFFFFFFFFu - (uint32_t)best;
@@ -427,9 +444,9 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
                         s.keys[pos] = 0;
                     }
                     cnt = t + 1;
-                    __syncthreads();
+                    frame_sync<WAVE>();
                 }
-                __syncthreads();
+                frame_sync<WAVE>();
                 if (tid == 0) {
                     s.gb[0] = 0;
                     s.gb[1] = 0;
@@ -444,7 +461,7 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
                     for (int t = 0; t < a.W; t++) s.win[t] = t < cnt ? s.topn[t] : NONE;
                 }
             }
-            __syncthreads();
+            frame_sync<WAVE>();
 
             // ---- flip the chosen bits; toggle parity of their checks -------
             for (int u = tid; u < a.W; u += T) {
@@ -467,7 +484,7 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
                 }
                 if (fl) atomicOr(&s.ctl[CTL_FLAGS], fl);
             }
-            __syncthreads();
+            frame_sync<WAVE>();
             const int flags = s.ctl[CTL_FLAGS];
             if (!(a.flags & FWBF_FLAG_NO_CYCLE_EXIT)) {
                 if (!(flags & F_ANY)) {  // no flip: fixed point until K_max
@@ -509,7 +526,7 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
                     }
                 }
             }
-            __syncthreads();
+            frame_sync<WAVE>();
             const int weight = s.ctl[CTL_WEIGHT];
             if (tid == 0) s.ctl[CTL_FLAGS] = 0;
             k += 1;
@@ -542,10 +559,10 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
                     atomicAdd(&s.keys[slot], KEY32 ? ((uint32_t)d << a.idxb) : (uint32_t)d);
                 }
             }
-            __syncthreads();
+            frame_sync<WAVE>();
         }
     }
-    __syncthreads();
+    frame_sync<WAVE>();
 
     // ---- output z_k, rounds, syndrome flag --------------------------------
     const int NW = (N + 31) >> 5;
@@ -555,7 +572,7 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
         a.iters[f] = k;
         a.ok[f] = (uint8_t)okf;
     }
-    __syncthreads();
+    frame_sync<WAVE>();
 }
 
 template <int DT, bool KEY32, int T>
@@ -598,9 +615,16 @@ __global__ __launch_bounds__(T) void decode_kernel(DecodeArgs a)
 // ---------------------------------------------------------------------------
 constexpr int MAX_JOBS = 8;
 
+// A ticket is a chunk of consecutive frames of one job.  Jobs whose frames
+// need one wavefront (wave[j]) are decoded one frame per wavefront, each
+// wavefront in its own LDS region of lds_job[j] bytes; the others by the
+// whole workgroup.
 struct BatchArgs {
     DecodeArgs job[MAX_JOBS];
-    int64_t base[MAX_JOBS + 1];  // first ticket of each job; base[njobs] = total
+    int64_t cbase[MAX_JOBS + 1];  // first ticket of each job; cbase[njobs] = number of tickets
+    int chunk[MAX_JOBS];
+    int wave[MAX_JOBS];
+    int lds_job[MAX_JOBS];
     int njobs;
     unsigned long long *counter;
 };
@@ -636,26 +660,41 @@ __global__ __launch_bounds__(T) void batched_kernel(BatchArgs b)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ long long s_ticket;
-    int cur = -1;
     for (;;) {
         if (threadIdx.x == 0) s_ticket = (long long)atomicAdd(b.counter, 1ull);
         __syncthreads();
         const long long tk = s_ticket;
         __syncthreads();  // every thread has read the ticket before it is overwritten
-        if (tk >= b.base[b.njobs]) break;
+        if (tk >= b.cbase[b.njobs]) break;
         int j = 0;
-        while (j + 1 < b.njobs && b.base[j + 1] <= tk) j++;
+        while (j + 1 < b.njobs && b.cbase[j + 1] <= tk) j++;
         const DecodeArgs &a = b.job[j];
-        Lds s = lds_of(smem, a);
-        if (j != cur) {
+        const int64_t f0 = (tk - b.cbase[j]) * b.chunk[j];
+        const int64_t f1 = f0 + b.chunk[j] < a.F ? f0 + b.chunk[j] : a.F;
+        bool done = false;
+        if constexpr (T > 64) {
+            if (b.wave[j]) {
+                const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+                Lds s = lds_of(smem + w * b.lds_job[j], a);
+                for (int t = lane; t < a.nb * a.dvmax; t += 64) s.col[t] = a.col[t];
+                for (int t = lane; t < a.mb * a.dcmax; t += 64) s.row[t] = a.row[t];
+                for (int t = lane; t < a.nb; t += 64) s.cdeg[t] = a.coldeg[t];
+                for (int t = lane; t < a.mb; t += 64) s.rdeg[t] = a.rowdeg[t];
+                frame_sync<true>();
+                for (int64_t f = f0 + w; f < f1; f += T / 64) decode_frame<DT, KEY32, 64, true>(a, s, f);
+                __syncthreads();  // the regions are reused by the next ticket
+                done = true;
+            }
+        }
+        if (!done) {
+            Lds s = lds_of(smem, a);
             for (int t = threadIdx.x; t < a.nb * a.dvmax; t += T) s.col[t] = a.col[t];
             for (int t = threadIdx.x; t < a.mb * a.dcmax; t += T) s.row[t] = a.row[t];
             for (int t = threadIdx.x; t < a.nb; t += T) s.cdeg[t] = a.coldeg[t];
             for (int t = threadIdx.x; t < a.mb; t += T) s.rdeg[t] = a.rowdeg[t];
             __syncthreads();
-            cur = j;
+            for (int64_t f = f0; f < f1; f++) decode_frame<DT, KEY32, T>(a, s, f);
         }
-        decode_frame<DT, KEY32, T>(a, s, tk - b.base[j]);
     }
 }
 
@@ -983,14 +1022,26 @@ extern "C" int fwbf_decode_batched(const fwbf_batch_item *items, int n_items, in
     memset(&b, 0, sizeof b);
     b.njobs = n_items;
     int lds = 0;
-    int64_t total = 0;
+    int64_t total = 0, tickets = 0;
     for (int i = 0; i < n_items; i++) {
         const fwbf_batch_item &it = items[i];
         fwbf_params p = *it.params;
-        p.threads_per_frame = T;
+        // frames that take 64 threads on their own are decoded one per
+        // wavefront when the launch is wider (automatic width only)
+        const int N = it.code->N;
+        const bool wave = threads_per_frame == 0 && T > 64 && N <= 2048;
+        p.threads_per_frame = wave ? 64 : T;
         int Ti = 0;
-        const int k = prepare_decode(it.code, &p, &b.job[i], &Ti, true);
+        int k = prepare_decode(it.code, &p, &b.job[i], &Ti, true);
         if (k < 0) return k;
+        b.wave[i] = wave && (int64_t)(T / 64) * b.job[i].lds_bytes <= 160 * 1024;
+        if (wave && !b.wave[i]) {
+            p.threads_per_frame = T;
+            k = prepare_decode(it.code, &p, &b.job[i], &Ti, true);
+            if (k < 0) return k;
+        }
+        b.lds_job[i] = b.job[i].lds_bytes;
+        b.chunk[i] = b.wave[i] ? 4 * (T / 64) : 2;
         DeviceTables tb;
         const int rc = device_tables(const_cast<fwbf_code *>(it.code), &tb);
         if (rc) return rc;
@@ -998,11 +1049,12 @@ extern "C" int fwbf_decode_batched(const fwbf_batch_item *items, int n_items, in
         a.y = it.y_dev; a.F = it.F; a.stride = it.y_stride;
         a.z = it.z_dev; a.iters = it.iters_dev; a.ok = it.ok_dev;
         a.col = tb.col; a.row = tb.row; a.coldeg = tb.coldeg; a.rowdeg = tb.rowdeg;
-        b.base[i] = total;
+        b.cbase[i] = tickets;
         total += it.F;
-        lds = std::max(lds, a.lds_bytes);
+        tickets += (it.F + b.chunk[i] - 1) / b.chunk[i];
+        lds = std::max(lds, b.wave[i] ? (T / 64) * a.lds_bytes : a.lds_bytes);
     }
-    b.base[n_items] = total;
+    b.cbase[n_items] = tickets;
     if (total == 0) return FWBF_OK;
     b.counter = (unsigned long long *)workspace_dev;
     hipStream_t st = (hipStream_t)stream;
@@ -1015,7 +1067,7 @@ extern "C" int fwbf_decode_batched(const fwbf_batch_item *items, int n_items, in
     if (e != hipSuccess) return hip_fail(e, "batched occupancy");
     if (blocks < 1) return fail(FWBF_E_UNSUPPORTED, "batched kernel does not fit on a compute unit");
     if (blocks_per_cu > 0) blocks = std::min(blocks, blocks_per_cu);
-    const int64_t grid = std::min<int64_t>(total, (int64_t)blocks * cus);
+    const int64_t grid = std::min<int64_t>(tickets, (int64_t)blocks * cus);
     hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, st, b.counter);
     e = hipGetLastError();
     if (e == hipSuccess)

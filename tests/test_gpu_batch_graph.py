@@ -52,6 +52,29 @@ def test_mixed_code_batch_equals_per_code_decoding(T):
                     (zo, ito, oko), f"oracle N={code.N}")
 
 
+def test_batch_one_frame_per_wavefront_ragged_chunks():
+    """Short frames decoded one per wavefront inside 256-thread workgroups
+    (N = 186, EG(255) with strided blocks) next to frames that take the
+    whole workgroup (N = 4032), with frame counts that leave partial
+    chunks: equal to decoding each code alone."""
+    eg = fwbf.Code.from_text(synth.eg_code_text(4))
+    jobs = [(fwbf.Code.from_seed(3, 6, 31, 1), 1001, dict(groups=6)),
+            (eg, 333, dict(select=fwbf.STRIDED, groups=16, alpha=1.0)),
+            (fwbf.Code.from_seed(3, 6, 672, 3), 77, dict(groups=32))]
+    batch = []
+    for i, (code, F, kw) in enumerate(jobs):
+        y = _frames(code, F, 30 + i, torch.float32, 1.0)
+        batch.append((code, y, fwbf.DecodeParams(dtype=fwbf.F32, max_iter=60, **kw)))
+    outs = fwbf.decode_batched(batch)
+    torch.cuda.synchronize()
+    for (code, y, p), (z, it, ok) in zip(batch, outs):
+        print(f"batch item N={code.N} F={y.shape[0]}", flush=True)
+        zr, itr, okr = fwbf.decode(code, y, p)
+        torch.cuda.synchronize()
+        assert_same((z.cpu().numpy(), it.cpu().numpy(), ok.cpu().numpy()),
+                    (zr.cpu().numpy(), itr.cpu().numpy(), okr.cpu().numpy()), f"batch N={code.N}")
+
+
 def test_int8_batch_equals_fast_kernel():
     jobs = []
     for i, (spec, F, G) in enumerate([((3, 6, 31, 1), 700, 6), ((3, 6, 168, 2), 1500, 8)]):
