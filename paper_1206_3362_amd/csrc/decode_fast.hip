@@ -16,7 +16,11 @@
 //     minima are computed (each check adds its signed reliability to its
 //     members; the first check of a column also adds -a_num |y_n|);
 //   - winner bookkeeping (previous flips, flip masks, the unsatisfied-check
-//     count) stays in registers and wave ballots.
+//     count) stays in registers and wave ballots;
+//   - a workgroup holds FAST_WAVES independent wavefronts, each decoding its
+//     own frames with wavefront-scope barriers; the frame-independent tables
+//     (shifts, the slot of every bit) are stored once per workgroup, which
+//     with at most 96 VGPRs gives 5 wavefronts per SIMD.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,6 +33,7 @@ namespace fwbf {
 namespace {
 
 constexpr uint32_t NONE = 0xFFFFFFFFu;
+constexpr int FAST_WAVES = 4;  // independent wavefronts (frames) per workgroup
 
 struct FastArgs {
     const void *y;
@@ -47,7 +52,9 @@ struct FastArgs {
     int aden, anum, idxb;
     uint32_t idxmask, bias, zero_val;
     // LDS offsets in bytes
-    int o_chk, o_chkp, o_y, o_z, o_syn, o_list, o_sh, o_slot, lds_bytes;
+    // LDS: tables shared by the workgroup (o_sh, o_slot), then one region of
+    // wave_bytes per wavefront (offsets relative to the region; keys at 0)
+    int o_chk, o_chkp, o_y, o_z, o_syn, o_list, o_sh, o_slot, o_wave0, wave_bytes, lds_bytes;
 };
 
 __device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t mag, uint32_t mask)
@@ -110,31 +117,44 @@ template <> struct FT<FWBF_I16> {
     using Y = int16_t;
 };
 
+// Ordering of one wavefront's LDS operations across its lanes: a frame
+// belongs to one wavefront, whose LDS operations complete in issue order;
+// the fences and the wave barrier keep the compiler from moving memory
+// operations across this point.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int DT, int DV, int DC, int C>
-__global__ __launch_bounds__(64) void fast_kernel(FastArgs a)
+__global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu(5))) void fast_kernel(FastArgs a)
 {
     using Y = typename FT<DT>::Y;
     extern __shared__ __align__(16) unsigned char smem[];
-    uint32_t *keys = (uint32_t *)smem;
-    uint32_t *chk = (uint32_t *)(smem + a.o_chk);
-    uint8_t *chkp = smem + a.o_chkp;
-    Y *yv = (Y *)(smem + a.o_y);
-    uint32_t *zw = (uint32_t *)(smem + a.o_z);
-    uint32_t *syn = (uint32_t *)(smem + a.o_syn);
-    uint32_t *list = (uint32_t *)(smem + a.o_list);
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    unsigned char *wbase = smem + a.o_wave0 + wv * a.wave_bytes;
+    uint32_t *keys = (uint32_t *)wbase;
+    uint32_t *chk = (uint32_t *)(wbase + a.o_chk);
+    uint8_t *chkp = wbase + a.o_chkp;
+    Y *yv = (Y *)(wbase + a.o_y);
+    uint32_t *zw = (uint32_t *)(wbase + a.o_z);
+    uint32_t *syn = (uint32_t *)(wbase + a.o_syn);
+    uint32_t *list = (uint32_t *)(wbase + a.o_list);
     uint32_t *sh = (uint32_t *)(smem + a.o_sh);
     uint16_t *slotof = (uint16_t *)(smem + a.o_slot);  // slot word of every bit (frame-independent)
 
-    const uint32_t lane = threadIdx.x;
     const uint32_t Z = a.Z;
     const int N = a.N, M = a.M;
-    for (int t = lane; t < DV * a.nb; t += 64) sh[t] = a.shift[t];
-    for (int n = lane; n < a.N; n += 64) {
+    for (int t = threadIdx.x; t < DV * a.nb; t += 64 * FAST_WAVES) sh[t] = a.shift[t];
+    for (int n = threadIdx.x; n < a.N; n += 64 * FAST_WAVES) {
         uint32_t gg, pp;
         if (a.strided) { pp = fdiv(n, a.magG, a.maskG); gg = n - pp * a.Geff; }
         else { gg = fdiv(n, a.magP, a.maskP); pp = n - gg * a.p; }
         slotof[n] = (uint16_t)slot_addr(gg * a.L + pp / C, pp & (C - 1));
     }
+    __syncthreads();  // the only workgroup barrier: the wavefronts run independently from here
 
     // lane -> block layout
     const uint32_t g = lane >> a.logL;
@@ -145,11 +165,11 @@ __global__ __launch_bounds__(64) void fast_kernel(FastArgs a)
     auto bit_at = [&](uint32_t pos) { return a.strided ? pos * (uint32_t)a.Geff + g : gp + pos; };
     const int NW = (N + 31) >> 5;
 
-    const FrameRange fr = xcd_frames(a.F);
+    const FrameRange fr = xcd_frames_waves(a.F, FAST_WAVES, (int)wv);
     for (int64_t f = fr.first; f < fr.end; f += fr.step) {
         if (a.skip && a.skip[f]) continue;  // uniform across the wave
         const Y *yrow = (const Y *)a.y + f * a.stride;
-        __syncthreads();
+        wave_sync();
         for (int w = lane; w < ((M + 63) >> 6) * 2; w += 64) syn[w] = 0;
         for (int w = lane; w < ((N + 63) >> 6) * 2; w += 64) zw[w] = 0;
         // ---- received values -> LDS ---------------------------------------
@@ -188,7 +208,7 @@ __global__ __launch_bounds__(64) void fast_kernel(FastArgs a)
             }
             ((uint4 *)keys)[chunk_of(lane, kk >> 2)] = v;
         }
-        __syncthreads();
+        wave_sync();
         // hard decisions z_0 = [y < 0] (Section III, Initialization)
         for (int it = 0; it < 2; it++) {
             const int cidx = lane + 64 * it;
@@ -252,7 +272,7 @@ __global__ __launch_bounds__(64) void fast_kernel(FastArgs a)
                 if (valid && par) atomicOr(&syn[(i * Z + r) >> 5], 1u << ((i * Z + r) & 31));
             }
         }
-        __syncthreads();
+        wave_sync();
 
         int k = 0, okf = 0;
         uint32_t prv = NONE;
@@ -320,7 +340,7 @@ __global__ __launch_bounds__(64) void fast_kernel(FastArgs a)
                 k += 1;
                 if (weight == 0) { okf = 1; break; }
                 if (k == a.max_iter) break;
-                __syncthreads();
+                wave_sync();
                 // ---- member metric updates ---------------------------------
                 const int ntask = nflip * DV * DC;
                 for (int base = 0; base < ntask; base += 64) {
@@ -343,10 +363,10 @@ __global__ __launch_bounds__(64) void fast_kernel(FastArgs a)
                         atomicAdd(&keys[slotof[nq]], (uint32_t)d << a.idxb);
                     }
                 }
-                __syncthreads();
+                wave_sync();
             }
         }
-        __syncthreads();
+        wave_sync();
         uint32_t *zo = a.z + f * NW;
         for (int w = lane; w < NW; w += 64) zo[w] = zw[w];
         if (lane == 0) {
@@ -379,15 +399,15 @@ hipError_t launch_fast(const FastArgs &a, hipStream_t st, int *grid_out, bool qu
     if (a.lds_bytes > 65536)
         (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, a.lds_bytes);
     int blocks = 0, dev = 0, cus = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kern, 64, a.lds_bytes);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kern, 64 * FAST_WAVES, a.lds_bytes);
     if (e == hipSuccess) e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
     if (blocks < 1) return hipErrorInvalidConfiguration;
-    const int64_t grid = std::min<int64_t>(a.F, (int64_t)blocks * cus);
+    const int64_t grid = std::min<int64_t>((a.F + FAST_WAVES - 1) / FAST_WAVES, (int64_t)blocks * cus);
     *grid_out = (int)grid;
     if (query) return hipSuccess;
-    hipLaunchKernelGGL(kern, dim3((int)grid), dim3(64), a.lds_bytes, st, a);
+    hipLaunchKernelGGL(kern, dim3((int)grid), dim3(64 * FAST_WAVES), a.lds_bytes, st, a);
     return hipGetLastError();
 }
 
@@ -465,18 +485,21 @@ int try_fast_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int
     const int esz = p->dtype == FWBF_I8 ? 1 : 2;
     a.vec_ok = (((uintptr_t)y & 15) == 0) && ((stride * esz) % 16 == 0);
     // LDS layout
-    int off = 64 * C * 4;  // keys
+    int off = 0;
     auto take = [&](int bytes, int align) { off = (off + align - 1) / align * align; int o = off; off += bytes; return o; };
+    a.o_sh = take(4 * dv * c->nb, 4);
+    a.o_slot = take(2 * c->N, 4);
+    a.o_wave0 = (off + 15) / 16 * 16;
+    off = 64 * C * 4;  // keys, then the rest of one wavefront's frame state
     a.o_chk = take(4 * c->M, 4);
     a.o_chkp = take(p->dtype == FWBF_I16 ? c->M : 0, 4);
     a.o_y = take(esz * ((c->N + 15) / 16 * 16), 16);
     a.o_z = take(((c->N + 63) / 64) * 8, 8);
     a.o_syn = take(((c->M + 63) / 64) * 8, 8);
-    a.o_list = take(4 * dv * 64, 4);
-    a.o_sh = take(4 * dv * c->nb, 4);
-    a.o_slot = take(2 * c->N, 4);
-    a.lds_bytes = (off + 15) / 16 * 16;
-    if (a.lds_bytes > 64 * 1024) return 0;
+    a.o_list = take(4 * dv * a.Geff, 4);
+    a.wave_bytes = (off + 15) / 16 * 16;
+    a.lds_bytes = a.o_wave0 + FAST_WAVES * a.wave_bytes;
+    if (a.lds_bytes > 160 * 1024) return 0;
     a.y = y; a.F = F; a.stride = stride;
     a.z = z; a.iters = iters; a.ok = ok;
     a.shift = shift_dev;

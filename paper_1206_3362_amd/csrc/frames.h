@@ -29,3 +29,21 @@ __device__ __forceinline__ FrameRange xcd_frames(int64_t F)
 }
 
 }  // namespace fwbf
+
+namespace fwbf {
+
+// The same ranges when every workgroup runs W independent wavefronts, each
+// decoding its own frames: wavefront w of workgroup b is worker b*W + w
+// (all W on the XCD of b).
+__device__ __forceinline__ FrameRange xcd_frames_waves(int64_t F, int W, int w)
+{
+    constexpr int NX = 8;
+    const int64_t G = gridDim.x, b = blockIdx.x;
+    if (G % NX != 0 || F < G * W) return FrameRange{b * W + w, F, G * W};
+    const int64_t x = b % NX, per = G / NX;
+    const int64_t Fx = (F + NX - 1) / NX;
+    const int64_t end = (x + 1) * Fx < F ? (x + 1) * Fx : F;
+    return FrameRange{x * Fx + (b / NX) * W + w, end, per * W};
+}
+
+}  // namespace fwbf
