@@ -197,41 +197,61 @@ struct LearnArgs {
     uint32_t magZ, maskZ, magP, maskP;
     int p, L, logL, Geff, k, T;
     float A, dv;
-    int o_chk, o_y, o_z, o_syn, o_list, o_sh, o_cand, o_slot, o_net, lds_bytes;
+    // LDS: tables shared by the workgroup (o_sh, o_slot, o_net), then one
+    // region of wave_bytes per wavefront (offsets relative to it; slots at 0)
+    int o_chk, o_y, o_z, o_syn, o_list, o_sh, o_cand, o_slot, o_net, o_wave0, wave_bytes, lds_bytes;
 };
+
+// independent wavefronts (frames) per workgroup; the tables (shifts, slot
+// of every bit, scorer biases) are stored once per workgroup.  The kernel is
+// compiled for four wavefronts per SIMD (128 VGPRs, a few spilled), which
+// measured faster than three without spills.
+constexpr int LEARN_WAVES = 4;
+
+// barrier of the one wavefront that owns a frame (its LDS operations
+// complete in issue order; the fences keep the compiler from moving memory
+// operations across this point)
+__device__ __forceinline__ void lwave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __device__ __forceinline__ uint32_t slot_chunk(uint32_t lane, uint32_t kk) { return (kk << 6) + (lane ^ ((kk & 15) << 2)); }
 __device__ __forceinline__ uint32_t slot_word(uint32_t lane, uint32_t k) { return slot_chunk(lane, k >> 2) * 4 + (k & 3); }
 
 template <int DV, int DC, int C>
-__global__ __launch_bounds__(64) void learned_kernel(LearnArgs a)
+__global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_eu(4))) void learned_kernel(LearnArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    uint32_t *slots = (uint32_t *)smem;  // (S + SOFF) << 4 | u per bit
-    uint32_t *chk = (uint32_t *)(smem + a.o_chk);
-    int8_t *yv = (int8_t *)(smem + a.o_y);
-    uint32_t *zw = (uint32_t *)(smem + a.o_z);
-    uint32_t *syn = (uint32_t *)(smem + a.o_syn);
-    uint32_t *list = (uint32_t *)(smem + a.o_list);
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    unsigned char *wbase = smem + a.o_wave0 + wv * a.wave_bytes;
+    uint32_t *slots = (uint32_t *)wbase;  // (S + SOFF) << 4 | u per bit
+    uint32_t *chk = (uint32_t *)(wbase + a.o_chk);
+    int8_t *yv = (int8_t *)(wbase + a.o_y);
+    uint32_t *zw = (uint32_t *)(wbase + a.o_z);
+    uint32_t *syn = (uint32_t *)(wbase + a.o_syn);
+    uint32_t *list = (uint32_t *)(wbase + a.o_list);
+    uint4 *cand = (uint4 *)(wbase + a.o_cand);  // 32 proposals: n, S+SOFF, u, a
     uint32_t *sh = (uint32_t *)(smem + a.o_sh);
-    uint4 *cand = (uint4 *)(smem + a.o_cand);  // 32 proposals: n, S+SOFF, u, a
     uint16_t *slotof = (uint16_t *)(smem + a.o_slot);  // slot word of every bit
     float *nbias = (float *)(smem + a.o_net);               // b1[32], b2[32], W3[32]
 
-    const uint32_t lane = threadIdx.x;
     const uint32_t Z = a.Z;
     const int N = a.N, M = a.M;
-    for (int t = lane; t < DV * a.nb; t += 64) sh[t] = a.shift[t];
-    for (int n = lane; n < a.N; n += 64) {
+    for (int t = threadIdx.x; t < DV * a.nb; t += 64 * LEARN_WAVES) sh[t] = a.shift[t];
+    for (int n = threadIdx.x; n < a.N; n += 64 * LEARN_WAVES) {
         const uint32_t gg = fdiv(n, a.magP, a.maskP);
         const uint32_t pp = n - gg * a.p;
         slotof[n] = (uint16_t)slot_word(gg * a.L + pp / C, pp & (C - 1));
     }
-    for (int t = lane; t < 32; t += 64) {
+    for (int t = threadIdx.x; t < 32; t += 64 * LEARN_WAVES) {
         nbias[t] = a.params[O_B1 + t];
         nbias[32 + t] = a.params[O_B2 + t];
         nbias[64 + t] = a.params[O_W3 + t];
     }
+    __syncthreads();  // the only workgroup barrier: the wavefronts run independently from here
     NetL net;
     {
         const int i = lane & 31, hi = lane >> 5;
@@ -255,14 +275,14 @@ __global__ __launch_bounds__(64) void learned_kernel(LearnArgs a)
     const int NW = (N + 31) >> 5;
     const int NC = a.Geff * a.k;  // proposals per round (<= 32)
 
-    const FrameRange fr = xcd_frames(a.F);
+    const FrameRange fr = xcd_frames_waves(a.F, LEARN_WAVES, (int)wv);
     for (int64_t f = fr.first; f < fr.end; f += fr.step) {
         const int8_t *yrow = a.y + f * a.stride;
-        __syncthreads();
+        lwave_sync();
         for (int w = lane; w < ((M + 63) >> 6) * 2; w += 64) syn[w] = 0;
         for (int w = lane; w < ((N + 63) >> 6) * 2; w += 64) zw[w] = 0;
         for (int n = lane; n < N; n += 64) yv[n] = yrow[n];
-        __syncthreads();
+        lwave_sync();
         // slot words: S = 0, u = 0 and |y| of the slot's bit
         uint64_t realm = 0;
 #pragma unroll
@@ -288,7 +308,7 @@ __global__ __launch_bounds__(64) void learned_kernel(LearnArgs a)
                 zw[(n0 >> 5) + 1] = (uint32_t)(b >> 32);
             }
         }
-        __syncthreads();
+        lwave_sync();
         // check minima, syndrome, initial S and u pushed from the check side
         int weight = 0;
         for (int i = 0; i < DV; i++) {
@@ -327,7 +347,7 @@ __global__ __launch_bounds__(64) void learned_kernel(LearnArgs a)
                 if (valid && par) atomicOr(&syn[(i * Z + r) >> 5], 1u << ((i * Z + r) & 31));
             }
         }
-        __syncthreads();
+        lwave_sync();
 
         int t = 0, okf = 0, rec_end = 0;
         uint32_t prv = NONE;
@@ -365,7 +385,7 @@ __global__ __launch_bounds__(64) void learned_kernel(LearnArgs a)
                     cand[g * a.k + rk] = make_uint4(real ? gp + bpos : NONE, word, 0, 0);
                 }
             }
-            __syncthreads();
+            lwave_sync();
             // features of proposal lane % 32, score
             const uint32_t j = lane & 31;
             const uint4 cj = j < (uint32_t)NC ? cand[j] : make_uint4(NONE, 0, 0, 0);
@@ -435,7 +455,7 @@ __global__ __launch_bounds__(64) void learned_kernel(LearnArgs a)
             const int nflip = __popcll(fmask);
             weight += 2 * sum_ones - DV * nflip;
             t += 1;
-            __syncthreads();
+            lwave_sync();
             const int ntask = nflip * DV * DC;
             for (int base = 0; base < ntask; base += 64) {
                 const int tk = base + (int)lane;
@@ -451,9 +471,9 @@ __global__ __launch_bounds__(64) void learned_kernel(LearnArgs a)
                     atomicAdd(&slots[slotof[nq]], (uint32_t)d);
                 }
             }
-            __syncthreads();
+            lwave_sync();
         }
-        __syncthreads();
+        lwave_sync();
         // records of the rounds not run are marked invalid
         if (a.rec)
             for (int s = rec_end; s < a.T; s++)
@@ -741,19 +761,22 @@ extern "C" int fwbf_decode_learned(const fwbf_code *code, const fwbf_params *pla
     a.T = lp->rounds;
     a.A = lp->scale;
     a.dv = 3.0f;
-    int off = 64 * C * 4;
+    int off = 0;
     auto take = [&](int bytes, int align) { off = (off + align - 1) / align * align; int o = off; off += bytes; return o; };
+    a.o_net = take(4 * 96, 16);
+    a.o_sh = take(4 * 3 * code->nb, 4);
+    a.o_slot = take(2 * code->N, 4);
+    a.o_wave0 = (off + 15) / 16 * 16;
+    off = 64 * C * 4;  // slots, then the rest of one wavefront's frame state
     a.o_chk = take(4 * code->M, 4);
     a.o_y = take((code->N + 15) / 16 * 16, 16);
     a.o_z = take(((code->N + 63) / 64) * 8, 8);
     a.o_syn = take(((code->M + 63) / 64) * 8, 8);
-    a.o_list = take(4 * 3 * 64, 4);
-    a.o_sh = take(4 * 3 * code->nb, 4);
+    a.o_list = take(4 * 3 * a.Geff, 4);
     a.o_cand = take(16 * 32, 16);
-    a.o_slot = take(2 * code->N, 4);
-    a.o_net = take(4 * 96, 16);
-    a.lds_bytes = (off + 15) / 16 * 16;
-    if (a.lds_bytes > 64 * 1024) return fail(FWBF_E_UNSUPPORTED, "frame state exceeds 64 KiB of LDS");
+    a.wave_bytes = (off + 15) / 16 * 16;
+    a.lds_bytes = a.o_wave0 + LEARN_WAVES * a.wave_bytes;
+    if (a.lds_bytes > 160 * 1024) return fail(FWBF_E_UNSUPPORTED, "frame state exceeds 160 KiB of LDS");
     DeviceTables tb;
     rc = device_tables(const_cast<fwbf_code *>(code), &tb);
     if (rc) return rc;
@@ -764,13 +787,15 @@ extern "C" int fwbf_decode_learned(const fwbf_code *code, const fwbf_params *pla
     hipStream_t st = (hipStream_t)stream;
     auto launch = [&](auto kern) -> int {
         int blocks = 0, dev = 0, cus = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kern, 64, a.lds_bytes);
+        if (a.lds_bytes > 65536)
+            (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, a.lds_bytes);
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kern, 64 * LEARN_WAVES, a.lds_bytes);
         if (e == hipSuccess) e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) return hip_fail(e, "learned decode occupancy");
         if (blocks < 1) return fail(FWBF_E_UNSUPPORTED, "learned kernel does not fit");
-        const int64_t grid = std::min<int64_t>(F, (int64_t)blocks * cus);
-        hipLaunchKernelGGL(kern, dim3((int)grid), dim3(64), a.lds_bytes, st, a);
+        const int64_t grid = std::min<int64_t>((F + LEARN_WAVES - 1) / LEARN_WAVES, (int64_t)blocks * cus);
+        hipLaunchKernelGGL(kern, dim3((int)grid), dim3(64 * LEARN_WAVES), a.lds_bytes, st, a);
         e = hipGetLastError();
         return e == hipSuccess ? FWBF_OK : hip_fail(e, "learned decode launch");
     };
