@@ -1,6 +1,6 @@
 """CPU oracle for FWBF decoding -- test infrastructure only.
 
-This package is the judge the HIP library is checked against.  Only the test
+This package is the reference the HIP library is checked against.  Only the test
 suite, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import it; the product path never does.  It shares no code
 with ``paper_1206_3362_amd`` (the seeded input generators in

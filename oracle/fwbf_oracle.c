@@ -3,7 +3,7 @@
  * of LDPC codes (Ma, Li, Zhu, Zhang, Qi, "An Improved WBF Algorithm for
  * Higher-Speed Decoding of LDPC Codes").
  *
- * TEST INFRASTRUCTURE ONLY.  This file is the judge the GPU library is checked
+ * TEST INFRASTRUCTURE ONLY.  This file is the reference the GPU library is checked
  * against.  Only the test suite, the smoke check and the CPU-baseline leg of
  * the benchmark may load it.  It shares no code, header, table or constant
  * generator with the HIP library; the two sides only agree on the published
