@@ -58,9 +58,10 @@ class Trainer:
         import torch
         self.torch = torch
         self.code, self.cfg, self.dev = code, cfg, device
+        # the device comes up through torch before the library's first call
+        self.params = torch.from_numpy(init_params(cfg.rounds, seed=cfg.seed)).to(device)
         self.lp = fwbf.LearnedParams(cfg.rounds, cfg.groups, cfg.topk, 16.0)
         self.P = fwbf.scorer_size(cfg.rounds)
-        self.params = torch.from_numpy(init_params(cfg.rounds, seed=cfg.seed)).to(device)
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)
         self.grad = torch.zeros(self.P + 2, dtype=torch.float32, device=device)
@@ -119,3 +120,33 @@ class Trainer:
         self.m.copy_(self.torch.from_numpy(d["m"]))
         self.v.copy_(self.torch.from_numpy(d["v"]))
         self.step_count = int(d["step"])
+
+
+def main(argv=None):
+    """Train the scorer of the N=1008 (3,6) code on the GPU and write a
+    checkpoint: python -m paper_1206_3362_amd.learned --steps 512 --out x.npz"""
+    import argparse
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--steps", type=int, default=512, help="steps of --batch frames (512 x 8192 = 2^22)")
+    ap.add_argument("--batch", type=int, default=1 << 13)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--rounds", type=int, default=16)
+    ap.add_argument("--groups", type=int, default=32)
+    ap.add_argument("--topk", type=int, default=1)
+    ap.add_argument("--seed", type=int, default=7)
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    import torch
+    torch.zeros(1, device="cuda")  # bring the device up before the library loads
+    code = fwbf.Code.from_seed(3, 6, 168, 2)
+    cfg = TrainConfig(rounds=a.rounds, groups=a.groups, topk=a.topk, batch=a.batch, steps=a.steps,
+                      lr=a.lr, seed=a.seed)
+    tr = Trainer(code, cfg).train(log_every=max(1, a.steps // 16))
+    tr.torch.cuda.synchronize()
+    for step, loss, records, lpass in tr.history:
+        print(f"step {step}: loss {loss:.4f} records {records} learned-pass decoded {lpass:.3f}", flush=True)
+    tr.save(a.out)
+
+
+if __name__ == "__main__":
+    main()
