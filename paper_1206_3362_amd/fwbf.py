@@ -80,6 +80,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise FwbfError(E_INVALID, f"{LIB_PATH} not built (run __graft_entry__.build())")
+        # torch owns the device: bring it up before the library (and its HIP
+        # code objects) is loaded into the process
+        torch = _torch()
+        if torch.cuda.is_available():
+            torch.cuda.init()
         L = C.CDLL(LIB_PATH)
         vp, i32, i64, u64 = C.c_void_p, C.c_int, C.c_int64, C.c_uint64
         L.fwbf_last_error.restype = C.c_char_p
