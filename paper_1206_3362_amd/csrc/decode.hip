@@ -796,14 +796,16 @@ int occupancy(int DT, bool key32, int T, int lds, int *blocks)
 
 // Validates parameters and fills the kernel arguments (everything but the
 // data pointers).  Shared by the plain decoder and the batched launch.
-int prepare_decode(const fwbf_code *c, const fwbf_params *p, DecodeArgs *out, int *T_out, bool force_key64 = false);
+int prepare_decode(const fwbf_code *c, const fwbf_params *p, DecodeArgs *out, int *T_out, bool force_key64 = false,
+                   bool force_alias = false);
 int try_fast_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int64_t F, int64_t stride,
                     uint32_t *z, int32_t *iters, uint8_t *ok, hipStream_t st, const uint32_t *shift_dev,
                     const uint8_t *skip, int iters_add);
 int try_cyclic_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int64_t F, int64_t stride,
                       uint32_t *z, int32_t *iters, uint8_t *ok, hipStream_t st);
 
-int prepare_decode(const fwbf_code *c, const fwbf_params *p, DecodeArgs *out, int *T_out, bool force_key64)
+int prepare_decode(const fwbf_code *c, const fwbf_params *p, DecodeArgs *out, int *T_out, bool force_key64,
+                   bool force_alias)
 {
     if (!c || !p) return fail(FWBF_E_INVALID, "null code or params");
     if (p->dtype < FWBF_F32 || p->dtype > FWBF_I16) return fail(FWBF_E_INVALID, "unknown dtype");
@@ -899,7 +901,7 @@ int prepare_decode(const fwbf_code *c, const fwbf_params *p, DecodeArgs *out, in
         a.lds_bytes = (off + 15) / 16 * 16;
         a.mag_alias = alias ? 1 : 0;
     };
-    layout(false);
+    layout(force_alias);
     if (a.lds_bytes > 160 * 1024) layout(true);
     if (a.lds_bytes > 160 * 1024) return fail(FWBF_E_UNSUPPORTED, "frame state exceeds 160 KiB of LDS");
     a.idxb = key32 ? a.idxb : 0;
@@ -935,16 +937,30 @@ extern "C" int fwbf_decode(const fwbf_code *code, const fwbf_params *params, con
                              t.shift, nullptr, 0);
         if (rc != 0) return rc < 0 ? rc : FWBF_OK;
     }
-    a.y = y_dev; a.F = F; a.stride = y_stride;
-    a.z = z_dev; a.iters = iters_dev; a.ok = ok_dev;
-    a.col = t.col; a.row = t.row; a.coldeg = t.coldeg; a.rowdeg = t.rowdeg;
     int dev = 0, cus = 0, blocks = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return hip_fail(e, "device query");
     rc = occupancy(params->dtype, key32, T, a.lds_bytes, &blocks);
     if (rc) return rc;
+    if (!a.mag_alias) {
+        // staging |y| over the slots shrinks the frame's LDS; take that
+        // layout when it lets more frames share a compute unit
+        DecodeArgs b;
+        int Tb = 0, blocks_b = 0;
+        if (prepare_decode(code, params, &b, &Tb, false, true) == k) {
+            rc = occupancy(params->dtype, key32, T, b.lds_bytes, &blocks_b);
+            if (rc) return rc;
+            if (blocks_b > blocks) {
+                a = b;
+                blocks = blocks_b;
+            }
+        }
+    }
     if (blocks < 1) return fail(FWBF_E_UNSUPPORTED, "decode kernel does not fit on a compute unit");
+    a.y = y_dev; a.F = F; a.stride = y_stride;
+    a.z = z_dev; a.iters = iters_dev; a.ok = ok_dev;
+    a.col = t.col; a.row = t.row; a.coldeg = t.coldeg; a.rowdeg = t.rowdeg;
     const int64_t grid = std::min<int64_t>(F, (int64_t)blocks * cus);
     return dispatch(params->dtype, key32, T, a, (int)grid, (hipStream_t)stream);
 }
@@ -1018,56 +1034,83 @@ extern "C" int fwbf_decode_batched(const fwbf_batch_item *items, int n_items, in
             T = std::max(T, t);
         }
     }
-    BatchArgs b;
-    memset(&b, 0, sizeof b);
-    b.njobs = n_items;
-    int lds = 0;
-    int64_t total = 0, tickets = 0;
-    for (int i = 0; i < n_items; i++) {
-        const fwbf_batch_item &it = items[i];
-        fwbf_params p = *it.params;
-        // frames that take 64 threads on their own are decoded one per
-        // wavefront when the launch is wider (automatic width only)
-        const int N = it.code->N;
-        const bool wave = threads_per_frame == 0 && T > 64 && N <= 2048;
-        p.threads_per_frame = wave ? 64 : T;
-        int Ti = 0;
-        int k = prepare_decode(it.code, &p, &b.job[i], &Ti, true);
-        if (k < 0) return k;
-        b.wave[i] = wave && (int64_t)(T / 64) * b.job[i].lds_bytes <= 160 * 1024;
-        if (wave && !b.wave[i]) {
-            p.threads_per_frame = T;
-            k = prepare_decode(it.code, &p, &b.job[i], &Ti, true);
+    // builds the job table for one LDS layout; returns the dynamic LDS the
+    // launch needs (the largest job's), or an error code
+    int64_t total = 0;
+    for (int i = 0; i < n_items; i++) total += items[i].F;
+    auto build = [&](bool alias, BatchArgs &b) -> int {
+        memset(&b, 0, sizeof b);
+        b.njobs = n_items;
+        int lds = 0;
+        int64_t tickets = 0;
+        for (int i = 0; i < n_items; i++) {
+            const fwbf_batch_item &it = items[i];
+            fwbf_params p = *it.params;
+            // frames that take 64 threads on their own are decoded one per
+            // wavefront when the launch is wider (automatic width only)
+            const int N = it.code->N;
+            const bool wave = threads_per_frame == 0 && T > 64 && N <= 2048;
+            p.threads_per_frame = wave ? 64 : T;
+            int Ti = 0;
+            int k = prepare_decode(it.code, &p, &b.job[i], &Ti, true, alias);
             if (k < 0) return k;
+            b.wave[i] = wave && (int64_t)(T / 64) * b.job[i].lds_bytes <= 160 * 1024;
+            if (wave && !b.wave[i]) {
+                p.threads_per_frame = T;
+                k = prepare_decode(it.code, &p, &b.job[i], &Ti, true, alias);
+                if (k < 0) return k;
+            }
+            b.lds_job[i] = b.job[i].lds_bytes;
+            b.chunk[i] = b.wave[i] ? 4 * (T / 64) : 2;
+            DeviceTables tb;
+            const int rc = device_tables(const_cast<fwbf_code *>(it.code), &tb);
+            if (rc) return rc;
+            DecodeArgs &a = b.job[i];
+            a.y = it.y_dev; a.F = it.F; a.stride = it.y_stride;
+            a.z = it.z_dev; a.iters = it.iters_dev; a.ok = it.ok_dev;
+            a.col = tb.col; a.row = tb.row; a.coldeg = tb.coldeg; a.rowdeg = tb.rowdeg;
+            b.cbase[i] = tickets;
+            tickets += (it.F + b.chunk[i] - 1) / b.chunk[i];
+            lds = std::max(lds, b.wave[i] ? (T / 64) * a.lds_bytes : a.lds_bytes);
         }
-        b.lds_job[i] = b.job[i].lds_bytes;
-        b.chunk[i] = b.wave[i] ? 4 * (T / 64) : 2;
-        DeviceTables tb;
-        const int rc = device_tables(const_cast<fwbf_code *>(it.code), &tb);
-        if (rc) return rc;
-        DecodeArgs &a = b.job[i];
-        a.y = it.y_dev; a.F = it.F; a.stride = it.y_stride;
-        a.z = it.z_dev; a.iters = it.iters_dev; a.ok = it.ok_dev;
-        a.col = tb.col; a.row = tb.row; a.coldeg = tb.coldeg; a.rowdeg = tb.rowdeg;
-        b.cbase[i] = tickets;
-        total += it.F;
-        tickets += (it.F + b.chunk[i] - 1) / b.chunk[i];
-        lds = std::max(lds, b.wave[i] ? (T / 64) * a.lds_bytes : a.lds_bytes);
-    }
-    b.cbase[n_items] = tickets;
+        b.cbase[n_items] = tickets;
+        return lds;
+    };
+    auto blocks_for = [&](int lds, int *blocks) {
+        return dtype == FWBF_F32 ? occupancy_batched<FWBF_F32>(T, lds, blocks)
+               : dtype == FWBF_I8 ? occupancy_batched<FWBF_I8>(T, lds, blocks)
+                                  : occupancy_batched<FWBF_I16>(T, lds, blocks);
+    };
+    BatchArgs b;
+    int lds = build(false, b);
+    if (lds < 0) return lds;
     if (total == 0) return FWBF_OK;
-    b.counter = (unsigned long long *)workspace_dev;
     hipStream_t st = (hipStream_t)stream;
     int dev = 0, cus = 0, blocks = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = dtype == FWBF_F32 ? occupancy_batched<FWBF_F32>(T, lds, &blocks)
-                             : dtype == FWBF_I8 ? occupancy_batched<FWBF_I8>(T, lds, &blocks)
-                                                : occupancy_batched<FWBF_I16>(T, lds, &blocks);
+    if (e == hipSuccess) e = blocks_for(lds, &blocks);
     if (e != hipSuccess) return hip_fail(e, "batched occupancy");
+    {
+        // staging |y| over the slots shrinks every job's LDS (and lets more
+        // jobs take the one-frame-per-wavefront form); take that layout when
+        // it lets more workgroups share a compute unit
+        BatchArgs b2;
+        const int lds2 = build(true, b2);
+        if (lds2 < 0) return lds2;
+        int blocks2 = 0;
+        e = blocks_for(lds2, &blocks2);
+        if (e != hipSuccess) return hip_fail(e, "batched occupancy");
+        if (blocks2 > blocks) {
+            b = b2;
+            lds = lds2;
+            blocks = blocks2;
+        }
+    }
+    b.counter = (unsigned long long *)workspace_dev;
     if (blocks < 1) return fail(FWBF_E_UNSUPPORTED, "batched kernel does not fit on a compute unit");
     if (blocks_per_cu > 0) blocks = std::min(blocks, blocks_per_cu);
-    const int64_t grid = std::min<int64_t>(tickets, (int64_t)blocks * cus);
+    const int64_t grid = std::min<int64_t>(b.cbase[n_items], (int64_t)blocks * cus);
     hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, st, b.counter);
     e = hipGetLastError();
     if (e == hipSuccess)
