@@ -42,3 +42,30 @@ def assert_same(g, o, what=""):
     bad = np.nonzero((zg != zo).any(1) | (ig != io) | (kg != ko))[0]
     assert bad.size == 0, (f"{what}: {bad.size} frames differ, first {bad[:8].tolist()}; "
                            f"gpu iters {ig[bad[:4]].tolist()} oracle {io[bad[:4]].tolist()}")
+
+
+def check_properties(ocode, z, it, ok, max_iter, what):
+    """Syndrome flag == [H z = 0] and ok == 0 -> rounds == K_max, on every frame."""
+    rp, rb = ocode.rows()
+    M, N = ocode.M, ocode.N
+    deg = np.diff(rp)
+    members = np.full((M, int(deg.max())), N, np.int64)  # column N is a zero pad
+    for m in range(M):
+        members[m, :deg[m]] = rb[rp[m]:rp[m + 1]]
+    mem = torch.from_numpy(members).to(z.device)
+    F, W = z.shape
+    sh = torch.arange(32, device=z.device, dtype=torch.int32)
+    chunk = max(1, (1 << 28) // (M * members.shape[1]))
+    zero_syn = torch.empty(F, dtype=torch.bool, device=z.device)
+    for f0 in range(0, F, chunk):
+        zc = z[f0:f0 + chunk]
+        bits = ((zc.unsqueeze(-1) >> sh) & 1).to(torch.uint8).reshape(zc.shape[0], W * 32)[:, :N]
+        bits = torch.cat([bits, torch.zeros_like(bits[:, :1])], 1)
+        par = bits[:, mem].sum(-1, dtype=torch.int32) & 1
+        zero_syn[f0:f0 + chunk] = par.sum(1) == 0
+    okb = ok.bool()
+    n_bad = int((okb != zero_syn).sum())
+    assert n_bad == 0, f"{what}: {n_bad} frames whose flag disagrees with H z"
+    n_short = int(((~okb) & (it != max_iter)).sum())
+    assert n_short == 0, f"{what}: {n_short} failed frames stopped before K_max"
+    assert int(((it < 0) | (it > max_iter)).sum()) == 0, f"{what}: rounds outside [0, K_max]"
