@@ -293,18 +293,30 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
     const Y *yrow = (const Y *)a.y + f * a.stride;
     s.yrow = yrow;
     const int Nr = (N + 63) & ~63, Mr = (M + 63) & ~63;
-    for (int n = tid; n < Nr; n += T) {
-        bool neg = false;
-        if (n < N) {
-            const Y v = yrow[n];
-            neg = v < (Y)0;
-            if constexpr (Tt::isf) mag[n] = fabsf(v);
-            else mag[n] = (Mag)(v < 0 ? -(int)v : (int)v);
+    // eight loads in flight per thread before any is used (n < Nr is
+    // uniform across a wavefront: Nr is a multiple of 64)
+    constexpr int UNR = 8;
+    for (int n0 = tid; n0 < Nr; n0 += UNR * T) {
+        Y v[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; u++) {
+            const int n = n0 + u * T;
+            v[u] = n < N ? yrow[n] : (Y)0;
         }
-        const unsigned long long b = __ballot(neg);
-        if (lane == 0) {
-            s.zw[(n >> 5)] = (uint32_t)b;
-            s.zw[(n >> 5) + 1] = (uint32_t)(b >> 32);
+#pragma unroll
+        for (int u = 0; u < UNR; u++) {
+            const int n = n0 + u * T;
+            if (n >= Nr) break;
+            const bool neg = n < N && v[u] < (Y)0;
+            if (n < N) {
+                if constexpr (Tt::isf) mag[n] = fabsf(v[u]);
+                else mag[n] = (Mag)(v[u] < 0 ? -(int)v[u] : (int)v[u]);
+            }
+            const unsigned long long b = __ballot(neg);
+            if (lane == 0) {
+                s.zw[(n >> 5)] = (uint32_t)b;
+                s.zw[(n >> 5) + 1] = (uint32_t)(b >> 32);
+            }
         }
     }
     for (int w = tid; w < (Mr >> 5); w += T) s.tog[w] = 0;

@@ -196,6 +196,7 @@ struct LearnArgs {
     int N, M, Z, nb;
     uint32_t magZ, maskZ, magP, maskP;
     int p, L, logL, Geff, k, T;
+    int vec_ok;  // y and its row stride allow 16-byte loads
     float A, dv;
     // LDS: tables shared by the workgroup (o_sh, o_slot, o_net), then one
     // region of wave_bytes per wavefront (offsets relative to it; slots at 0)
@@ -281,7 +282,17 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
         lwave_sync();
         for (int w = lane; w < ((M + 63) >> 6) * 2; w += 64) syn[w] = 0;
         for (int w = lane; w < ((N + 63) >> 6) * 2; w += 64) zw[w] = 0;
-        for (int n = lane; n < N; n += 64) yv[n] = yrow[n];
+        {
+            // the frame in 16-byte pieces, both loads in flight together
+            const int nchunk = a.vec_ok ? min(N >> 4, 128) : 0;
+            const uint4 *src = (const uint4 *)yrow;
+            uint4 v0 = make_uint4(0, 0, 0, 0), v1 = v0;
+            if ((int)lane < nchunk) v0 = src[lane];
+            if ((int)lane + 64 < nchunk) v1 = src[lane + 64];
+            if ((int)lane < nchunk) ((uint4 *)yv)[lane] = v0;
+            if ((int)lane + 64 < nchunk) ((uint4 *)yv)[lane + 64] = v1;
+            for (int n = nchunk * 16 + (int)lane; n < N; n += 64) yv[n] = yrow[n];
+        }
         lwave_sync();
         // slot words: S = 0, u = 0 and |y| of the slot's bit
         uint64_t realm = 0;
@@ -781,6 +792,7 @@ extern "C" int fwbf_decode_learned(const fwbf_code *code, const fwbf_params *pla
     rc = device_tables(const_cast<fwbf_code *>(code), &tb);
     if (rc) return rc;
     a.y = (const int8_t *)y_dev; a.F = F; a.stride = y_stride;
+    a.vec_ok = (((uintptr_t)y_dev & 15) == 0) && (y_stride % 16 == 0);
     a.z = z_dev; a.iters = iters_dev; a.ok = ok_dev; a.learned_ok = learned_ok_dev;
     a.rec = records_dev; a.pool = pool_dev; a.pool_n = pool_n; a.f0 = f0;
     a.params = scorer_dev; a.shift = tb.shift;
