@@ -132,6 +132,7 @@ template <int DT, int DV, int DC, int C>
 __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu(5))) void fast_kernel(FastArgs a)
 {
     using Y = typename FT<DT>::Y;
+    constexpr int QB = DC <= 2 ? 1 : DC <= 4 ? 2 : DC <= 8 ? 3 : DC <= 16 ? 4 : DC <= 32 ? 5 : 6;  // bits of q
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     unsigned char *wbase = smem + a.o_wave0 + wv * a.wave_bytes;
@@ -233,8 +234,12 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                 const uint32_t r = r0 + lane;
                 const bool valid = r < Z;
                 uint32_t nn[DC], av[DC];
-                uint32_t m1 = 0xFFFFu, m2 = 0xFFFFu, pos = 0, par = 0;
+                uint32_t par = 0;
                 if (valid) {
+                    // the two smallest keys |y| << QB | q: their magnitudes are
+                    // min1 and min2 (with multiplicity), the first one's q is
+                    // the lowest position holding min1
+                    uint32_t k1 = 0xFFFFFFFFu, k2 = 0xFFFFFFFFu, sx = 0;
 #pragma unroll
                     for (int q = 0; q < DC; q++) {
                         const uint32_t n = q * Z + addmod(r, js[q], Z);
@@ -242,13 +247,14 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                         const uint32_t av_ = (uint32_t)(v < 0 ? -v : v);
                         nn[q] = n;
                         av[q] = av_;
-                        par ^= (uint32_t)(v < 0);
-                        const bool lt = av_ < m1;
-                        m2 = lt ? m1 : min(m2, av_);
-                        pos = lt ? (uint32_t)q : pos;
-                        m1 = lt ? av_ : m1;
+                        sx ^= (uint32_t)v;  // bit 31: parity of the negative members
+                        const uint32_t key = (av_ << QB) | (uint32_t)q;
+                        k2 = min(k2, max(k1, key));
+                        k1 = min(k1, key);
                     }
-                    if (DC < 2) m2 = 0;
+                    par = sx >> 31;
+                    const uint32_t m1 = k1 >> QB, pos = k1 & ((1u << QB) - 1);
+                    const uint32_t m2 = DC < 2 ? 0u : (k2 >> QB);
                     const uint32_t m = i * Z + r;
                     if constexpr (DT == FWBF_I8) {
                         chk[m] = m1 | (m2 << 8) | (pos << 16);
@@ -256,14 +262,16 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                         chk[m] = m1 | (m2 << 16);
                         chkp[m] = (uint8_t)pos;
                     }
-                    // push this check's term of eq. (1) to its members
+                    // push this check's term of eq. (1) to its members: the
+                    // two signed values (a_den w << idxb) are formed once
+                    const uint32_t e1 = __umul24((uint32_t)a.aden, m1) << a.idxb;
+                    const uint32_t e2 = __umul24((uint32_t)a.aden, a.imwbf ? m2 : m1) << a.idxb;
+                    const uint32_t d1 = par ? e1 : 0u - e1, d2 = par ? e2 : 0u - e2;
 #pragma unroll
                     for (int q = 0; q < DC; q++) {
-                        const uint32_t w = (a.imwbf && pos == (uint32_t)q) ? m2 : m1;
-                        int d = par ? a.aden * (int)w : -a.aden * (int)w;
-                        if (i == 0) d -= a.anum * (int)av[q];
-                        const uint32_t n = nn[q];
-                        atomicAdd(&keys[slotof[n]], (uint32_t)d << a.idxb);
+                        uint32_t d = pos == (uint32_t)q ? d2 : d1;
+                        if (i == 0) d -= __umul24((uint32_t)a.anum, av[q]) << a.idxb;
+                        atomicAdd(&keys[slotof[nn[q]]], d);
                     }
                 }
                 const unsigned long long b = __ballot(valid && par);
