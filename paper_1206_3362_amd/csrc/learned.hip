@@ -32,7 +32,8 @@ namespace {
 
 constexpr int H = 32;
 constexpr uint32_t NONE = 0xFFFFFFFFu;
-constexpr int SOFF = 2048;  // slot word: (S + SOFF) << 12 | |y| << 4 | u
+// slot word of a bit: S << 16 (S signed, |S| <= dv * 128) + |y| << 8 + u (u <= dv);
+// adds to S and u never carry or borrow across the fields
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -225,16 +226,17 @@ __device__ __forceinline__ uint32_t slot_word(uint32_t lane, uint32_t k) { retur
 template <int DV, int DC, int C>
 __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_eu(4))) void learned_kernel(LearnArgs a)
 {
+    static_assert(DC <= 8, "check positions are packed in 3 bits");
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     unsigned char *wbase = smem + a.o_wave0 + wv * a.wave_bytes;
-    uint32_t *slots = (uint32_t *)wbase;  // (S + SOFF) << 4 | u per bit
+    uint32_t *slots = (uint32_t *)wbase;  // slot words
     uint32_t *chk = (uint32_t *)(wbase + a.o_chk);
     int8_t *yv = (int8_t *)(wbase + a.o_y);
     uint32_t *zw = (uint32_t *)(wbase + a.o_z);
     uint32_t *syn = (uint32_t *)(wbase + a.o_syn);
     uint32_t *list = (uint32_t *)(wbase + a.o_list);
-    uint4 *cand = (uint4 *)(wbase + a.o_cand);  // 32 proposals: n, S+SOFF, u, a
+    uint4 *cand = (uint4 *)(wbase + a.o_cand);  // 32 proposals: n, slot word
     uint32_t *sh = (uint32_t *)(smem + a.o_sh);
     uint16_t *slotof = (uint16_t *)(smem + a.o_slot);  // slot word of every bit
     float *nbias = (float *)(smem + a.o_net);               // b1[32], b2[32], W3[32]
@@ -306,7 +308,7 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
                 const uint32_t n = gp + pos;
                 const bool real = (int)g < a.Geff && (int)pos < a.p && (int)n < N;
                 const int yn = real ? (int)yv[n] : 0;
-                vp[u] = ((uint32_t)SOFF << 12) | ((uint32_t)(yn < 0 ? -yn : yn) << 4);
+                vp[u] = (uint32_t)(yn < 0 ? -yn : yn) << 8;
                 realm |= (uint64_t)real << (kk + u);
             }
             ((uint4 *)slots)[slot_chunk(lane, kk >> 2)] = v;
@@ -330,28 +332,30 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
                 const uint32_t r = r0 + lane;
                 const bool valid = r < Z;
                 uint32_t nn[DC];
-                uint32_t m1 = 0xFFFFu, m2 = 0xFFFFu, pos = 0, par = 0;
+                uint32_t par = 0;
                 if (valid) {
+                    // the two smallest keys |y| << 3 | q (q < 8): min1, min2 (with
+                    // multiplicity) and the lowest position holding min1
+                    uint32_t k1 = 0xFFFFFFFFu, k2 = 0xFFFFFFFFu, sx = 0;
 #pragma unroll
                     for (int q = 0; q < DC; q++) {
                         const uint32_t n = q * Z + addmod(r, js[q], Z);
                         const int v = (int)yv[n];
                         const uint32_t av = (uint32_t)(v < 0 ? -v : v);
                         nn[q] = n;
-                        par ^= (uint32_t)(v < 0);
-                        const bool lt = av < m1;
-                        m2 = lt ? m1 : min(m2, av);
-                        pos = lt ? (uint32_t)q : pos;
-                        m1 = lt ? av : m1;
+                        sx ^= (uint32_t)v;  // bit 31: parity of the negative members
+                        const uint32_t key = (av << 3) | (uint32_t)q;
+                        k2 = min(k2, max(k1, key));
+                        k1 = min(k1, key);
                     }
+                    par = sx >> 31;
+                    const uint32_t m1 = k1 >> 3, m2 = k2 >> 3, pos = k1 & 7u;
                     chk[i * Z + r] = m1 | (m2 << 8) | (pos << 16);
+                    // the check's two signed terms, formed once
+                    const uint32_t d1 = ((uint32_t)(par ? (int)m1 : -(int)m1) << 16) + par;
+                    const uint32_t d2 = ((uint32_t)(par ? (int)m2 : -(int)m2) << 16) + par;
 #pragma unroll
-                    for (int q = 0; q < DC; q++) {
-                        const uint32_t w = (pos == (uint32_t)q) ? m2 : m1;
-                        const int d = ((par ? (int)w : -(int)w) << 12) + (int)par;
-                        const uint32_t n = nn[q];
-                        atomicAdd(&slots[slotof[n]], (uint32_t)d);
-                    }
+                    for (int q = 0; q < DC; q++) atomicAdd(&slots[slotof[nn[q]]], pos == (uint32_t)q ? d2 : d1);
                 }
                 const unsigned long long b = __ballot(valid && par);
                 weight += __popcll(b);
@@ -371,22 +375,29 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
             // excluded before the next pass
             uint64_t excl = 0;
             for (int rk = 0; rk < a.k; rk++) {
-                unsigned long long best = 0;
+                // the lane's best live slot, scanned in ascending position with
+                // a strict comparison (ties keep the lower position; -0 == +0)
+                const uint64_t livem = realm & ~excl;
+                float bE = -__builtin_huge_valf();  // E is finite: a live slot always beats it
+                uint32_t bi = NONE;                  // no live slot yet
 #pragma unroll
                 for (int kk = 0; kk < C; kk += 4) {
                     const uint4 v = ((const uint4 *)slots)[slot_chunk(lane, kk >> 2)];
                     const uint32_t vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
                     for (int u = 0; u < 4; u++) {
-                        const float S = (float)((int)(vv[u] >> 12) - SOFF);
-                        const float E = __builtin_fmaf(-al, (float)((vv[u] >> 4) & 0xFFu), be * S);
-                        const bool live = ((realm & ~excl) >> (kk + u)) & 1;
-                        const unsigned long long key = live ? (((unsigned long long)orderable(E) << 32) |
-                                                               (0xFFFFFFFFu - (pos0 + kk + u)))
-                                                            : 0ull;
-                        best = umax64(best, key);
+                        const float S = (float)((int32_t)vv[u] >> 16);
+                        const float E = __builtin_fmaf(-al, (float)((vv[u] >> 8) & 0xFFu), be * S);
+                        const uint32_t lm = kk + u < 32 ? (uint32_t)livem : (uint32_t)(livem >> 32);
+                        const bool live = (lm >> ((kk + u) & 31)) & 1;
+                        const bool take = live && E > bE;
+                        bE = take ? E : bE;
+                        bi = take ? (uint32_t)(kk + u) : bi;
                     }
                 }
+                unsigned long long best = bi == NONE ? 0ull
+                                                     : (((unsigned long long)orderable(bE) << 32) |
+                                                        (0xFFFFFFFFu - (pos0 + bi)));
                 best = group_max64(best, a.L);
                 const uint32_t bpos = 0xFFFFFFFFu - (uint32_t)best;
                 const bool real = (best >> 32) != 0;
@@ -401,8 +412,8 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
             const uint32_t j = lane & 31;
             const uint4 cj = j < (uint32_t)NC ? cand[j] : make_uint4(NONE, 0, 0, 0);
             const bool realc = cj.x != NONE;
-            const int cS = (int)(cj.y >> 12) - SOFF;
-            const uint32_t ca = (cj.y >> 4) & 0xFFu, cu = cj.y & 15u;
+            const int cS = (int32_t)cj.y >> 16;
+            const uint32_t ca = (cj.y >> 8) & 0xFFu, cu = cj.y & 0xFFu;
             bf16x4 x = pack4(0.f, 0.f, 0.f, 0.f);
             if (lane < 32 && realc) {
                 const float E = __builtin_fmaf(-al, (float)ca, be * (float)cS);
@@ -478,7 +489,7 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
                     const uint32_t nq = q * Z + addmod(r, sh[i * a.nb + q], Z);
                     const uint32_t cwd = chk[m];
                     const uint32_t w = (((cwd >> 16) & 0xFF) == (uint32_t)q) ? ((cwd >> 8) & 0xFF) : (cwd & 0xFF);
-                    const int d = (e >> 31) ? ((2 * (int)w) << 12) + 1 : -((2 * (int)w) << 12) - 1;
+                    const uint32_t d = (e >> 31) ? ((2u * w) << 16) + 1u : 0u - (((2u * w) << 16) + 1u);
                     atomicAdd(&slots[slotof[nq]], (uint32_t)d);
                 }
             }
