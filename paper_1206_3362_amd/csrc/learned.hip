@@ -87,11 +87,11 @@ __device__ void load_net(Net &n, const float *p)
     n.b3 = p[O_B3];
 }
 
-// decode-side network: MFMA weight operands in registers, biases and W3 in
-// LDS (read per row), to keep the kernel's register count low
+// decode-side network: everything in LDS (the MFMA weight operands per lane,
+// biases and W3 per row), read at each scoring, to keep the kernel's register
+// count low
 struct NetL {
-    bf16x4 w1;
-    bf16x4 w2[4];
+    const bf16x4 *wq;           // lane l: W1 operand at wq[5l], W2 operands at wq[5l + 1 + c]
     const float *b1, *b2, *w3;  // LDS copies
     float b3;
 };
@@ -99,8 +99,9 @@ struct NetL {
 __device__ __forceinline__ float net_score(const NetL &n, bf16x4 x)
 {
     const int l = threadIdx.x & 63;
+    const bf16x4 *wl = n.wq + 5 * l;
     f32x16 acc = {};
-    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(n.w1, x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(wl[0], x, acc, 0, 0, 0);
     bf16x4 h1[4];
     for (int c = 0; c < 4; c++) {
         float h[4];
@@ -108,7 +109,7 @@ __device__ __forceinline__ float net_score(const NetL &n, bf16x4 x)
         h1[c] = pack4(h[0], h[1], h[2], h[3]);
     }
     f32x16 acc2 = {};
-    for (int c = 0; c < 4; c++) acc2 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(n.w2[c], h1[c], acc2, 0, 0, 0);
+    for (int c = 0; c < 4; c++) acc2 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(wl[1 + c], h1[c], acc2, 0, 0, 0);
     float part = 0.0f;
     for (int q = 0; q < 16; q++) {
         const int row = row_of(q, l);
@@ -199,9 +200,9 @@ struct LearnArgs {
     int p, L, logL, Geff, k, T;
     int vec_ok;  // y and its row stride allow 16-byte loads
     float A, dv;
-    // LDS: tables shared by the workgroup (o_sh, o_slot, o_net), then one
+    // LDS: tables shared by the workgroup (o_sh, o_slot, o_net, o_netw), then one
     // region of wave_bytes per wavefront (offsets relative to it; slots at 0)
-    int o_chk, o_y, o_z, o_syn, o_list, o_sh, o_cand, o_slot, o_net, o_wave0, wave_bytes, lds_bytes;
+    int o_chk, o_y, o_z, o_syn, o_list, o_sh, o_cand, o_slot, o_net, o_netw, o_wave0, wave_bytes, lds_bytes;
 };
 
 // independent wavefronts (frames) per workgroup; the tables (shifts, slot
@@ -240,6 +241,7 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
     uint32_t *sh = (uint32_t *)(smem + a.o_sh);
     uint16_t *slotof = (uint16_t *)(smem + a.o_slot);  // slot word of every bit
     float *nbias = (float *)(smem + a.o_net);               // b1[32], b2[32], W3[32]
+    bf16x4 *nw = (bf16x4 *)(smem + a.o_netw);               // MFMA weight operands, 5 per lane
 
     const uint32_t Z = a.Z;
     const int N = a.N, M = a.M;
@@ -254,17 +256,23 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
         nbias[32 + t] = a.params[O_B2 + t];
         nbias[64 + t] = a.params[O_W3 + t];
     }
+    if (threadIdx.x < 64) {
+        // MFMA operands of lane l: W1[l%32][4(l/32) + 0..3] (zero for the
+        // upper half: only 4 inputs), W2[l%32][8c + 4(l/32) + 0..3]
+        const int i = lane & 31, hi = lane >> 5;
+        const float *p = a.params;
+        nw[5 * lane] = hi == 0 ? pack4(p[O_W1 + i * 4 + 0], p[O_W1 + i * 4 + 1], p[O_W1 + i * 4 + 2], p[O_W1 + i * 4 + 3])
+                               : pack4(0.f, 0.f, 0.f, 0.f);
+        for (int c = 0; c < 4; c++) {
+            const float *r = p + O_W2 + i * H + 8 * c + 4 * hi;
+            nw[5 * lane + 1 + c] = pack4(r[0], r[1], r[2], r[3]);
+        }
+    }
     __syncthreads();  // the only workgroup barrier: the wavefronts run independently from here
     NetL net;
     {
-        const int i = lane & 31, hi = lane >> 5;
         const float *p = a.params;
-        net.w1 = hi == 0 ? pack4(p[O_W1 + i * 4 + 0], p[O_W1 + i * 4 + 1], p[O_W1 + i * 4 + 2], p[O_W1 + i * 4 + 3])
-                         : pack4(0.f, 0.f, 0.f, 0.f);
-        for (int c = 0; c < 4; c++) {
-            const float *r = p + O_W2 + i * H + 8 * c + 4 * hi;
-            net.w2[c] = pack4(r[0], r[1], r[2], r[3]);
-        }
+        net.wq = nw;
         net.b1 = nbias;
         net.b2 = nbias + 32;
         net.w3 = nbias + 64;
@@ -279,27 +287,61 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
     const int NC = a.Geff * a.k;  // proposals per round (<= 32)
 
     const FrameRange fr = xcd_frames_waves(a.F, LEARN_WAVES, (int)wv);
+    const int nchunk = a.vec_ok ? min(N >> 4, 128) : 0;
+    // the 16-byte pieces of a frame (up to two per lane; every lane loads,
+    // idle lanes a copy of the last piece, so the loads need no lane mask)
+    auto fetch = [&](int64_t ff, uint4 *x) {
+        if (nchunk == 0) return;
+        const uint4 *src = (const uint4 *)(a.y + ff * a.stride);
+        x[0] = src[min((int)lane, nchunk - 1)];
+        if (nchunk > 64) x[1] = src[min((int)lane + 64, nchunk - 1)];
+    };
+    // the next frame's pieces are loaded while the current frame decodes
+    uint4 nxt[2] = {make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0)};
+    if (fr.first < fr.end) fetch(fr.first, nxt);
     for (int64_t f = fr.first; f < fr.end; f += fr.step) {
         const int8_t *yrow = a.y + f * a.stride;
+        const uint4 vc[2] = {nxt[0], nxt[1]};
+        if (f + fr.step < fr.end) fetch(f + fr.step, nxt);
         lwave_sync();
         for (int w = lane; w < ((M + 63) >> 6) * 2; w += 64) syn[w] = 0;
         for (int w = lane; w < ((N + 63) >> 6) * 2; w += 64) zw[w] = 0;
         {
-            // the frame in 16-byte pieces, both loads in flight together
-            const int nchunk = a.vec_ok ? min(N >> 4, 128) : 0;
-            const uint4 *src = (const uint4 *)yrow;
-            uint4 v0 = make_uint4(0, 0, 0, 0), v1 = v0;
-            if ((int)lane < nchunk) v0 = src[lane];
-            if ((int)lane + 64 < nchunk) v1 = src[lane + 64];
-            if ((int)lane < nchunk) ((uint4 *)yv)[lane] = v0;
-            if ((int)lane + 64 < nchunk) ((uint4 *)yv)[lane + 64] = v1;
-            for (int n = nchunk * 16 + (int)lane; n < N; n += 64) yv[n] = yrow[n];
+            // the frame's pieces to LDS; z_0 = [y < 0] from their sign bits
+#pragma unroll
+            for (int it = 0; it < 2; it++) {
+                const int cidx = (int)lane + 64 * it;
+                if (cidx < nchunk) {
+                    ((uint4 *)yv)[cidx] = vc[it];
+                    const uint32_t xs[4] = {vc[it].x, vc[it].y, vc[it].z, vc[it].w};
+                    uint32_t msk = 0;
+#pragma unroll
+                    for (int u = 0; u < 4; u++)
+                        msk |= (((((xs[u] >> 7) & 0x01010101u) * 0x01020408u) >> 24) & 0xFu) << (4 * u);
+                    if (msk) atomicOr(&zw[cidx >> 1], msk << (16 * (cidx & 1)));
+                }
+            }
+            for (int n = nchunk * 16 + (int)lane; n < N; n += 64) {
+                const int8_t v = yrow[n];
+                yv[n] = v;
+                if (v < 0) atomicOr(&zw[n >> 5], 1u << (n & 31));
+            }
         }
         lwave_sync();
-        // slot words: S = 0, u = 0 and |y| of the slot's bit
+        // slot words: S = 0, u = 0 and |y| of the slot's bit; when every
+        // lane's slots are 16 aligned consecutive bits, |y| comes from one
+        // 16-byte read per 16 slots
+        const bool a16 = (C % 16 == 0) && (a.p % 16 == 0);
         uint64_t realm = 0;
+        uint4 y16 = make_uint4(0, 0, 0, 0);
 #pragma unroll
         for (int kk = 0; kk < C; kk += 4) {
+            if (a16 && (kk & 15) == 0) {
+                const uint32_t n0 = gp + pos0 + kk;
+                y16 = (int)g < a.Geff && (int)n0 < N ? ((const uint4 *)yv)[n0 >> 4] : make_uint4(0, 0, 0, 0);
+            }
+            const uint32_t yw = ((kk & 15) >> 2) == 0 ? y16.x : ((kk & 15) >> 2) == 1 ? y16.y
+                              : ((kk & 15) >> 2) == 2 ? y16.z : y16.w;
             uint4 v;
             uint32_t *vp = (uint32_t *)&v;
 #pragma unroll
@@ -307,19 +349,12 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
                 const uint32_t pos = pos0 + kk + u;
                 const uint32_t n = gp + pos;
                 const bool real = (int)g < a.Geff && (int)pos < a.p && (int)n < N;
-                const int yn = real ? (int)yv[n] : 0;
+                int yn = a16 ? (int)(int8_t)(yw >> (8 * u)) : (real ? (int)yv[n] : 0);
+                yn = real ? yn : 0;
                 vp[u] = (uint32_t)(yn < 0 ? -yn : yn) << 8;
                 realm |= (uint64_t)real << (kk + u);
             }
             ((uint4 *)slots)[slot_chunk(lane, kk >> 2)] = v;
-        }
-        for (int n0 = 0; n0 < N; n0 += 64) {
-            const int n = n0 + (int)lane;
-            const unsigned long long b = __ballot(n < N && yv[n] < 0);
-            if (lane == 0) {
-                zw[n0 >> 5] = (uint32_t)b;
-                zw[(n0 >> 5) + 1] = (uint32_t)(b >> 32);
-            }
         }
         lwave_sync();
         // check minima, syndrome, initial S and u pushed from the check side
@@ -786,6 +821,7 @@ extern "C" int fwbf_decode_learned(const fwbf_code *code, const fwbf_params *pla
     int off = 0;
     auto take = [&](int bytes, int align) { off = (off + align - 1) / align * align; int o = off; off += bytes; return o; };
     a.o_net = take(4 * 96, 16);
+    a.o_netw = take(64 * 5 * 8, 16);
     a.o_sh = take(4 * 3 * code->nb, 4);
     a.o_slot = take(2 * code->N, 4);
     a.o_wave0 = (off + 15) / 16 * 16;
