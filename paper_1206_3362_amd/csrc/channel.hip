@@ -93,32 +93,64 @@ __global__ __launch_bounds__(256) void count_kernel(int N, int64_t F, int64_t f0
                                                     const uint8_t *ok, int max_iter,
                                                     unsigned long long *counters)
 {
-    extern __shared__ unsigned long long part[];  // 6 + max_iter + 1
-    const int nc = 7 + max_iter;
-    for (int t = threadIdx.x; t < nc; t += blockDim.x) part[t] = 0;
-    __syncthreads();
-    const int NW = (N + 31) >> 5;
+    // per wavefront: a histogram of rounds (max_iter + 1 bins, 32-bit), then
+    // 6 workgroup totals (64-bit)
+    extern __shared__ unsigned long long lds_count[];
+    const int nbin = max_iter + 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
-    for (int64_t f = (int64_t)blockIdx.x * nwave + wave; f < F; f += (int64_t)gridDim.x * nwave) {
-        const int64_t fa = f0 + f;
-        const uint32_t *cw = pool ? pool + (size_t)(fa % pool_n) * NW : nullptr;
-        uint32_t be = 0;
-        for (int w = lane; w < NW; w += 64) be += __popc(z[f * NW + w] ^ (cw ? cw[w] : 0u));
-        for (int d = 32; d >= 1; d >>= 1) be += __shfl_xor(be, d, 64);
-        if (lane == 0) {
+    uint32_t *hist = (uint32_t *)lds_count;
+    unsigned long long *tot = lds_count + (nwave * nbin + 1) / 2;
+    for (int t = threadIdx.x; t < nwave * nbin; t += blockDim.x) hist[t] = 0;
+    for (int t = threadIdx.x; t < 6; t += blockDim.x) tot[t] = 0;
+    __syncthreads();
+    uint32_t *h = hist + wave * nbin;
+    // a wavefront pass covers P frames of NWp lanes each (one word per lane;
+    // NWp = 64 and a word loop when a frame has more than 64 words)
+    const int NW = (N + 31) >> 5;
+    int NWp = 1;
+    while (NWp < NW && NWp < 64) NWp <<= 1;
+    const int P = 64 / NWp;
+    const int sub = lane / NWp, wl = lane % NWp;
+    const unsigned long long smask = NWp == 64 ? ~0ull : (((1ull << NWp) - 1) << (sub * NWp));
+    unsigned long long bit_err = 0, it_sum = 0, frame_err = 0, undet = 0, nfr = 0, nok = 0;
+    for (int64_t fb = ((int64_t)blockIdx.x * nwave + wave) * P; fb < F; fb += (int64_t)gridDim.x * nwave * P) {
+        const int64_t f = fb + sub;
+        bool err = false;
+        if (f < F) {
+            const uint32_t *cw = pool ? pool + (size_t)((f0 + f) % pool_n) * NW : nullptr;
+            for (int w = wl; w < NW; w += NWp) {
+                const uint32_t d = z[f * NW + w] ^ (cw ? cw[w] : 0u);
+                bit_err += __popc(d);
+                err |= d != 0;
+            }
+        }
+        const bool fe = (__ballot(err) & smask) != 0;  // some word of this lane's frame differs
+        if (wl == 0 && f < F) {
             const int it = iters[f];
-            atomicAdd(&part[0], (unsigned long long)be);
-            if (be) atomicAdd(&part[1], 1ull);
-            if (be && ok[f]) atomicAdd(&part[2], 1ull);
-            atomicAdd(&part[3], (unsigned long long)it);
-            atomicAdd(&part[4], 1ull);
-            if (ok[f]) atomicAdd(&part[5], 1ull);
-            if (it >= 0 && it <= max_iter) atomicAdd(&part[6 + it], 1ull);
+            const bool okf = ok[f] != 0;
+            frame_err += fe;
+            undet += fe && okf;
+            it_sum += (unsigned long long)(int64_t)it;
+            nfr += 1;
+            nok += okf;
+            if (it >= 0 && it <= max_iter) atomicAdd(&h[it], 1u);
         }
     }
+    // totals: wavefront sums, then one LDS atomic per wavefront and counter
+    unsigned long long v[6] = {bit_err, frame_err, undet, it_sum, nfr, nok};
+#pragma unroll
+    for (int c = 0; c < 6; c++) {
+        for (int d = 32; d >= 1; d >>= 1) v[c] += __shfl_xor(v[c], d, 64);
+        if (lane == 0 && v[c]) atomicAdd(&tot[c], v[c]);
+    }
     __syncthreads();
-    for (int t = threadIdx.x; t < nc; t += blockDim.x)
-        if (part[t]) atomicAdd(&counters[t], part[t]);
+    for (int t = threadIdx.x; t < 6; t += blockDim.x)
+        if (tot[t]) atomicAdd(&counters[t], tot[t]);
+    for (int b = threadIdx.x; b < nbin; b += blockDim.x) {
+        unsigned long long sum = 0;
+        for (int w = 0; w < nwave; w++) sum += hist[w * nbin + b];
+        if (sum) atomicAdd(&counters[6 + b], sum);
+    }
 }
 
 int grid_for(int64_t work, int block)
@@ -171,7 +203,9 @@ extern "C" int fwbf_count(int N, int64_t F, int64_t f0, const uint32_t *z_dev, c
     if (F == 0) return FWBF_OK;
     if (!z_dev || !iters_dev || !ok_dev || !counters_dev) return fail(FWBF_E_INVALID, "null buffer");
     const int grid = grid_for(F * 64, 256);
-    const size_t lds = sizeof(unsigned long long) * (7 + max_iter);
+    const size_t lds = sizeof(uint32_t) * 4 * (size_t)(max_iter + 1) + 8 + sizeof(unsigned long long) * 6;
+    if (lds > 65536)
+        (void)hipFuncSetAttribute((const void *)count_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(count_kernel, dim3(grid), dim3(256), lds, (hipStream_t)stream, N, F, f0, z_dev, pool_dev,
                        pool_n, iters_dev, ok_dev, max_iter, (unsigned long long *)counters_dev);
     hipError_t e = hipGetLastError();
