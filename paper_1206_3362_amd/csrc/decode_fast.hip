@@ -233,19 +233,27 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
             for (uint32_t r0 = 0; r0 < Z; r0 += 64) {
                 const uint32_t r = r0 + lane;
                 const bool valid = r < Z;
-                uint32_t nn[DC], av[DC];
+                uint32_t nn[DC], av[DC], sl[DC];
+                int yq[DC];
                 uint32_t par = 0;
                 if (valid) {
+                    // every LDS read of the check first (its members' values
+                    // and slots), so that they are in flight together and
+                    // none waits behind the atomic pushes below
+#pragma unroll
+                    for (int q = 0; q < DC; q++) nn[q] = q * Z + addmod(r, js[q], Z);
+#pragma unroll
+                    for (int q = 0; q < DC; q++) yq[q] = (int)yv[nn[q]];
+#pragma unroll
+                    for (int q = 0; q < DC; q++) sl[q] = slotof[nn[q]];
                     // the two smallest keys |y| << QB | q: their magnitudes are
                     // min1 and min2 (with multiplicity), the first one's q is
                     // the lowest position holding min1
                     uint32_t k1 = 0xFFFFFFFFu, k2 = 0xFFFFFFFFu, sx = 0;
 #pragma unroll
                     for (int q = 0; q < DC; q++) {
-                        const uint32_t n = q * Z + addmod(r, js[q], Z);
-                        const int v = (int)yv[n];
+                        const int v = yq[q];
                         const uint32_t av_ = (uint32_t)(v < 0 ? -v : v);
-                        nn[q] = n;
                         av[q] = av_;
                         sx ^= (uint32_t)v;  // bit 31: parity of the negative members
                         const uint32_t key = (av_ << QB) | (uint32_t)q;
@@ -271,7 +279,7 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                     for (int q = 0; q < DC; q++) {
                         uint32_t d = pos == (uint32_t)q ? d2 : d1;
                         if (i == 0) d -= __umul24((uint32_t)a.anum, av[q]) << a.idxb;
-                        atomicAdd(&keys[slotof[nn[q]]], d);
+                        atomicAdd(&keys[sl[q]], d);
                     }
                 }
                 const unsigned long long b = __ballot(valid && par);
@@ -350,25 +358,31 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                 if (k == a.max_iter) break;
                 wave_sync();
                 // ---- member metric updates ---------------------------------
+                // (check, member) tasks, 64 per pass.  ntask <= 64 blocks *
+                // DV * DC, and t / DC = (t * DM) >> 16 is exact for
+                // t < 65536 / (DM * DC - 65536) (>= 1170 for DC <= 56)
                 const int ntask = nflip * DV * DC;
+                constexpr uint32_t DM = ((1u << 16) + DC - 1) / DC;
+                static_assert(DC <= 56 && 64 * DV * DC < 65536 / (DM * DC - 65536), "task index range");
                 for (int base = 0; base < ntask; base += 64) {
                     const int t = base + (int)lane;
                     if (t < ntask) {
-                        const int u = t / DC, q = t - (t / DC) * DC;
+                        const uint32_t u = __umul24((uint32_t)t, DM) >> 16;
+                        const uint32_t q = (uint32_t)t - __umul24(u, (uint32_t)DC);
                         const uint32_t e = list[u];
                         const uint32_t r = e & 0xFFFFu, i = (e >> 16) & 0x7FFFu;
-                        const uint32_t m = i * Z + r;
-                        const uint32_t nq = q * Z + addmod(r, sh[i * a.nb + q], Z);
+                        const uint32_t m = __umul24(i, Z) + r;
+                        const uint32_t nq = __umul24(q, Z) + addmod(r, sh[__umul24(i, (uint32_t)a.nb) + q], Z);
                         uint32_t w;
                         if constexpr (DT == FWBF_I8) {
                             const uint32_t cw = chk[m];
-                            w = (a.imwbf && ((cw >> 16) & 0xFF) == (uint32_t)q) ? ((cw >> 8) & 0xFF) : (cw & 0xFF);
+                            w = (a.imwbf && ((cw >> 16) & 0xFF) == q) ? ((cw >> 8) & 0xFF) : (cw & 0xFF);
                         } else {
                             const uint32_t cw = chk[m];
-                            w = (a.imwbf && chkp[m] == (uint32_t)q) ? (cw >> 16) : (cw & 0xFFFF);
+                            w = (a.imwbf && chkp[m] == q) ? (cw >> 16) : (cw & 0xFFFF);
                         }
-                        const int d = (e >> 31) ? 2 * a.aden * (int)w : -2 * a.aden * (int)w;
-                        atomicAdd(&keys[slotof[nq]], (uint32_t)d << a.idxb);
+                        const uint32_t dm = __umul24(2u * (uint32_t)a.aden, w) << a.idxb;
+                        atomicAdd(&keys[slotof[nq]], (e >> 31) ? dm : 0u - dm);
                     }
                 }
                 wave_sync();
