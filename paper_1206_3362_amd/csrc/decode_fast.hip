@@ -45,7 +45,8 @@ struct FastArgs {
     const uint8_t *skip;    // optional: frames with skip[f] != 0 are left untouched
     int iters_add;          // add the rounds to iters[f] instead of storing them
     int N, M, Z, nb;
-    uint32_t magZ, maskZ, magP, maskP, magG, maskG;
+    uint32_t magP, maskP, magG, maskG;
+    uint32_t rZ24;  // n / Z = (n * rZ24) >> 20 for every bit n
     int strided;  // block g = {n : n mod G = g}: bit n = pos G + g
     int p, L, logL, Geff, Lc;
     int single, imwbf, max_iter, cycle_exit, vec_ok;
@@ -163,7 +164,7 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
     const uint32_t pos0 = (lane & (a.L - 1)) * C;
     const uint32_t gp = g * a.p;
     // bit at position pos of this lane's block
-    auto bit_at = [&](uint32_t pos) { return a.strided ? pos * (uint32_t)a.Geff + g : gp + pos; };
+    auto bit_at = [&](uint32_t pos) { return a.strided ? __umul24(pos, (uint32_t)a.Geff) + g : gp + pos; };
     const int NW = (N + 31) >> 5;
 
     const FrameRange fr = xcd_frames_waves(a.F, FAST_WAVES, (int)wv);
@@ -272,8 +273,9 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                     }
                     // push this check's term of eq. (1) to its members: the
                     // two signed values (a_den w << idxb) are formed once
-                    const uint32_t e1 = __umul24((uint32_t)a.aden, m1) << a.idxb;
-                    const uint32_t e2 = __umul24((uint32_t)a.aden, a.imwbf ? m2 : m1) << a.idxb;
+                    // (minima are at most 32768: 16 bits)
+                    const uint32_t e1 = __umul24((uint32_t)a.aden, m1 & 0xFFFFu) << a.idxb;
+                    const uint32_t e2 = a.imwbf ? __umul24((uint32_t)a.aden, m2 & 0xFFFFu) << a.idxb : e1;
                     const uint32_t d1 = par ? e1 : 0u - e1, d2 = par ? e2 : 0u - e2;
 #pragma unroll
                     for (int q = 0; q < DC; q++) {
@@ -329,8 +331,8 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                 uint32_t onesm = 0;
                 if (flip) {
                     atomicXor(&zw[n >> 5], 1u << (n & 31));
-                    const uint32_t j = fdiv(n, a.magZ, a.maskZ);
-                    const uint32_t c = n - j * Z;
+                    const uint32_t j = __umul24(n, a.rZ24) >> 20;  // block column: n / Z
+                    const uint32_t c = n - __umul24(j, Z);
                     uint32_t rr[DV], old[DV];
 #pragma unroll
                     for (int t = 0; t < DV; t++) rr[t] = submod(c, sh[t * a.nb + j], Z);
@@ -486,7 +488,11 @@ int try_fast_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int
     a.logL = ilog2c(L);
     a.Lc = L * C;
     a.N = c->N; a.M = c->M; a.Z = c->Z; a.nb = c->nb;
-    magic_c(c->Z, &a.magZ, &a.maskZ);
+    // a 24-bit reciprocal of Z that divides every bit index exactly (always
+    // so for the codes taken here: Z <= 341); otherwise the general kernel
+    a.rZ24 = (uint32_t)(((1u << 20) + c->Z - 1) / c->Z);
+    for (int n = 0; n < c->N; n++)
+        if (((uint64_t)n * a.rZ24) >> 20 != (uint64_t)(n / c->Z) || (uint64_t)n * a.rZ24 >= (1ull << 32)) return 0;
     magic_c(a.p, &a.magP, &a.maskP);
     magic_c(a.Geff, &a.magG, &a.maskG);
     a.single = p->select == FWBF_SINGLE;
