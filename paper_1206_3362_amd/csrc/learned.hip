@@ -196,7 +196,7 @@ struct LearnArgs {
     const float *params;
     const uint32_t *shift;
     int N, M, Z, nb;
-    uint32_t magZ, maskZ, magP, maskP;
+    uint32_t rZ24, magP, maskP;  // n / Z = (n * rZ24) >> 22 for every bit n
     int p, L, logL, Geff, k, T;
     int vec_ok;  // y and its row stride allow 16-byte loads
     float A, dv;
@@ -371,13 +371,20 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
                 if (valid) {
                     // the two smallest keys |y| << 3 | q (q < 8): min1, min2 (with
                     // multiplicity) and the lowest position holding min1
+                    // (every LDS read of the check is issued before its pushes)
+                    uint32_t sl[DC];
+                    int yq[DC];
+#pragma unroll
+                    for (int q = 0; q < DC; q++) nn[q] = q * Z + addmod(r, js[q], Z);
+#pragma unroll
+                    for (int q = 0; q < DC; q++) yq[q] = (int)yv[nn[q]];
+#pragma unroll
+                    for (int q = 0; q < DC; q++) sl[q] = slotof[nn[q]];
                     uint32_t k1 = 0xFFFFFFFFu, k2 = 0xFFFFFFFFu, sx = 0;
 #pragma unroll
                     for (int q = 0; q < DC; q++) {
-                        const uint32_t n = q * Z + addmod(r, js[q], Z);
-                        const int v = (int)yv[n];
+                        const int v = yq[q];
                         const uint32_t av = (uint32_t)(v < 0 ? -v : v);
-                        nn[q] = n;
                         sx ^= (uint32_t)v;  // bit 31: parity of the negative members
                         const uint32_t key = (av << 3) | (uint32_t)q;
                         k2 = min(k2, max(k1, key));
@@ -390,7 +397,7 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
                     const uint32_t d1 = ((uint32_t)(par ? (int)m1 : -(int)m1) << 16) + par;
                     const uint32_t d2 = ((uint32_t)(par ? (int)m2 : -(int)m2) << 16) + par;
 #pragma unroll
-                    for (int q = 0; q < DC; q++) atomicAdd(&slots[slotof[nn[q]]], pos == (uint32_t)q ? d2 : d1);
+                    for (int q = 0; q < DC; q++) atomicAdd(&slots[sl[q]], pos == (uint32_t)q ? d2 : d1);
                 }
                 const unsigned long long b = __ballot(valid && par);
                 weight += __popcll(b);
@@ -488,8 +495,8 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
             if (flip) {
                 const uint32_t n = nsel;
                 atomicXor(&zw[n >> 5], 1u << (n & 31));
-                const uint32_t jb = fdiv(n, a.magZ, a.maskZ);
-                const uint32_t c = n - jb * Z;
+                const uint32_t jb = __umul24(n, a.rZ24) >> 22;  // block column: n / Z
+                const uint32_t c = n - __umul24(jb, Z);
                 uint32_t rr[DV], old[DV];
 #pragma unroll
                 for (int tt = 0; tt < DV; tt++) rr[tt] = submod(c, sh[tt * a.nb + jb], Z);
@@ -513,17 +520,22 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
             weight += 2 * sum_ones - DV * nflip;
             t += 1;
             lwave_sync();
+            // (check, member) tasks, 64 per pass: ntask <= 32 blocks * DV * DC,
+            // and t / DC = (t * DM) >> 16 is exact for t < 65536 / (DM * DC - 65536)
             const int ntask = nflip * DV * DC;
+            constexpr uint32_t DM = ((1u << 16) + DC - 1) / DC;
+            static_assert(32 * DV * DC < 65536 / (DM * DC - 65536), "task index range");
             for (int base = 0; base < ntask; base += 64) {
                 const int tk = base + (int)lane;
                 if (tk < ntask) {
-                    const int u = tk / DC, q = tk - (tk / DC) * DC;
+                    const uint32_t u = __umul24((uint32_t)tk, DM) >> 16;
+                    const uint32_t q = (uint32_t)tk - __umul24(u, (uint32_t)DC);
                     const uint32_t e = list[u];
                     const uint32_t r = e & 0xFFFFu, i = (e >> 16) & 0x7FFFu;
-                    const uint32_t m = i * Z + r;
-                    const uint32_t nq = q * Z + addmod(r, sh[i * a.nb + q], Z);
+                    const uint32_t m = __umul24(i, Z) + r;
+                    const uint32_t nq = __umul24(q, Z) + addmod(r, sh[__umul24(i, (uint32_t)a.nb) + q], Z);
                     const uint32_t cwd = chk[m];
-                    const uint32_t w = (((cwd >> 16) & 0xFF) == (uint32_t)q) ? ((cwd >> 8) & 0xFF) : (cwd & 0xFF);
+                    const uint32_t w = (((cwd >> 16) & 0xFF) == q) ? ((cwd >> 8) & 0xFF) : (cwd & 0xFF);
                     const uint32_t d = (e >> 31) ? ((2u * w) << 16) + 1u : 0u - (((2u * w) << 16) + 1u);
                     atomicAdd(&slots[slotof[nq]], (uint32_t)d);
                 }
@@ -813,7 +825,12 @@ extern "C" int fwbf_decode_learned(const fwbf_code *code, const fwbf_params *pla
     if (!C) return fail(FWBF_E_UNSUPPORTED, "block too long for one wave");
     a.L = L; a.logL = ilog2l(L);
     a.N = code->N; a.M = code->M; a.Z = code->Z; a.nb = code->nb;
-    magic_l(code->Z, &a.magZ, &a.maskZ);
+    // a 24-bit reciprocal of Z that divides every bit index exactly (so for
+    // Z <= 835, every code this kernel takes: N = 6Z <= 4096)
+    a.rZ24 = (uint32_t)(((1u << 22) + code->Z - 1) / code->Z);
+    for (int n = 0; n < code->N; n++)
+        if (((uint64_t)n * a.rZ24) >> 22 != (uint64_t)(n / code->Z) || (uint64_t)n * a.rZ24 >= (1ull << 32))
+            return fail(FWBF_E_UNSUPPORTED, "block size too large for the learned kernel");
     magic_l(a.p, &a.magP, &a.maskP);
     a.T = lp->rounds;
     a.A = lp->scale;
