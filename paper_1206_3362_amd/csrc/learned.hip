@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 
 #include "frames.h"
@@ -200,6 +201,7 @@ struct LearnArgs {
     int p, L, logL, Geff, k, T;
     int vec_ok;  // y and its row stride allow 16-byte loads
     float A, dv;
+    float invA;   // 1/A when A is a power of two (then x * invA == x / A), else 0
     // LDS: tables shared by the workgroup (o_sh, o_slot, o_net, o_netw), then one
     // region of wave_bytes per wavefront (offsets relative to it; slots at 0)
     int o_chk, o_y, o_z, o_syn, o_list, o_sh, o_cand, o_slot, o_net, o_netw, o_wave0, wave_bytes, lds_bytes;
@@ -256,6 +258,8 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
         nbias[32 + t] = a.params[O_B2 + t];
         nbias[64 + t] = a.params[O_W3 + t];
     }
+    // the round feature t / T for every round (divided once here)
+    for (int t = threadIdx.x; t < a.T; t += 64 * LEARN_WAVES) nbias[96 + t] = (float)t / (float)a.T;
     if (threadIdx.x < 64) {
         // MFMA operands of lane l: W1[l%32][4(l/32) + 0..3] (zero for the
         // upper half: only 4 inputs), W2[l%32][8c + 4(l/32) + 0..3]
@@ -279,6 +283,7 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
         net.b3 = p[O_B3];
     }
 
+    const float qu1 = 1.0f / a.dv, qu2 = 2.0f / a.dv, qu3 = 3.0f / a.dv;  // u / dv feature values
     const uint32_t g = lane >> a.logL;
     const bool lead = ((lane & (a.L - 1)) == 0) && (int)g < a.Geff;
     const uint32_t pos0 = (lane & (a.L - 1)) * C;
@@ -459,7 +464,13 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
             bf16x4 x = pack4(0.f, 0.f, 0.f, 0.f);
             if (lane < 32 && realc) {
                 const float E = __builtin_fmaf(-al, (float)ca, be * (float)cS);
-                x = pack4((float)ca / a.A, E / a.A, (float)cu / a.dv, (float)t / (float)a.T);
+                // the same quotients as dividing: a power-of-two scale is a
+                // multiply by its reciprocal, u / dv takes one of dv + 1 values
+                float fa, fe;
+                if (a.invA != 0.0f) { fa = (float)ca * a.invA; fe = E * a.invA; }
+                else { fa = (float)ca / a.A; fe = E / a.A; }
+                const float fu = cu == 0 ? 0.0f : cu == 1 ? qu1 : cu == 2 ? qu2 : cu == 3 ? qu3 : (float)cu / a.dv;
+                x = pack4(fa, fe, fu, nbias[96 + t]);
             }
             const float score = net_score(net, x);
             if (a.rec && lane < 32 && j < (uint32_t)NC) {
@@ -834,10 +845,15 @@ extern "C" int fwbf_decode_learned(const fwbf_code *code, const fwbf_params *pla
     magic_l(a.p, &a.magP, &a.maskP);
     a.T = lp->rounds;
     a.A = lp->scale;
+    {
+        int ex = 0;
+        const float mant = std::frexp(lp->scale, &ex);
+        a.invA = (mant == 0.5f && ex > -120 && ex < 120) ? std::ldexp(1.0f, 1 - ex) : 0.0f;
+    }
     a.dv = 3.0f;
     int off = 0;
     auto take = [&](int bytes, int align) { off = (off + align - 1) / align * align; int o = off; off += bytes; return o; };
-    a.o_net = take(4 * 96, 16);
+    a.o_net = take(4 * (96 + 64), 16);  // b1, b2, W3, then t / T for t < 64 rounds
     a.o_netw = take(64 * 5 * 8, 16);
     a.o_sh = take(4 * 3 * code->nb, 4);
     a.o_slot = take(2 * code->N, 4);
