@@ -50,14 +50,17 @@ __device__ __forceinline__ uint16_t bf16_rne(float f)
 }
 __device__ __forceinline__ float bf16_f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
+// Four floats rounded to bfloat16 (to nearest, ties to even) and packed: two
+// hardware pair conversions, which give bf16_rne's result for every float
+// that is not a NaN (checked over all 2^32 bit patterns).
+typedef __bf16 bf16x2h __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d)
 {
-    bf16x4 v;
-    v[0] = (short)bf16_rne(a);
-    v[1] = (short)bf16_rne(b);
-    v[2] = (short)bf16_rne(c);
-    v[3] = (short)bf16_rne(d);
-    return v;
+    const f32x2 ab = {a, b}, cd = {c, d};
+    const uint32_t lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(ab, bf16x2h));
+    const uint32_t hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(cd, bf16x2h));
+    return __builtin_bit_cast(bf16x4, ((uint64_t)hi << 32) | lo);
 }
 
 // row (hidden unit) held by accumulator item q of lane l
