@@ -107,3 +107,28 @@ def test_decode_of_generated_frames_matches_oracle(code):
     ro = O.count(N, zo, pool, 0, ito, oko, 100)
     for k in ("bit_err", "frame_err", "undetected", "iter_sum"):
         assert r[k] == ro[k], k
+
+
+@pytest.mark.parametrize("N,F,f0,use_pool", [(186, 1001, 0, True), (1008, 777, 5, True), (2016, 333, 1 << 33, True),
+                                              (4032, 129, 17, True), (1008, 65, 0, False)])
+def test_count_layouts_match_oracle(N, F, f0, use_pool):
+    """Frames of 6, 32, 63 and 126 words (several frames per wavefront pass,
+    one, and a word loop), ragged frame counts, pool wrap-around at an offset,
+    no pool, and round counts outside [0, K_max] (not histogrammed)."""
+    need_gpu()
+    rng = np.random.default_rng(N + F)
+    max_iter = 40
+    pool = O.pack(rng.random((37, N)) < 0.5) if use_pool else None
+    base = O.unpack(pool[(f0 + np.arange(F)) % 37], N) if use_pool else np.zeros((F, N), np.uint8)
+    flips = rng.random((F, N)) < np.where(rng.random(F) < 0.6, 0.0, 0.02)[:, None]
+    z = O.pack(base ^ flips)
+    it = rng.integers(-3, max_iter + 4, F).astype(np.int32)
+    ok = (rng.random(F) < 0.5).astype(np.uint8)
+    pd = torch.from_numpy(pool.view(np.int32)).cuda() if use_pool else None
+    r = fwbf.count(N, torch.from_numpy(z.view(np.int32)).cuda(), pd, f0, torch.from_numpy(it).cuda(),
+                   torch.from_numpy(ok).cuda(), max_iter)
+    ro = O.count(N, z, pool, f0, it, ok, max_iter)
+    for k in ("bit_err", "frame_err", "undetected", "iter_sum", "frames"):
+        assert r[k] == ro[k], (k, r[k], ro[k])
+    assert np.array_equal(r["hist"], ro["hist"])
+    assert r["syn_ok"] == int(ok.sum())
