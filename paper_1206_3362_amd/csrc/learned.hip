@@ -37,6 +37,7 @@ constexpr uint32_t NONE = 0xFFFFFFFFu;
 // adds to S and u never carry or borrow across the fields
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8h __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // parameter vector offsets (float32): W1[32][4] b1 W2[32][32] b2 W3 b3 alpha[T] beta[T]
@@ -112,8 +113,15 @@ __device__ __forceinline__ float net_score(const NetL &n, bf16x4 x)
         for (int u = 0; u < 4; u++) h[u] = fmaxf(acc[4 * c + u] + n.b1[row_of(4 * c + u, l)], 0.0f);
         h1[c] = pack4(h[0], h[1], h[2], h[3]);
     }
+    // layer 2 as two 16-deep products: the A and B operands of chunks 2c and
+    // 2c + 1 side by side hold the same hidden units at the same (lane half,
+    // element) positions, so each product sums over 16 of the 32 units
     f32x16 acc2 = {};
-    for (int c = 0; c < 4; c++) acc2 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(wl[1 + c], h1[c], acc2, 0, 0, 0);
+    for (int c = 0; c < 2; c++) {
+        const bf16x8h a8 = __builtin_bit_cast(bf16x8h, __builtin_shufflevector(wl[1 + 2 * c], wl[2 + 2 * c], 0, 1, 2, 3, 4, 5, 6, 7));
+        const bf16x8h b8 = __builtin_bit_cast(bf16x8h, __builtin_shufflevector(h1[2 * c], h1[2 * c + 1], 0, 1, 2, 3, 4, 5, 6, 7));
+        acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a8, b8, acc2, 0, 0, 0);
+    }
     float part = 0.0f;
     for (int q = 0; q < 16; q++) {
         const int row = row_of(q, l);
