@@ -164,7 +164,7 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
     const uint32_t pos0 = (lane & (a.L - 1)) * C;
     const uint32_t gp = g * a.p;
     // bit at position pos of this lane's block
-    auto bit_at = [&](uint32_t pos) { return a.strided ? __umul24(pos, (uint32_t)a.Geff) + g : gp + pos; };
+    auto bit_at = [&](uint32_t pos) { return a.strided ? mul24(pos, (uint32_t)a.Geff) + g : gp + pos; };
     const int NW = (N + 31) >> 5;
 
     const FrameRange fr = xcd_frames_waves(a.F, FAST_WAVES, (int)wv);
@@ -274,13 +274,13 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                     // push this check's term of eq. (1) to its members: the
                     // two signed values (a_den w << idxb) are formed once
                     // (minima are at most 32768: 16 bits)
-                    const uint32_t e1 = __umul24((uint32_t)a.aden, m1 & 0xFFFFu) << a.idxb;
-                    const uint32_t e2 = a.imwbf ? __umul24((uint32_t)a.aden, m2 & 0xFFFFu) << a.idxb : e1;
+                    const uint32_t e1 = mul24((uint32_t)a.aden, m1 & 0xFFFFu) << a.idxb;
+                    const uint32_t e2 = a.imwbf ? mul24((uint32_t)a.aden, m2 & 0xFFFFu) << a.idxb : e1;
                     const uint32_t d1 = par ? e1 : 0u - e1, d2 = par ? e2 : 0u - e2;
 #pragma unroll
                     for (int q = 0; q < DC; q++) {
                         uint32_t d = pos == (uint32_t)q ? d2 : d1;
-                        if (i == 0) d -= __umul24((uint32_t)a.anum, av[q]) << a.idxb;
+                        if (i == 0) d -= mul24((uint32_t)a.anum, av[q]) << a.idxb;
                         atomicAdd(&keys[sl[q]], d);
                     }
                 }
@@ -331,8 +331,8 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                 uint32_t onesm = 0;
                 if (flip) {
                     atomicXor(&zw[n >> 5], 1u << (n & 31));
-                    const uint32_t j = __umul24(n, a.rZ24) >> 20;  // block column: n / Z
-                    const uint32_t c = n - __umul24(j, Z);
+                    const uint32_t j = mul24(n, a.rZ24) >> 20;  // block column: n / Z
+                    const uint32_t c = n - mul24(j, Z);
                     uint32_t rr[DV], old[DV];
 #pragma unroll
                     for (int t = 0; t < DV; t++) rr[t] = submod(c, sh[t * a.nb + j], Z);
@@ -369,12 +369,12 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                 for (int base = 0; base < ntask; base += 64) {
                     const int t = base + (int)lane;
                     if (t < ntask) {
-                        const uint32_t u = __umul24((uint32_t)t, DM) >> 16;
-                        const uint32_t q = (uint32_t)t - __umul24(u, (uint32_t)DC);
+                        const uint32_t u = mul24((uint32_t)t, DM) >> 16;
+                        const uint32_t q = (uint32_t)t - mul24(u, (uint32_t)DC);
                         const uint32_t e = list[u];
                         const uint32_t r = e & 0xFFFFu, i = (e >> 16) & 0x7FFFu;
-                        const uint32_t m = __umul24(i, Z) + r;
-                        const uint32_t nq = __umul24(q, Z) + addmod(r, sh[__umul24(i, (uint32_t)a.nb) + q], Z);
+                        const uint32_t m = mul24(i, Z) + r;
+                        const uint32_t nq = mul24(q, Z) + addmod(r, sh[mul24(i, (uint32_t)a.nb) + q], Z);
                         uint32_t w;
                         if constexpr (DT == FWBF_I8) {
                             const uint32_t cw = chk[m];
@@ -383,7 +383,7 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                             const uint32_t cw = chk[m];
                             w = (a.imwbf && chkp[m] == q) ? (cw >> 16) : (cw & 0xFFFF);
                         }
-                        const uint32_t dm = __umul24(2u * (uint32_t)a.aden, w) << a.idxb;
+                        const uint32_t dm = mul24(2u * (uint32_t)a.aden, w) << a.idxb;
                         atomicAdd(&keys[slotof[nq]], (e >> 31) ? dm : 0u - dm);
                     }
                 }

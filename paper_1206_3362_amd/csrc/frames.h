@@ -47,3 +47,12 @@ __device__ __forceinline__ FrameRange xcd_frames_waves(int64_t F, int W, int w)
 }
 
 }  // namespace fwbf
+
+namespace fwbf {
+
+// Product of the low 24 bits of a and b (v_mul_u32_u24, full rate), as an
+// unsigned 32-bit value: HIP's __umul24 returns int, which would turn a
+// product at or above 2^31 negative under shifts and comparisons.
+__device__ __forceinline__ uint32_t mul24(uint32_t a, uint32_t b) { return (uint32_t)__umul24(a, b); }
+
+}  // namespace fwbf

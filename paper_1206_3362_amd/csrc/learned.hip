@@ -517,8 +517,8 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
             if (flip) {
                 const uint32_t n = nsel;
                 atomicXor(&zw[n >> 5], 1u << (n & 31));
-                const uint32_t jb = __umul24(n, a.rZ24) >> 22;  // block column: n / Z
-                const uint32_t c = n - __umul24(jb, Z);
+                const uint32_t jb = mul24(n, a.rZ24) >> 22;  // block column: n / Z
+                const uint32_t c = n - mul24(jb, Z);
                 uint32_t rr[DV], old[DV];
 #pragma unroll
                 for (int tt = 0; tt < DV; tt++) rr[tt] = submod(c, sh[tt * a.nb + jb], Z);
@@ -550,12 +550,12 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
             for (int base = 0; base < ntask; base += 64) {
                 const int tk = base + (int)lane;
                 if (tk < ntask) {
-                    const uint32_t u = __umul24((uint32_t)tk, DM) >> 16;
-                    const uint32_t q = (uint32_t)tk - __umul24(u, (uint32_t)DC);
+                    const uint32_t u = mul24((uint32_t)tk, DM) >> 16;
+                    const uint32_t q = (uint32_t)tk - mul24(u, (uint32_t)DC);
                     const uint32_t e = list[u];
                     const uint32_t r = e & 0xFFFFu, i = (e >> 16) & 0x7FFFu;
-                    const uint32_t m = __umul24(i, Z) + r;
-                    const uint32_t nq = __umul24(q, Z) + addmod(r, sh[__umul24(i, (uint32_t)a.nb) + q], Z);
+                    const uint32_t m = mul24(i, Z) + r;
+                    const uint32_t nq = mul24(q, Z) + addmod(r, sh[mul24(i, (uint32_t)a.nb) + q], Z);
                     const uint32_t cwd = chk[m];
                     const uint32_t w = (((cwd >> 16) & 0xFF) == q) ? ((cwd >> 8) & 0xFF) : (cwd & 0xFF);
                     const uint32_t d = (e >> 31) ? ((2u * w) << 16) + 1u : 0u - (((2u * w) << 16) + 1u);
