@@ -490,9 +490,12 @@ int try_fast_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int
     a.N = c->N; a.M = c->M; a.Z = c->Z; a.nb = c->nb;
     // a 24-bit reciprocal of Z that divides every bit index exactly (always
     // so for the codes taken here: Z <= 341); otherwise the general kernel
+    // (exact for every n < N when (N - 1) (rZ24 Z - 2^20) < 2^20: the error
+    // n (rZ24 Z - 2^20) / (Z 2^20) then stays below 1 / Z)
     a.rZ24 = (uint32_t)(((1u << 20) + c->Z - 1) / c->Z);
-    for (int n = 0; n < c->N; n++)
-        if (((uint64_t)n * a.rZ24) >> 20 != (uint64_t)(n / c->Z) || (uint64_t)n * a.rZ24 >= (1ull << 32)) return 0;
+    if ((uint64_t)(c->N - 1) * ((uint64_t)a.rZ24 * c->Z - (1u << 20)) >= (1u << 20) ||
+        (uint64_t)c->N * a.rZ24 >= (1ull << 32))
+        return 0;
     magic_c(a.p, &a.magP, &a.maskP);
     magic_c(a.Geff, &a.magG, &a.maskG);
     a.single = p->select == FWBF_SINGLE;

@@ -849,10 +849,11 @@ extern "C" int fwbf_decode_learned(const fwbf_code *code, const fwbf_params *pla
     a.N = code->N; a.M = code->M; a.Z = code->Z; a.nb = code->nb;
     // a 24-bit reciprocal of Z that divides every bit index exactly (so for
     // Z <= 835, every code this kernel takes: N = 6Z <= 4096)
+    // (exact for every n < N when (N - 1) (rZ24 Z - 2^22) < 2^22)
     a.rZ24 = (uint32_t)(((1u << 22) + code->Z - 1) / code->Z);
-    for (int n = 0; n < code->N; n++)
-        if (((uint64_t)n * a.rZ24) >> 22 != (uint64_t)(n / code->Z) || (uint64_t)n * a.rZ24 >= (1ull << 32))
-            return fail(FWBF_E_UNSUPPORTED, "block size too large for the learned kernel");
+    if ((uint64_t)(code->N - 1) * ((uint64_t)a.rZ24 * code->Z - (1u << 22)) >= (1u << 22) ||
+        (uint64_t)code->N * a.rZ24 >= (1ull << 32))
+        return fail(FWBF_E_UNSUPPORTED, "block size too large for the learned kernel");
     magic_l(a.p, &a.magP, &a.maskP);
     a.T = lp->rounds;
     a.A = lp->scale;
