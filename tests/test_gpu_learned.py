@@ -96,11 +96,11 @@ def _plain_oracle(ocode, y, G, alpha_den=5, max_iter=100):
     return O.decode(ocode, y, G=G, max_iter=max_iter, alpha_num=1, alpha_den=alpha_den)
 
 
-def _learned_reference(ocode, y, p, T, G, k, plain_G, alpha_den=5):
+def _learned_reference(ocode, y, p, T, G, k, plain_G, alpha_den=5, A=16.0):
     adj = R._adjacency(ocode)
     zs, its, oks, recs = [], [], [], []
     for f in range(y.shape[0]):
-        z, rounds, ok, rc = R.learned_decode_frame(ocode, y[f], p.astype(np.float64), T, G, k, 16.0, 3, adj)
+        z, rounds, ok, rc = R.learned_decode_frame(ocode, y[f], p.astype(np.float64), T, G, k, A, 3, adj)
         if not ok:
             zp, itp, okp = _plain_oracle(ocode, y[f:f + 1], plain_G, alpha_den)
             z, rounds, ok = O.unpack(zp, ocode.N)[0], rounds + int(itp[0]), bool(okp[0])
@@ -108,10 +108,14 @@ def _learned_reference(ocode, y, p, T, G, k, plain_G, alpha_den=5):
     return np.array(zs), np.array(its), np.array(oks), recs
 
 
-@pytest.mark.parametrize("name,mbnbZ,G,k,T", [("n186", (3, 6, 31, 1), 6, 4, 8),
-                                              ("n1008", (3, 6, 168, 2), 32, 1, 8),
-                                              ("n1008", (3, 6, 168, 2), 8, 4, 6)])
-def test_learned_pass_matches_reference(name, mbnbZ, G, k, T):
+@pytest.mark.parametrize("name,mbnbZ,G,k,T,A", [("n186", (3, 6, 31, 1), 6, 4, 8, 16.0),
+                                                ("n1008", (3, 6, 168, 2), 32, 1, 8, 16.0),
+                                                ("n1008", (3, 6, 168, 2), 8, 4, 6, 16.0),
+                                                ("n1008", (3, 6, 168, 2), 32, 1, 6, 12.0)])
+def test_learned_pass_matches_reference(name, mbnbZ, G, k, T, A):
+    """The learned pass plus fallback against the float64 reference; a scale
+    A that is not a power of two takes the divided feature path, T = 6 the
+    non-power-of-two round feature t / T."""
     g = fwbf.Code.from_seed(*mbnbZ)
     o = O.Code.from_seed(*mbnbZ)
     Fn = 96
@@ -119,7 +123,7 @@ def test_learned_pass_matches_reference(name, mbnbZ, G, k, T):
     p[-2 * T:-T] = 0.2
     p[-T:] = 1.0
     y = synth.awgn_frames(g.N, Fn, synth.sigma_for(4.5, g.rate), 9, None, np.int8)
-    lp = fwbf.LearnedParams(T, G, k, 16.0)
+    lp = fwbf.LearnedParams(T, G, k, A)
     plain = fwbf.DecodeParams(dtype=fwbf.I8, groups=8, max_iter=100)
     rec = fwbf.record_buffer(Fn, T)
     z, it, ok, lok = fwbf.decode_learned(g, torch.from_numpy(y).cuda(), plain, lp,
@@ -127,9 +131,9 @@ def test_learned_pass_matches_reference(name, mbnbZ, G, k, T):
     torch.cuda.synchronize()
     zg = O.unpack(z.cpu().numpy().view(np.uint32), g.N)
     itg, okg = it.cpu().numpy(), ok.cpu().numpy().astype(bool)
-    zr, itr, okr, recs = _learned_reference(o, y, p, T, G, k, 8)
+    zr, itr, okr, recs = _learned_reference(o, y, p, T, G, k, 8, A=A)
     same = (zg == zr).all(1) & (itg == itr) & (okg == okr)
-    print(f"{name} G={G} k={k}: {same.sum()}/{Fn} frames identical, "
+    print(f"{name} G={G} k={k} A={A}: {same.sum()}/{Fn} frames identical, "
           f"learned-pass successes {int(lok.sum())}", flush=True)
     assert same.mean() >= 0.95
     # round-0 proposals depend only on exact single-precision metrics
