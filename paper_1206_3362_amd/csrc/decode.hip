@@ -11,7 +11,9 @@
 //         the second minimum when n holds the minimum, else the minimum);
 //   syn   syndrome bits, tog per-round toggle parities, zw hard decisions.
 // Slots: block g (p = ceil(N/G) bits) is padded to Lc = L*C slots held by L
-// consecutive threads with C slots each (L a power of two); padding slots
+// consecutive threads with C slots each (L a power of two; lane l of the
+// block holds positions l, l + L, ..., so a wavefront's slot accesses fall
+// on consecutive words); padding slots
 // hold key 0 and never win (the "null" metric padding of the paper's
 // footnote to Section V).
 //
@@ -237,25 +239,28 @@ __device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v,
     return ((unsigned long long)hi << 32) | lo;
 }
 
-// maximum over the slots [s0, s0 + C) of one thread, as a 64-bit key
-// (value << 32 | ~position) where position is the slot offset in the block
+// maximum over the C slots of one thread, as a 64-bit key
+// (value << 32 | ~position) where position is the slot offset in the block.
+// Lane l of a block owns positions l, l + L, l + 2L, ...: at every step the
+// lanes of a wavefront touch consecutive words (no LDS bank conflicts), and
+// the first strict maximum along k is the lowest position.
 template <bool KEY32>
-__device__ __forceinline__ unsigned long long thread_best(const DecodeArgs &a, const uint32_t *keys, int s0, uint32_t pos0)
+__device__ __forceinline__ unsigned long long thread_best(const DecodeArgs &a, const uint32_t *keys, int s0, uint32_t l)
 {
     if constexpr (KEY32) {
         uint32_t best = 0;
-        for (int k = 0; k < a.C; k++) best = max(best, keys[s0 + k]);
+        for (int k = 0; k < a.C; k++) best = max(best, keys[s0 + k * a.L]);
         // unpack into the common 64-bit form
         return ((unsigned long long)(best >> a.idxb) << 32) | (0xFFFFFFFFu - (a.idxmask - (best & a.idxmask)));
     } else {
         uint32_t best = 0, bk = 0;
         for (int k = 0; k < a.C; k++) {
-            const uint32_t v = keys[s0 + k];
+            const uint32_t v = keys[s0 + k * a.L];
             const bool gt = v > best;
             best = gt ? v : best;
             bk = gt ? (uint32_t)k : bk;
         }
-        return ((unsigned long long)best << 32) | (0xFFFFFFFFu - (pos0 + bk));
+        return ((unsigned long long)best << 32) | (0xFFFFFFFFu - (l + bk * (uint32_t)a.L));
     }
 }
 
@@ -381,17 +386,16 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
         // ---- initial metrics (eq. (1)) into the slots ---------------------
         for (int pi = 0; pi < a.P; pi++) {
             const int g = pi * a.GP + (tid >> a.logL);
-            const int pos0 = (tid & (a.L - 1)) * a.C;
-            const int s0 = (pi * T + tid) * a.C;
+            const int l = tid & (a.L - 1);
             for (int kk = 0; kk < a.C; kk++) {
-                const int pos = pos0 + kk;
+                const int pos = l + kk * a.L;
                 const int n = (int)bit_of(a, g, pos);
                 uint32_t key = 0;
                 if (g < a.Geff && pos < a.p && n < N) {
                     const uint32_t v = metric_val<DT>(a, s, n, imwbf);
                     key = KEY32 ? ((v << a.idxb) | (a.idxmask - pos)) : v;
                 }
-                s.keys[s0 + kk] = key;
+                s.keys[g * a.Lc + pos] = key;
             }
         }
         for (int u = tid; u < a.W; u += T) s.prv[u] = NONE;
@@ -404,8 +408,8 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
             if (a.select != FWBF_TOPL) {
                 for (int pi = 0; pi < a.P; pi++) {
                     const int g = pi * a.GP + (tid >> a.logL);
-                    const int pos0 = (tid & (a.L - 1)) * a.C;
-                    unsigned long long best = thread_best<KEY32>(a, s.keys, (pi * T + tid) * a.C, pos0);
+                    const int l = tid & (a.L - 1);
+                    unsigned long long best = thread_best<KEY32>(a, s.keys, g * a.Lc + l, l);
                     const int lw = a.L < 64 ? a.L : 64;
                     for (int d = 1; d < lw; d <<= 1) {
                         const unsigned long long o = shfl_xor_u64(best, d);
@@ -438,7 +442,8 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
                 // (single block layout), each excluded before the next
                 int cnt = 0;
                 for (int t = 0; t < a.lambda; t++) {
-                    unsigned long long best = thread_best<KEY32>(a, s.keys, tid * a.C, (tid & (a.L - 1)) * a.C);
+                    unsigned long long best = thread_best<KEY32>(a, s.keys, (tid >> a.logL) * a.Lc + (tid & (a.L - 1)),
+                                                                  tid & (a.L - 1));
                     for (int d = 1; d < 64; d <<= 1) {
                         const unsigned long long o = shfl_xor_u64(best, d);
                         best = o > best ? o : best;
