@@ -283,7 +283,7 @@ def other_workload(a):
                             "frames": sum(s[1] for s in specs)})
     elif a.workload == "n32400_i16":
         code = fwbf.Code.from_seed(3, 30, 1080, 5)
-        F = 1 << 15
+        F = 1 << 18
         pool = torch.from_numpy(code.encode(5, 0, 64).view(np.int32)).to(dev)
         res = {}
         for eb in (5.0, 6.0, 7.0):
@@ -298,7 +298,7 @@ def other_workload(a):
         line.update(metric="decoded Gb/s, plain FWBF, N=32400 (3,30) QC rate 0.9, int16",
                     value=res[6.0]["gbps"], ms_per_step=res[6.0]["ms"], dtype="int32", points=res,
                     config={"workload": "N=32400 (3,30) QC Z=1080 K=29162, int16 x256, G=64, K_max=100, "
-                                        "2^15 frames per point", "frames": F})
+                                        "2^18 frames per point", "frames": F})
     elif a.workload == "minsum_eg255":
         minsum_eg255(a, line)
     elif a.workload == "strided_n1008":

@@ -85,21 +85,21 @@ def test_mixed_batch_full_size():
 
 
 def test_n32400_int16_full_size():
-    """(3,30) Z=1080 rate-0.9 code, 2^15 int16 frames (scale 256) at 6 dB,
+    """(3,30) Z=1080 rate-0.9 code, 2^18 int16 frames (scale 256) at 6 dB,
     G=64, K_max=100."""
     need_gpu()
     from paper_1206_3362_amd import fwbf
     code = fwbf.Code.from_seed(*CODES["n32400"])
     oc = O.Code.from_seed(*CODES["n32400"])
-    N, F = code.N, 1 << 15
+    N, F = code.N, 1 << 18
     pool = torch.from_numpy(code.encode(5, 0, 64).view(np.int32)).cuda()
     y = fwbf.channel(N, F, 0, pool, 900, 6, float(synth.sigma_for(6.0, code.rate)), dtype=torch.int16,
                      scale=256.0)
     p = fwbf.DecodeParams(dtype=fwbf.I16, groups=64, max_iter=100)
     z, it, ok = fwbf.decode(code, y, p)
     torch.cuda.synchronize()
-    check_sampled(oc, y, z, it, ok, sample_rows(F, 64, 3), "n32400 i16 2^15", groups=64, max_iter=100)
-    check_properties(oc, z, it, ok, 100, "n32400 i16 2^15")
+    check_sampled(oc, y, z, it, ok, sample_rows(F, 64, 3), "n32400 i16 2^18", groups=64, max_iter=100)
+    check_properties(oc, z, it, ok, 100, "n32400 i16 2^18")
 
 
 @pytest.mark.parametrize("dt", [torch.float32, torch.int8])
