@@ -259,27 +259,45 @@ def other_workload(a):
                     config={"workload": "N=186 (3,6) QC Z=31, all-zero codeword, 3 dB, f32, WBF, "
                                         "alpha 0.2, G=6, K_max=50, 1000 frames", "frames": F})
     elif a.workload == "mixed_f32":
-        specs = [((3, 6, 168, 2), 1 << 18, 8), ((3, 6, 672, 3), 1 << 16, 32), ((4, 20, 400, 4), 1 << 15, 64)]
+        from paper_1206_3362_amd import autotune
+        # reference G per code and the candidates the autotuner may take
+        specs = [((3, 6, 168, 2), 1 << 18, 8, (4, 6, 8, 12, 16)),
+                 ((3, 6, 672, 3), 1 << 16, 32, (8, 12, 16, 24, 32, 48)),
+                 ((4, 20, 400, 4), 1 << 15, 64, (16, 24, 32, 48, 64, 96))]
         jobs, bits = [], 0
-        for i, (spec, F, G) in enumerate(specs):
+        for i, (spec, F, G, _) in enumerate(specs):
             code = fwbf.Code.from_seed(*spec)
             pool = torch.from_numpy(code.encode(31 + i, 0, 256).view(np.int32)).to(dev)
             eb = synth.uniform_frames(code.N, F, 77 + i, 3.0, 6.0)
             sig = torch.from_numpy(synth.sigma_for(eb, code.rate).astype(np.float32)).to(dev)
             y = fwbf.channel(code.N, F, 0, pool, 500 + i, i, 0.0, sigma_per_frame=sig)
-            jobs.append((code, y, fwbf.DecodeParams(dtype=fwbf.F32, groups=G, max_iter=100)))
+            jobs.append((code, y, pool, fwbf.DecodeParams(dtype=fwbf.F32, groups=G, max_iter=100)))
             bits += F * code.N
+        tuned = autotune.tune_batch(jobs, [s[3] for s in specs], tune_frames=1 << 14,
+                                    widths=(0, 128, 256), blocks=(0, 2, 4), repeats=3)
+        batch = [(code, y, p) for (code, y, _, _), p in zip(jobs, tuned["params"])]
+        T, bpc = tuned["threads_per_frame"], tuned["blocks_per_cu"]
         ws = torch.zeros(64, dtype=torch.int32, device=dev)
-        ms = _timed(lambda: fwbf.decode_batched(jobs, workspace=ws), a.steps, a.warmup)
-        ms256 = _timed(lambda: fwbf.decode_batched(jobs, threads_per_frame=256, workspace=ws), a.steps,
-                       a.warmup)
-        sep = _timed(lambda: [fwbf.decode(c, y, p) for c, y, p in jobs], a.steps, a.warmup)
+        ms = _timed(lambda: fwbf.decode_batched(batch, threads_per_frame=T, blocks_per_cu=bpc, workspace=ws),
+                    a.steps, a.warmup)
+        ref = [(code, y, p0) for code, y, _, p0 in jobs]
+        ms_ref = _timed(lambda: fwbf.decode_batched(ref, workspace=ws), a.steps, a.warmup)
+        sep = _timed(lambda: [fwbf.decode(c, y, p) for c, y, p in batch], a.steps, a.warmup)
+        outs = fwbf.decode_batched(batch, threads_per_frame=T, blocks_per_cu=bpc, workspace=ws)
+        fer = [fwbf.count(code.N, z, pool, 0, it, ok, 100)["frame_err"] / y.shape[0]
+               for (code, y, pool, _), (z, it, ok) in zip(jobs, outs)]
         line.update(metric="decoded Gb/s, mixed-code persistent batch (float32)",
                     value=round(bits / (ms * 1e-3) / 1e9, 3), ms_per_step=round(ms, 4), dtype="f32",
                     separate_launches_gbps=round(bits / (sep * 1e-3) / 1e9, 3),
-                    one_width_256_gbps=round(bits / (ms256 * 1e-3) / 1e9, 3),
+                    reference_G_gbps=round(bits / (ms_ref * 1e-3) / 1e9, 3),
+                    tuned={"G": [p.groups for p in tuned["params"]], "threads_per_frame": T,
+                           "blocks_per_cu": bpc, "fer": [round(x, 5) for x in fer],
+                           "g_table": [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items()}
+                                       for r in tuned["g_table"]],
+                           "shape_table": tuned["shape_table"]},
                     config={"workload": "N=1008/4032 (3,6) + N=8000 (4,20) QC, 2^18/2^16/2^15 frames, "
-                                        "Eb/N0 U[3,6] dB per frame, f32, G=8/32/64, one launch",
+                                        "Eb/N0 U[3,6] dB per frame, f32, K_max=100, G and launch shape "
+                                        "autotuned (reference G=8/32/64), one launch",
                             "frames": sum(s[1] for s in specs)})
     elif a.workload == "n32400_i16":
         code = fwbf.Code.from_seed(3, 30, 1080, 5)

@@ -349,7 +349,7 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
                     if (v < m1) { m2 = m1; m1 = v; pos = q; }
                     else if (v < m2) m2 = v;
                 }
-                if (deg < 2) m2 = 0.0f;  // empty minimum over N(m)\n
+                if (deg < 2) m2 = 0.0f;  // empty minimum over N(m) minus the member
                 chk[m] = pack_chk<DT>(__float_as_uint(m1), __float_as_uint(m2), 0);
                 s.chkp[m] = (uint8_t)pos;
             } else {

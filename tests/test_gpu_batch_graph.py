@@ -119,7 +119,7 @@ def test_graph_sweep_replays_equal_eager_launches():
 def test_autotuner_respects_fer_constraint(tmp_path):
     code = fwbf.Code.from_seed(3, 6, 168, 2)
     cache = str(tmp_path / "tune.json")
-    r = autotune.tune(code, 6.0, G_ref=8, Gs=(8, 16, 32), shapes=((0, 0), (128, 0)), frames=8192,
+    r = autotune.tune(code, 6.0, G_ref=8, Gs=(8, 16, 32), widths=(0, 128), frames=8192,
                       cache=cache)
     assert r["admissible"]
     n = 8192
@@ -129,6 +129,39 @@ def test_autotuner_respects_fer_constraint(tmp_path):
         if row["admissible"]:
             assert row["gbps"] <= r["gbps"] + 1e-9
     # cached
-    r2 = autotune.tune(code, 6.0, G_ref=8, Gs=(8, 16, 32), shapes=((0, 0), (128, 0)), frames=8192,
+    r2 = autotune.tune(code, 6.0, G_ref=8, Gs=(8, 16, 32), widths=(0, 128), frames=8192,
                        cache=cache)
     assert r2 == r
+
+
+def test_batch_autotuner_choices():
+    """Each job's chosen G passes the frame-error test against its reference
+    G on the tuning frames, the chosen launch shape is the fastest timed one,
+    and the batch decoded with the chosen settings equals each code decoded
+    alone with the same G."""
+    jobs = []
+    for i, (spec, F, G) in enumerate(CODES):
+        code = fwbf.Code.from_seed(*spec)
+        pool = torch.from_numpy(code.encode(40 + i, 0, 64).view(np.int32)).cuda()
+        eb = synth.uniform_frames(code.N, F, 40 + i, 3.0, 6.0)
+        sig = torch.from_numpy(synth.sigma_for(eb, code.rate).astype(np.float32)).cuda()
+        y = fwbf.channel(code.N, F, 0, pool, 40 + i, 2, 0.0, sigma_per_frame=sig)
+        jobs.append((code, y, pool, fwbf.DecodeParams(dtype=fwbf.F32, groups=G, max_iter=100)))
+    cands = [(8, 16), (32, 64), (64, 128)]
+    r = autotune.tune_batch(jobs, cands, tune_frames=256, widths=(0, 256), blocks=(0, 2), repeats=1)
+    for (code, y, pool, p0), p, cand in zip(jobs, r["params"], cands):
+        assert p.groups in cand or p.groups == p0.groups
+        rows = [row for row in r["g_table"] if row["N"] == code.N]
+        n = min(256, y.shape[0])
+        for row in rows:
+            assert row["admissible"] == autotune.fer_admissible(round(row["fer"] * n), n,
+                                                                round(row["fer_ref"] * n), n)
+        pick = [row for row in rows if row["G"] == p.groups]
+        assert not pick or pick[0]["admissible"]
+    assert r["ms"] == min(row["ms"] for row in r["shape_table"])
+    batch = [(code, y, p) for (code, y, _, _), p in zip(jobs, r["params"])]
+    outs = fwbf.decode_batched(batch, threads_per_frame=r["threads_per_frame"],
+                               blocks_per_cu=r["blocks_per_cu"])
+    for (code, y, p), (z, it, ok) in zip(batch, outs):
+        z1, it1, ok1 = fwbf.decode(code, y, p)
+        assert torch.equal(z, z1) and torch.equal(it, it1) and torch.equal(ok, ok1)
