@@ -24,6 +24,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "decoded Gb/s at fixed FER (N=1008, 4 dB), learned vs plain FWBF; % HBM peak"
 HBM_PEAK_GBS = 8000.0
+# mixed-code batch: (code (mb, nb, Z, seed), frames, reference G, G candidates)
+MIXED_JOBS = [((3, 6, 168, 2), 1 << 18, 8, (4, 6, 8, 12, 16)),
+              ((3, 6, 672, 3), 1 << 16, 32, (8, 12, 16, 24, 32, 48)),
+              ((4, 20, 400, 4), 1 << 15, 64, (16, 24, 32, 48, 64, 96))]
+MIXED_TUNE = dict(tune_frames=1 << 14, widths=(0, 128, 256), blocks=(0, 2, 4), repeats=3)
 
 
 def parse():
@@ -260,10 +265,7 @@ def other_workload(a):
                                         "alpha 0.2, G=6, K_max=50, 1000 frames", "frames": F})
     elif a.workload == "mixed_f32":
         from paper_1206_3362_amd import autotune
-        # reference G per code and the candidates the autotuner may take
-        specs = [((3, 6, 168, 2), 1 << 18, 8, (4, 6, 8, 12, 16)),
-                 ((3, 6, 672, 3), 1 << 16, 32, (8, 12, 16, 24, 32, 48)),
-                 ((4, 20, 400, 4), 1 << 15, 64, (16, 24, 32, 48, 64, 96))]
+        specs = MIXED_JOBS
         jobs, bits = [], 0
         for i, (spec, F, G, _) in enumerate(specs):
             code = fwbf.Code.from_seed(*spec)
@@ -273,8 +275,7 @@ def other_workload(a):
             y = fwbf.channel(code.N, F, 0, pool, 500 + i, i, 0.0, sigma_per_frame=sig)
             jobs.append((code, y, pool, fwbf.DecodeParams(dtype=fwbf.F32, groups=G, max_iter=100)))
             bits += F * code.N
-        tuned = autotune.tune_batch(jobs, [s[3] for s in specs], tune_frames=1 << 14,
-                                    widths=(0, 128, 256), blocks=(0, 2, 4), repeats=3)
+        tuned = autotune.tune_batch(jobs, [s[3] for s in specs], **MIXED_TUNE)
         batch = [(code, y, p) for (code, y, _, _), p in zip(jobs, tuned["params"])]
         T, bpc = tuned["threads_per_frame"], tuned["blocks_per_cu"]
         ws = torch.zeros(64, dtype=torch.int32, device=dev)

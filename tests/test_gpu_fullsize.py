@@ -84,6 +84,34 @@ def test_mixed_batch_full_size():
         check_properties(oc, z, it, ok, 100, f"batch {name} f32")
 
 
+def test_mixed_batch_full_size_autotuned():
+    """The mixed batch as the benchmark times it: the autotuner picks each
+    code's G (under the frame-error constraint) and the launch shape with the
+    benchmark's candidate lists, then the one launch at those settings is
+    checked like the reference-G launch above."""
+    need_gpu()
+    import bench
+    from paper_1206_3362_amd import autotune, fwbf
+    jobs, ocs = [], []
+    for i, (spec, F, G, _) in enumerate(bench.MIXED_JOBS):
+        code = fwbf.Code.from_seed(*spec)
+        pool = torch.from_numpy(code.encode(31 + i, 0, 256).view(np.int32)).cuda()
+        eb = synth.uniform_frames(code.N, F, 77 + i, 3.0, 6.0)
+        sig = torch.from_numpy(synth.sigma_for(eb, code.rate).astype(np.float32)).cuda()
+        y = fwbf.channel(code.N, F, 0, pool, 500 + i, i, 0.0, sigma_per_frame=sig)
+        jobs.append((code, y, pool, fwbf.DecodeParams(dtype=fwbf.F32, groups=G, max_iter=100)))
+        ocs.append(O.Code.from_seed(*spec))
+    tuned = autotune.tune_batch(jobs, [j[3] for j in bench.MIXED_JOBS], **bench.MIXED_TUNE)
+    batch = [(code, y, p) for (code, y, _, _), p in zip(jobs, tuned["params"])]
+    outs = fwbf.decode_batched(batch, threads_per_frame=tuned["threads_per_frame"],
+                               blocks_per_cu=tuned["blocks_per_cu"])
+    torch.cuda.synchronize()
+    for (code, y, p), oc, (z, it, ok) in zip(batch, ocs, outs):
+        what = f"tuned batch N={code.N} G={p.groups} f32"
+        check_sampled(oc, y, z, it, ok, sample_rows(y.shape[0], 96, 3), what, groups=p.groups, max_iter=100)
+        check_properties(oc, z, it, ok, 100, what)
+
+
 def test_n32400_int16_full_size():
     """(3,30) Z=1080 rate-0.9 code, 2^18 int16 frames (scale 256) at 6 dB,
     G=64, K_max=100."""
