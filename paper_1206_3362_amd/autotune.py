@@ -158,6 +158,8 @@ def tune_batch(jobs, Gs, tune_frames=1 << 14, widths=(0, 128, 256), blocks=(0, 2
             shape_table.append(dict(threads_per_frame=T, blocks_per_cu=b, ms=ms))
             if best is None or ms < best["ms"]:
                 best = shape_table[-1]
+    if best is None:
+        raise fwbf.FwbfError(fwbf.E_UNSUPPORTED, "no candidate launch shape could decode this batch")
     return dict(params=chosen, threads_per_frame=best["threads_per_frame"],
                 blocks_per_cu=best["blocks_per_cu"], ms=best["ms"], g_table=g_table,
                 shape_table=shape_table)
