@@ -9,7 +9,8 @@
 //   chk   per check: minimum and second minimum of |y| over N(m) and the
 //         position of the minimum (the IMWBF weight of bit n in check m is
 //         the second minimum when n holds the minimum, else the minimum);
-//   syn   syndrome bits, tog per-round toggle parities, zw hard decisions.
+//   syn   syndrome bits, tog per-round toggle parities (integer inputs),
+//         zw hard decisions.
 // Slots: block g (p = ceil(N/G) bits) is padded to Lc = L*C slots held by L
 // consecutive threads with C slots each (L a power of two; lane l of the
 // block holds positions l, l + L, ..., so a wavefront's slot accesses fall
@@ -20,14 +21,17 @@
 // Round k (Section III, Step 2 then Step 1):
 //   select  each thread takes the max of its C slot keys, an xor-butterfly
 //           over the L threads of the block gives the block maximum;
-//   apply   winners with a positive metric toggle their hard decision and the
-//           toggle parity of their checks;
-//   claim   one winner per net-toggled check flips its syndrome bit and
-//           updates the unsatisfied-check count;
+//   apply   winners with a positive metric toggle their hard decision;
+//           float inputs also toggle their checks' syndrome bits at once
+//           (atomic xors that return the old bit, so each toggle moves the
+//           unsatisfied-check count by one), integer inputs toggle a
+//           per-round parity of their checks instead;
+//   claim   (integer inputs) one winner per net-toggled check flips its
+//           syndrome bit and updates the unsatisfied-check count;
 //   update  the metrics of the bits of every toggled check change: integer
 //           inputs add +-2 a_den w exactly, float inputs recompute the bit's
-//           metric from scratch in the fixed check order (so results equal
-//           a full recomputation bit for bit).
+//           metric from scratch in the fixed check order from the final
+//           syndrome (so results equal a full recomputation bit for bit).
 // The decoder is a deterministic function of the hard-decision vector; a
 // round without flips, or with the same flips as the round before, proves
 // the state sequence periodic with period 1 or 2, and the output at K_max
@@ -46,6 +50,9 @@ namespace {
 constexpr uint32_t NONE = 0xFFFFFFFFu;
 constexpr int CTL_FLAGS = 0, CTL_WEIGHT = 1;
 constexpr int F_ANY = 1, F_DIFF = 2;
+// task-list entry: check index, with this bit set when the toggle left the
+// check unsatisfied (check indices stay below 2^31)
+constexpr uint32_t TL_UNSAT = 0x80000000u;
 
 struct DecodeArgs {
     const void *y;
@@ -404,6 +411,9 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
         frame_sync<WAVE>();
 
         for (;;) {
+            // the previous round's flags were read before the barrier that
+            // ended it; the flip phase below sets them again
+            if (tid == 0) s.ctl[CTL_FLAGS] = 0;
             // ---- Step 2: choose at most one bit per block ------------------
             if (a.select != FWBF_TOPL) {
                 for (int pi = 0; pi < a.P; pi++) {
@@ -480,15 +490,108 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
             }
             frame_sync<WAVE>();
 
-            // ---- flip the chosen bits; toggle parity of their checks -------
-            for (int u = tid; u < a.W; u += T) {
-                const uint32_t n = s.win[u];
-                const uint32_t pv = s.prv[u];
-                s.prv[u] = n;
-                int fl = (n != pv) ? F_DIFF : 0;
-                if (n != NONE) {
-                    fl |= F_ANY;
-                    atomicXor(&s.zw[n >> 5], 1u << (n & 31));
+            if constexpr (Tt::isf) {
+                // ---- flip the chosen bits and toggle their checks' syndrome -----
+                // Every toggle is an atomic xor that returns the bit it
+                // replaced: the weight moves by one per toggle and each toggle
+                // is listed with the check's new bit (a check toggled by two
+                // winners is listed twice and ends unchanged).
+                for (int u = tid; u < a.W; u += T) {
+                    const uint32_t n = s.win[u];
+                    const uint32_t pv = s.prv[u];
+                    s.prv[u] = n;
+                    uint32_t *tl = s.tl + u * a.dvmax;
+                    for (int t = 0; t < a.dvmax; t++) tl[t] = NONE;
+                    int fl = (n != pv) ? F_DIFF : 0;
+                    if (n != NONE) {
+                        fl |= F_ANY;
+                        atomicXor(&s.zw[n >> 5], 1u << (n & 31));
+                        const uint32_t j = fdiv(n, a.magZ, a.maskZ);
+                        const int c = (int)(n - j * a.Z);
+                        for (int t = 0; t < s.cdeg[j]; t++) {
+                            const uint32_t e = s.col[j * a.dvmax + t];
+                            int r = c - (int)(e & 0xFFFF);
+                            r += (r < 0) ? a.Z : 0;
+                            const uint32_t m = (e >> 24) * a.Z + r;
+                            const uint32_t bit = 1u << (m & 31);
+                            const uint32_t so = atomicXor(&s.syn[m >> 5], bit);
+                            atomicAdd(&s.ctl[CTL_WEIGHT], (so & bit) ? -1 : 1);
+                            tl[t] = (so & bit) ? m : (m | TL_UNSAT);
+                        }
+                    }
+                    if (fl) atomicOr(&s.ctl[CTL_FLAGS], fl);
+                }
+                frame_sync<WAVE>();
+                const int flags = s.ctl[CTL_FLAGS];
+                if (!(a.flags & FWBF_FLAG_NO_CYCLE_EXIT)) {
+                    if (!(flags & F_ANY)) {  // no flip: fixed point until K_max
+                        k = a.max_iter;
+                        break;
+                    }
+                    if (!(flags & F_DIFF)) {
+                        // same flips as the previous round: z_{k+1} = z_{k-1}, the
+                        // states alternate; z_{K_max} = z_k iff K_max - k is even
+                        if (((a.max_iter - k) & 1) == 0)
+                            for (int u = tid; u < a.W; u += T) {
+                                const uint32_t n = s.win[u];
+                                if (n != NONE) atomicXor(&s.zw[n >> 5], 1u << (n & 31));
+                            }
+                        k = a.max_iter;
+                        break;
+                    }
+                }
+                const int weight = s.ctl[CTL_WEIGHT];
+                k += 1;
+                if (weight == 0) { okf = 1; break; }
+                if (k == a.max_iter) break;
+            } else {
+                // ---- flip the chosen bits; toggle parity of their checks -------
+                for (int u = tid; u < a.W; u += T) {
+                    const uint32_t n = s.win[u];
+                    const uint32_t pv = s.prv[u];
+                    s.prv[u] = n;
+                    int fl = (n != pv) ? F_DIFF : 0;
+                    if (n != NONE) {
+                        fl |= F_ANY;
+                        atomicXor(&s.zw[n >> 5], 1u << (n & 31));
+                        const uint32_t j = fdiv(n, a.magZ, a.maskZ);
+                        const int c = (int)(n - j * a.Z);
+                        for (int t = 0; t < s.cdeg[j]; t++) {
+                            const uint32_t e = s.col[j * a.dvmax + t];
+                            int r = c - (int)(e & 0xFFFF);
+                            r += (r < 0) ? a.Z : 0;
+                            const uint32_t m = (e >> 24) * a.Z + r;
+                            atomicXor(&s.tog[m >> 5], 1u << (m & 31));
+                        }
+                    }
+                    if (fl) atomicOr(&s.ctl[CTL_FLAGS], fl);
+                }
+                frame_sync<WAVE>();
+                const int flags = s.ctl[CTL_FLAGS];
+                if (!(a.flags & FWBF_FLAG_NO_CYCLE_EXIT)) {
+                    if (!(flags & F_ANY)) {  // no flip: fixed point until K_max
+                        k = a.max_iter;
+                        break;
+                    }
+                    if (!(flags & F_DIFF)) {
+                        // same flips as the previous round: z_{k+1} = z_{k-1}, the
+                        // states alternate; z_{K_max} = z_k iff K_max - k is even
+                        if (((a.max_iter - k) & 1) == 0)
+                            for (int u = tid; u < a.W; u += T) {
+                                const uint32_t n = s.win[u];
+                                if (n != NONE) atomicXor(&s.zw[n >> 5], 1u << (n & 31));
+                            }
+                        k = a.max_iter;
+                        break;
+                    }
+                }
+
+                // ---- claim net-toggled checks; update syndrome and its weight --
+                for (int u = tid; u < a.W; u += T) {
+                    const uint32_t n = s.win[u];
+                    uint32_t *tl = s.tl + u * a.dvmax;
+                    for (int t = 0; t < a.dvmax; t++) tl[t] = NONE;
+                    if (n == NONE) continue;
                     const uint32_t j = fdiv(n, a.magZ, a.maskZ);
                     const int c = (int)(n - j * a.Z);
                     for (int t = 0; t < s.cdeg[j]; t++) {
@@ -496,67 +599,35 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
                         int r = c - (int)(e & 0xFFFF);
                         r += (r < 0) ? a.Z : 0;
                         const uint32_t m = (e >> 24) * a.Z + r;
-                        atomicXor(&s.tog[m >> 5], 1u << (m & 31));
-                    }
-                }
-                if (fl) atomicOr(&s.ctl[CTL_FLAGS], fl);
-            }
-            frame_sync<WAVE>();
-            const int flags = s.ctl[CTL_FLAGS];
-            if (!(a.flags & FWBF_FLAG_NO_CYCLE_EXIT)) {
-                if (!(flags & F_ANY)) {  // no flip: fixed point until K_max
-                    k = a.max_iter;
-                    break;
-                }
-                if (!(flags & F_DIFF)) {
-                    // same flips as the previous round: z_{k+1} = z_{k-1}, the
-                    // states alternate; z_{K_max} = z_k iff K_max - k is even
-                    if (((a.max_iter - k) & 1) == 0)
-                        for (int u = tid; u < a.W; u += T) {
-                            const uint32_t n = s.win[u];
-                            if (n != NONE) atomicXor(&s.zw[n >> 5], 1u << (n & 31));
+                        const uint32_t bit = 1u << (m & 31);
+                        const uint32_t old = atomicAnd(&s.tog[m >> 5], ~bit);
+                        if (old & bit) {
+                            const uint32_t so = atomicXor(&s.syn[m >> 5], bit);
+                            atomicAdd(&s.ctl[CTL_WEIGHT], (so & bit) ? -1 : 1);
+                            tl[t] = (so & bit) ? m : (m | TL_UNSAT);
                         }
-                    k = a.max_iter;
-                    break;
-                }
-            }
-
-            // ---- claim net-toggled checks; update syndrome and its weight --
-            for (int u = tid; u < a.W; u += T) {
-                const uint32_t n = s.win[u];
-                uint32_t *tl = s.tl + u * a.dvmax;
-                for (int t = 0; t < a.dvmax; t++) tl[t] = NONE;
-                if (n == NONE) continue;
-                const uint32_t j = fdiv(n, a.magZ, a.maskZ);
-                const int c = (int)(n - j * a.Z);
-                for (int t = 0; t < s.cdeg[j]; t++) {
-                    const uint32_t e = s.col[j * a.dvmax + t];
-                    int r = c - (int)(e & 0xFFFF);
-                    r += (r < 0) ? a.Z : 0;
-                    const uint32_t m = (e >> 24) * a.Z + r;
-                    const uint32_t bit = 1u << (m & 31);
-                    const uint32_t old = atomicAnd(&s.tog[m >> 5], ~bit);
-                    if (old & bit) {
-                        const uint32_t so = atomicXor(&s.syn[m >> 5], bit);
-                        atomicAdd(&s.ctl[CTL_WEIGHT], (so & bit) ? -1 : 1);
-                        tl[t] = m;
                     }
                 }
+                frame_sync<WAVE>();
+                const int weight = s.ctl[CTL_WEIGHT];
+                k += 1;
+                if (weight == 0) { okf = 1; break; }
+                if (k == a.max_iter) break;
             }
-            frame_sync<WAVE>();
-            const int weight = s.ctl[CTL_WEIGHT];
-            if (tid == 0) s.ctl[CTL_FLAGS] = 0;
-            k += 1;
-            if (weight == 0) { okf = 1; break; }
-            if (k == a.max_iter) break;
 
             // ---- update the metrics of every bit of a toggled check --------
             const int ntask = a.W * a.dvmax * a.dcmax;
             for (int id = tid; id < ntask; id += T) {
                 const uint32_t e0 = fdiv(id, a.magD, a.maskD);
                 const uint32_t q = id - e0 * a.dcmax;
-                const uint32_t m = s.tl[e0];
-                if (m == NONE) continue;
+                const uint32_t ent = s.tl[e0];
+                if (ent == NONE) continue;
+                const uint32_t m = ent & ~TL_UNSAT;
+                // float: a check toggled by several winners is listed once per
+                // toggle; recompute its members for the entries whose new bit
+                // is the final one (the last toggle among them)
+                if constexpr (Tt::isf)
+                    if (((s.syn[m >> 5] >> (m & 31)) & 1) != (ent >> 31)) continue;
                 const uint32_t i = fdiv(m, a.magZ, a.maskZ);
                 if ((int)q >= s.rdeg[i]) continue;
                 const int r = (int)(m - i * a.Z);
@@ -572,7 +643,7 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
                     s.keys[slot] = metric_val<DT>(a, s, n, imwbf);  // KEY32 is never used for float
                 } else {
                     const int32_t w = weight_i<DT>(s, m, q, imwbf);
-                    const int32_t d = ((s.syn[m >> 5] >> (m & 31)) & 1) ? 2 * a.aden * w : -2 * a.aden * w;
+                    const int32_t d = (ent & TL_UNSAT) ? 2 * a.aden * w : -2 * a.aden * w;
                     atomicAdd(&s.keys[slot], KEY32 ? ((uint32_t)d << a.idxb) : (uint32_t)d);
                 }
             }
