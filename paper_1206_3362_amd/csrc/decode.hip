@@ -508,16 +508,31 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
                         atomicXor(&s.zw[n >> 5], 1u << (n & 31));
                         const uint32_t j = fdiv(n, a.magZ, a.maskZ);
                         const int c = (int)(n - j * a.Z);
-                        for (int t = 0; t < s.cdeg[j]; t++) {
-                            const uint32_t e = s.col[j * a.dvmax + t];
-                            int r = c - (int)(e & 0xFFFF);
-                            r += (r < 0) ? a.Z : 0;
-                            const uint32_t m = (e >> 24) * a.Z + r;
-                            const uint32_t bit = 1u << (m & 31);
-                            const uint32_t so = atomicXor(&s.syn[m >> 5], bit);
-                            atomicAdd(&s.ctl[CTL_WEIGHT], (so & bit) ? -1 : 1);
-                            tl[t] = (so & bit) ? m : (m | TL_UNSAT);
+                        const int deg = s.cdeg[j];
+                        int dw = 0;
+                        // four checks at a time, their toggles issued together
+                        for (int t0 = 0; t0 < deg; t0 += 4) {
+                            uint32_t mq[4], so[4];
+#pragma unroll
+                            for (int u = 0; u < 4; u++) {
+                                const uint32_t e = s.col[j * a.dvmax + min(t0 + u, deg - 1)];
+                                int r = c - (int)(e & 0xFFFF);
+                                r += (r < 0) ? a.Z : 0;
+                                mq[u] = (e >> 24) * a.Z + r;
+                            }
+#pragma unroll
+                            for (int u = 0; u < 4; u++)
+                                so[u] = t0 + u < deg ? atomicXor(&s.syn[mq[u] >> 5], 1u << (mq[u] & 31)) : 0u;
+#pragma unroll
+                            for (int u = 0; u < 4; u++) {
+                                if (t0 + u < deg) {
+                                    const uint32_t bit = 1u << (mq[u] & 31);
+                                    dw += (so[u] & bit) ? -1 : 1;
+                                    tl[t0 + u] = (so[u] & bit) ? mq[u] : (mq[u] | TL_UNSAT);
+                                }
+                            }
                         }
+                        if (dw) atomicAdd(&s.ctl[CTL_WEIGHT], dw);
                     }
                     if (fl) atomicOr(&s.ctl[CTL_FLAGS], fl);
                 }
