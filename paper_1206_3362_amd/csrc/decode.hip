@@ -514,21 +514,21 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
                         for (int t0 = 0; t0 < deg; t0 += 4) {
                             uint32_t mq[4], so[4];
 #pragma unroll
-                            for (int u = 0; u < 4; u++) {
-                                const uint32_t e = s.col[j * a.dvmax + min(t0 + u, deg - 1)];
+                            for (int v = 0; v < 4; v++) {
+                                const uint32_t e = s.col[j * a.dvmax + min(t0 + v, deg - 1)];
                                 int r = c - (int)(e & 0xFFFF);
                                 r += (r < 0) ? a.Z : 0;
-                                mq[u] = (e >> 24) * a.Z + r;
+                                mq[v] = (e >> 24) * a.Z + r;
                             }
 #pragma unroll
-                            for (int u = 0; u < 4; u++)
-                                so[u] = t0 + u < deg ? atomicXor(&s.syn[mq[u] >> 5], 1u << (mq[u] & 31)) : 0u;
+                            for (int v = 0; v < 4; v++)
+                                so[v] = t0 + v < deg ? atomicXor(&s.syn[mq[v] >> 5], 1u << (mq[v] & 31)) : 0u;
 #pragma unroll
-                            for (int u = 0; u < 4; u++) {
-                                if (t0 + u < deg) {
-                                    const uint32_t bit = 1u << (mq[u] & 31);
-                                    dw += (so[u] & bit) ? -1 : 1;
-                                    tl[t0 + u] = (so[u] & bit) ? mq[u] : (mq[u] | TL_UNSAT);
+                            for (int v = 0; v < 4; v++) {
+                                if (t0 + v < deg) {
+                                    const uint32_t bit = 1u << (mq[v] & 31);
+                                    dw += (so[v] & bit) ? -1 : 1;
+                                    tl[t0 + v] = (so[v] & bit) ? mq[v] : (mq[v] | TL_UNSAT);
                                 }
                             }
                         }
@@ -607,19 +607,56 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
                     uint32_t *tl = s.tl + u * a.dvmax;
                     for (int t = 0; t < a.dvmax; t++) tl[t] = NONE;
                     if (n == NONE) continue;
-                    const uint32_t j = fdiv(n, a.magZ, a.maskZ);
-                    const int c = (int)(n - j * a.Z);
-                    for (int t = 0; t < s.cdeg[j]; t++) {
-                        const uint32_t e = s.col[j * a.dvmax + t];
-                        int r = c - (int)(e & 0xFFFF);
-                        r += (r < 0) ? a.Z : 0;
-                        const uint32_t m = (e >> 24) * a.Z + r;
-                        const uint32_t bit = 1u << (m & 31);
-                        const uint32_t old = atomicAnd(&s.tog[m >> 5], ~bit);
-                        if (old & bit) {
-                            const uint32_t so = atomicXor(&s.syn[m >> 5], bit);
-                            atomicAdd(&s.ctl[CTL_WEIGHT], (so & bit) ? -1 : 1);
-                            tl[t] = (so & bit) ? m : (m | TL_UNSAT);
+                    if constexpr (T > 64) {
+                        const uint32_t j = fdiv(n, a.magZ, a.maskZ);
+                        const int c = (int)(n - j * a.Z);
+                        const int deg = s.cdeg[j];
+                        int dw = 0;
+                        // two checks at a time: their claims, then their syndrome
+                        // toggles, each issued together (measured faster in
+                        // workgroups wider than one wavefront, slower in one)
+                        for (int t0 = 0; t0 < deg; t0 += 2) {
+                            uint32_t mq[2], old[2], so[2];
+#pragma unroll
+                            for (int v = 0; v < 2; v++) {
+                                const uint32_t e = s.col[j * a.dvmax + min(t0 + v, deg - 1)];
+                                int r = c - (int)(e & 0xFFFF);
+                                r += (r < 0) ? a.Z : 0;
+                                mq[v] = (e >> 24) * a.Z + r;
+                            }
+#pragma unroll
+                            for (int v = 0; v < 2; v++)
+                                old[v] = t0 + v < deg ? atomicAnd(&s.tog[mq[v] >> 5], ~(1u << (mq[v] & 31))) : 0u;
+#pragma unroll
+                            for (int v = 0; v < 2; v++) {
+                                const uint32_t bit = 1u << (mq[v] & 31);
+                                so[v] = (old[v] & bit) ? atomicXor(&s.syn[mq[v] >> 5], bit) : 0u;
+                            }
+#pragma unroll
+                            for (int v = 0; v < 2; v++) {
+                                const uint32_t bit = 1u << (mq[v] & 31);
+                                if (old[v] & bit) {
+                                    dw += (so[v] & bit) ? -1 : 1;
+                                    tl[t0 + v] = (so[v] & bit) ? mq[v] : (mq[v] | TL_UNSAT);
+                                }
+                            }
+                        }
+                        if (dw) atomicAdd(&s.ctl[CTL_WEIGHT], dw);
+                    } else {
+                        const uint32_t j = fdiv(n, a.magZ, a.maskZ);
+                        const int c = (int)(n - j * a.Z);
+                        for (int t = 0; t < s.cdeg[j]; t++) {
+                            const uint32_t e = s.col[j * a.dvmax + t];
+                            int r = c - (int)(e & 0xFFFF);
+                            r += (r < 0) ? a.Z : 0;
+                            const uint32_t m = (e >> 24) * a.Z + r;
+                            const uint32_t bit = 1u << (m & 31);
+                            const uint32_t old = atomicAnd(&s.tog[m >> 5], ~bit);
+                            if (old & bit) {
+                                const uint32_t so = atomicXor(&s.syn[m >> 5], bit);
+                                atomicAdd(&s.ctl[CTL_WEIGHT], (so & bit) ? -1 : 1);
+                                tl[t] = (so & bit) ? m : (m | TL_UNSAT);
+                            }
                         }
                     }
                 }
