@@ -250,25 +250,62 @@ __device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v,
 // (value << 32 | ~position) where position is the slot offset in the block.
 // Lane l of a block owns positions l, l + L, l + 2L, ...: at every step the
 // lanes of a wavefront touch consecutive words (no LDS bank conflicts), and
-// the first strict maximum along k is the lowest position.
+// the first strict maximum along k is the lowest position.  The slots are
+// read KB at a time, all reads of a chunk issued before any is compared.
 template <bool KEY32>
 __device__ __forceinline__ unsigned long long thread_best(const DecodeArgs &a, const uint32_t *keys, int s0, uint32_t l)
 {
+    constexpr int KB = 8;
     if constexpr (KEY32) {
         uint32_t best = 0;
-        for (int k = 0; k < a.C; k++) best = max(best, keys[s0 + k * a.L]);
+        for (int k0 = 0; k0 < a.C; k0 += KB) {
+            uint32_t v[KB];
+#pragma unroll
+            for (int u = 0; u < KB; u++) v[u] = k0 + u < a.C ? keys[s0 + (k0 + u) * a.L] : 0u;
+#pragma unroll
+            for (int u = 0; u < KB; u++) best = max(best, v[u]);
+        }
         // unpack into the common 64-bit form
         return ((unsigned long long)(best >> a.idxb) << 32) | (0xFFFFFFFFu - (a.idxmask - (best & a.idxmask)));
     } else {
         uint32_t best = 0, bk = 0;
-        for (int k = 0; k < a.C; k++) {
-            const uint32_t v = keys[s0 + k * a.L];
-            const bool gt = v > best;
-            best = gt ? v : best;
-            bk = gt ? (uint32_t)k : bk;
+        for (int k0 = 0; k0 < a.C; k0 += KB) {
+            uint32_t v[KB];
+#pragma unroll
+            for (int u = 0; u < KB; u++) v[u] = k0 + u < a.C ? keys[s0 + (k0 + u) * a.L] : 0u;
+#pragma unroll
+            for (int u = 0; u < KB; u++) {
+                const bool gt = v[u] > best;
+                best = gt ? v[u] : best;
+                bk = gt ? (uint32_t)(k0 + u) : bk;
+            }
         }
         return ((unsigned long long)best << 32) | (0xFFFFFFFFu - (l + bk * (uint32_t)a.L));
     }
+}
+
+// row-local data movement (DPP) of a 64-bit value: xor 1, xor 2, mirror
+// within 8, mirror within 16
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp64(unsigned long long v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, 0xF, 0xF, false);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// maximum over aligned groups of w lanes (w a power of two <= 64, every lane
+// of the wavefront active); every lane of a group ends with the maximum
+__device__ __forceinline__ unsigned long long group_max64(unsigned long long v, int w)
+{
+    unsigned long long o;
+    if (w > 1) { o = dpp64<0xB1>(v); v = o > v ? o : v; }   // quad_perm [1,0,3,2]
+    if (w > 2) { o = dpp64<0x4E>(v); v = o > v ? o : v; }   // quad_perm [2,3,0,1]
+    if (w > 4) { o = dpp64<0x141>(v); v = o > v ? o : v; }  // row_half_mirror
+    if (w > 8) { o = dpp64<0x140>(v); v = o > v ? o : v; }  // row_mirror
+    if (w > 16) { o = shfl_xor_u64(v, 16); v = o > v ? o : v; }
+    if (w > 32) { o = shfl_xor_u64(v, 32); v = o > v ? o : v; }
+    return v;
 }
 
 // Barrier of one frame's threads: the workgroup, or (WAVE) the single
@@ -420,11 +457,7 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
                     const int g = pi * a.GP + (tid >> a.logL);
                     const int l = tid & (a.L - 1);
                     unsigned long long best = thread_best<KEY32>(a, s.keys, g * a.Lc + l, l);
-                    const int lw = a.L < 64 ? a.L : 64;
-                    for (int d = 1; d < lw; d <<= 1) {
-                        const unsigned long long o = shfl_xor_u64(best, d);
-                        best = o > best ? o : best;
-                    }
+                    best = group_max64(best, a.L < 64 ? a.L : 64);
                     if (a.L <= 64) {
                         if ((tid & (a.L - 1)) == 0 && g < a.Geff) {
                             const uint32_t val = (uint32_t)(best >> 32);
@@ -454,10 +487,7 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
                 for (int t = 0; t < a.lambda; t++) {
                     unsigned long long best = thread_best<KEY32>(a, s.keys, (tid >> a.logL) * a.Lc + (tid & (a.L - 1)),
                                                                   tid & (a.L - 1));
-                    for (int d = 1; d < 64; d <<= 1) {
-                        const unsigned long long o = shfl_xor_u64(best, d);
-                        best = o > best ? o : best;
-                    }
+                    best = group_max64(best, 64);
                     if (lane == 0) atomicMax(&s.gb[t & 1], best);
                     frame_sync<WAVE>();
                     best = s.gb[t & 1];
