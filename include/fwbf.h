@@ -69,7 +69,10 @@ typedef struct {
     float alpha;       /* F32: alpha of eq. (1) (ignored for WBF) */
     int32_t alpha_num; /* I8/I16: alpha = alpha_num / alpha_den (>= 0, > 0) */
     int32_t alpha_den;
-    int32_t threads_per_frame; /* 0 = automatic; else 64, 128, 256, 512 or 1024 */
+    int32_t threads_per_frame; /* 0 = automatic (by N; doubled when the
+                                  whole batch fits on the device at once at
+                                  the doubled width); else 64, 128, 256, 512
+                                  or 1024 */
     uint32_t flags;            /* FWBF_FLAG_* */
 } fwbf_params;
 

@@ -1092,7 +1092,6 @@ extern "C" int fwbf_decode(const fwbf_code *code, const fwbf_params *params, con
     int T = 0;
     const int k = prepare_decode(code, params, &a, &T);
     if (k < 0) return k;
-    const bool key32 = k == 1;
     if (F < 0) return fail(FWBF_E_INVALID, "F must be >= 0");
     if (y_stride < code->N) return fail(FWBF_E_INVALID, "y_stride must be >= N");
     if (F == 0) return FWBF_OK;
@@ -1111,22 +1110,48 @@ extern "C" int fwbf_decode(const fwbf_code *code, const fwbf_params *params, con
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return hip_fail(e, "device query");
-    rc = occupancy(params->dtype, key32, T, a.lds_bytes, &blocks);
-    if (rc) return rc;
-    if (!a.mag_alias) {
-        // staging |y| over the slots shrinks the frame's LDS; take that
-        // layout when it lets more frames share a compute unit
-        DecodeArgs b;
-        int Tb = 0, blocks_b = 0;
-        if (prepare_decode(code, params, &b, &Tb, false, true) == k) {
-            rc = occupancy(params->dtype, key32, T, b.lds_bytes, &blocks_b);
-            if (rc) return rc;
-            if (blocks_b > blocks) {
-                a = b;
-                blocks = blocks_b;
+    // the layout for parameters pp and how many of its workgroups fit on a
+    // compute unit; returns prepare_decode's key mode or an error code
+    auto choose = [&](const fwbf_params *pp, DecodeArgs &out, int &Tout, int &bl) -> int {
+        const int kk = prepare_decode(code, pp, &out, &Tout);
+        if (kk < 0) return kk;
+        int r = occupancy(pp->dtype, kk == 1, Tout, out.lds_bytes, &bl);
+        if (r) return r;
+        if (!out.mag_alias) {
+            // staging |y| over the slots shrinks the frame's LDS; take that
+            // layout when it lets more frames share a compute unit
+            DecodeArgs b;
+            int Tb = 0, bb = 0;
+            if (prepare_decode(code, pp, &b, &Tb, false, true) == kk) {
+                r = occupancy(pp->dtype, kk == 1, Tout, b.lds_bytes, &bb);
+                if (r) return r;
+                if (bb > bl) {
+                    out = b;
+                    bl = bb;
+                }
             }
         }
+        return kk;
+    };
+    int kc = choose(params, a, T, blocks);
+    if (kc < 0) return kc;
+    if (params->threads_per_frame == 0 && T < 1024) {
+        // a batch that the wider launch holds at once (every frame gets its
+        // own workgroup immediately) is bound by the time of one frame, and
+        // twice the threads per frame shortens each frame's phases
+        fwbf_params p2 = *params;
+        p2.threads_per_frame = 2 * T;
+        DecodeArgs a2;
+        int T2 = 0, blocks2 = 0;
+        const int k2 = choose(&p2, a2, T2, blocks2);
+        if (k2 >= 0 && blocks2 >= 1 && F <= (int64_t)blocks2 * cus) {
+            a = a2;
+            T = T2;
+            blocks = blocks2;
+            kc = k2;
+        }
     }
+    const bool key32 = kc == 1;
     if (blocks < 1) return fail(FWBF_E_UNSUPPORTED, "decode kernel does not fit on a compute unit");
     a.y = y_dev; a.F = F; a.stride = y_stride;
     a.z = z_dev; a.iters = iters_dev; a.ok = ok_dev;
