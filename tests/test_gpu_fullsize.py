@@ -60,6 +60,24 @@ def test_headline_launch_n1008_int8():
     check_properties(oc, z, it, ok, 100, "n1008 i8 2^20")
 
 
+def test_n186_wbf_all_frames():
+    """(3,6) Z=31 code, all-zero codeword, 1000 float frames at 3 dB from the
+    benchmark's channel seed, WBF, alpha 0.2, G=6, K_max=50, automatic launch
+    width (the whole batch fits on the device, so the library widens it):
+    every frame against the oracle."""
+    need_gpu()
+    from paper_1206_3362_amd import fwbf
+    code = fwbf.Code.from_seed(3, 6, 31, 1)
+    oc = O.Code.from_seed(*CODES["n186"])
+    F = 1000
+    y = fwbf.channel(code.N, F, 0, None, 2024, 0, float(synth.sigma_for(3.0, code.rate)))
+    p = fwbf.DecodeParams(dtype=fwbf.F32, weights=fwbf.WBF, groups=6, max_iter=50, alpha=0.2)
+    z, it, ok = fwbf.decode(code, y, p)
+    torch.cuda.synchronize()
+    check_sampled(oc, y, z, it, ok, np.arange(F), "n186 wbf 1000", weights=0, groups=6, max_iter=50, alpha=0.2)
+    check_properties(oc, z, it, ok, 50, "n186 wbf 1000")
+
+
 def test_mixed_batch_full_size():
     """N=1008/4032 (3,6) and N=8000 (4,20) codes with 2^18/2^16/2^15 float
     frames, Eb/N0 drawn per frame from U[3,6] dB, G=8/32/64, K_max=100, all
