@@ -25,9 +25,9 @@ sys.path.insert(0, ROOT)
 METRIC = "decoded Gb/s at fixed FER (N=1008, 4 dB), learned vs plain FWBF; % HBM peak"
 HBM_PEAK_GBS = 8000.0
 # mixed-code batch: (code (mb, nb, Z, seed), frames, reference G, G candidates)
-MIXED_JOBS = [((3, 6, 168, 2), 1 << 18, 8, (4, 6, 8, 12, 16)),
-              ((3, 6, 672, 3), 1 << 16, 32, (8, 12, 16, 24, 32, 48)),
-              ((4, 20, 400, 4), 1 << 15, 64, (16, 24, 32, 48, 64, 96))]
+MIXED_JOBS = [((3, 6, 168, 2), 1 << 18, 8, (2, 3, 4, 6, 8, 12, 16)),
+              ((3, 6, 672, 3), 1 << 16, 32, (4, 8, 12, 16, 24, 32, 48)),
+              ((4, 20, 400, 4), 1 << 15, 64, (4, 8, 12, 16, 24, 32, 48, 64, 96))]
 MIXED_TUNE = dict(tune_frames=1 << 14, widths=(0, 128, 256), blocks=(0, 2, 4), repeats=3)
 
 
