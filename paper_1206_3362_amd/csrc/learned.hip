@@ -754,18 +754,38 @@ __global__ __launch_bounds__(64) void grad_kernel(GradArgs g)
     }
 }
 
-// sums the per-workgroup partials in workgroup order and divides by the
-// number of valid records: out[0..P) gradient, out[P] loss, out[P+1] count
-__global__ void reduce_kernel(const float *partial, int nparts, int P, float *out)
+// sums the per-workgroup partials and divides by the number of valid
+// records: out[0..P) gradient, out[P] loss, out[P+1] count.  A workgroup
+// takes 64 consecutive entries (one per lane); its wavefront w adds the
+// partials w, w + RED_W, w + 2 RED_W, ... in that order, and wavefront 0 then
+// adds the RED_W sums in wavefront order: a fixed order, so the result does
+// not depend on scheduling.  Sums in double precision.
+constexpr int RED_W = 16;
+__global__ __launch_bounds__(64 * RED_W) void reduce_kernel(const float *partial, int nparts, int P, float *out)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P + 2) return;
+    __shared__ double acc_s[RED_W][64];
+    __shared__ double cnt_s[RED_W];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + lane;
+    const bool live = i < P + 2;
     double acc = 0.0, cnt = 0.0;
-    for (int b = 0; b < nparts; b++) {
-        acc += partial[(size_t)b * (P + 2) + i];
-        cnt += partial[(size_t)b * (P + 2) + P + 1];
+#pragma unroll 4
+    for (int b = w; b < nparts; b += RED_W) {
+        const float *row = partial + (size_t)b * (P + 2);
+        if (live) acc += row[i];
+        cnt += row[P + 1];
     }
-    out[i] = (i == P + 1) ? (float)cnt : (float)(cnt > 0 ? acc / cnt : 0.0);
+    acc_s[w][lane] = acc;
+    if (lane == 0) cnt_s[w] = cnt;
+    __syncthreads();
+    if (w == 0 && live) {
+        double a = 0.0, c = 0.0;
+        for (int v = 0; v < RED_W; v++) {
+            a += acc_s[v][lane];
+            c += cnt_s[v];
+        }
+        out[i] = (i == P + 1) ? (float)c : (float)(c > 0 ? a / c : 0.0);
+    }
 }
 
 __global__ void adam_kernel(float *p, const float *g, float *m, float *v, int P, float lr, float b1, float b2,
@@ -941,7 +961,8 @@ extern "C" int fwbf_scorer_grad(const fwbf_record *records_dev, int64_t n_tiles,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "scorer gradient launch");
     if (out_dev) {
-        hipLaunchKernelGGL(reduce_kernel, dim3((P + 2 + 255) / 256), dim3(256), 0, st, workspace_dev, parts, P, out_dev);
+        hipLaunchKernelGGL(reduce_kernel, dim3((P + 2 + 63) / 64), dim3(64 * RED_W), 0, st, workspace_dev, parts, P,
+                           out_dev);
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "gradient reduction launch");
     }

@@ -76,6 +76,10 @@ def test_gradients_match_reference():
     out = torch.zeros(P + 2, dtype=torch.float32, device="cuda")
     fwbf.scorer_grad(to_dev(rec), 512, lp, torch.from_numpy(p).cuda(), 2.0, out=out)
     g = out.cpu().numpy().astype(np.float64)
+    # the workgroup partials are summed in a fixed order: a second run is bit-identical
+    out2 = torch.zeros_like(out)
+    fwbf.scorer_grad(to_dev(rec), 512, lp, torch.from_numpy(p).cuda(), 2.0, out=out2)
+    assert torch.equal(out, out2)
     v = rec["valid"].astype(bool)
     tt = np.broadcast_to(t[:, None], rec.shape)[v]
     a, S, u, lab = rec["a"][v], rec["S"][v], rec["u"][v], rec["label"][v].astype(np.float64)
