@@ -609,6 +609,8 @@ __global__ __launch_bounds__(64) void grad_kernel(GradArgs g)
     __shared__ float sh2[32][33];  // h2 [hidden][cand]
     __shared__ float sx[4][33];    // features (rounded) [feature][cand]
     __shared__ float sab[2][64];   // alpha / beta gradient accumulators per round
+    __shared__ float sds[32];      // d loss / d score of every candidate of the tile
+    __shared__ float sw1c[32];     // W1[k][1] (rounded), the E_t column of layer 1
     const int l = threadIdx.x, j = l & 31, hi = l >> 5;
     Net net;
     load_net(net, g.params);
@@ -624,7 +626,7 @@ __global__ __launch_bounds__(64) void grad_kernel(GradArgs g)
         w2t[c] = pack4(g.params[O_W2 + (k0 + 0) * H + j], g.params[O_W2 + (k0 + 1) * H + j],
                        g.params[O_W2 + (k0 + 2) * H + j], g.params[O_W2 + (k0 + 3) * H + j]);
     }
-    const float w1col1 = bf16_f(bf16_rne(g.params[O_W1 + j * 4 + 1]));
+    if (l < 32) sw1c[l] = bf16_f(bf16_rne(g.params[O_W1 + l * 4 + 1]));
     __syncthreads();
     for (int64_t tile = blockIdx.x; tile < g.n_tiles; tile += gridDim.x) {
         const int t = (int)(tile % g.T);
@@ -673,6 +675,7 @@ __global__ __launch_bounds__(64) void grad_kernel(GradArgs g)
             sp1[row][j] = act.pre1[q] > 0.0f ? dh1[q] : 0.0f;
         }
         if (hi == 0) {
+            sds[j] = ds;
             sx[0][j] = bf16_f((uint16_t)x[0]);
             sx[1][j] = bf16_f((uint16_t)x[1]);
             sx[2][j] = bf16_f((uint16_t)x[2]);
@@ -693,7 +696,7 @@ __global__ __launch_bounds__(64) void grad_kernel(GradArgs g)
                 s1a = __builtin_fmaf(sp1[j][c], sx[0][c], s1a);
                 s1b = __builtin_fmaf(sp1[j][c], sx[1][c], s1b);
                 sb1 += sp1[j][c];
-                sw3 = __builtin_fmaf(sh2[j][c], __shfl(ds, c, 64), sw3);
+                sw3 = __builtin_fmaf(sh2[j][c], sds[c], sw3);
             }
             aW1a += s1a; aW1b += s1b; aB += sb1; aW3 += sw3;
         } else {
@@ -707,7 +710,7 @@ __global__ __launch_bounds__(64) void grad_kernel(GradArgs g)
         }
         // d x1 of candidate j -> alpha_t, beta_t
         float dx1 = 0;
-        for (int k = 0; k < 32; k++) dx1 = __builtin_fmaf(sp1[k][j], __shfl(w1col1, k, 64), dx1);
+        for (int k = 0; k < 32; k++) dx1 = __builtin_fmaf(sp1[k][j], sw1c[k], dx1);
         float ga = 0, gb = 0;
         if (hi == 0 && valid) {
             ga = dx1 * (-(float)r.a / g.A);
