@@ -255,7 +255,7 @@ __device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v,
 template <bool KEY32>
 __device__ __forceinline__ unsigned long long thread_best(const DecodeArgs &a, const uint32_t *keys, int s0, uint32_t l)
 {
-    constexpr int KB = 8;
+    constexpr int KB = 4;
     if constexpr (KEY32) {
         uint32_t best = 0;
         for (int k0 = 0; k0 < a.C; k0 += KB) {
