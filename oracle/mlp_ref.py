@@ -191,6 +191,23 @@ def exact_backward(params, a, S, u, t_idx, label, A, dv, T, pos_weight):
 
 
 # --------------------------------------------------------------------------
+# optimizer
+# --------------------------------------------------------------------------
+def adam_step(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One step of Adam (Kingma & Ba, 2015, Algorithm 1), float64, written
+    out as the published algorithm: biased moments, bias correction for step
+    number `step` (1-based), then the update with eps added to the square
+    root of the corrected second moment.  Returns new (params, m, v)."""
+    g = np.asarray(grad, np.float64)
+    m = beta1 * np.asarray(m, np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, np.float64) + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** step)
+    v_hat = v / (1.0 - beta2 ** step)
+    p = np.asarray(params, np.float64) - lr * m_hat / (np.sqrt(v_hat) + eps)
+    return p, m, v
+
+
+# --------------------------------------------------------------------------
 # learned decoding of one frame (literal, per round)
 # --------------------------------------------------------------------------
 def _adjacency(code):

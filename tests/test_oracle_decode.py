@@ -36,6 +36,38 @@ def test_hand_worked_example():
 VARIANTS = [(O.WBF, 0.0, 0, 1), (O.MWBF, 0.2, 1, 5), (O.IMWBF, 0.2, 1, 5)]
 
 
+@pytest.mark.parametrize("dtype,div", [(np.int8, 1), (np.int16, 1), (np.float32, 8)])
+def test_mwbf_is_wbf_minimum_minus_alpha_term(ocodes, dtype, div):
+    """WBF and MWBF share the check reliability (the minimum of |y| over all
+    of N(m), Section I), and MWBF subtracts alpha |y_n|: on any frame the
+    round-0 MWBF metric equals a_den S - a_num |y_n|, with S the WBF metric
+    at alpha = 0.  IMWBF (minimum over the other members) differs from it
+    wherever a check's minimum is held by one member.  Non-uniform |y| on
+    the N = 186 code; float frames are multiples of 1/8 so that every metric
+    is exact."""
+    c = ocodes("n186")
+    rng = np.random.default_rng(5)
+    differs = 0
+    for f in range(12):
+        q = rng.integers(-90, 91, c.N)
+        y = (q / div).astype(dtype) if div > 1 else q.astype(dtype)
+        a = np.abs(y.astype(np.float64))
+        S = O.decode_trace(c, y, weights=O.WBF, G=6, max_iter=1, alpha=0.0, alpha_num=0, alpha_den=1)["E0"]
+        if div > 1:
+            mw = O.decode_trace(c, y, weights=O.MWBF, G=6, max_iter=1, alpha=0.25)["E0"]
+            im = O.decode_trace(c, y, weights=O.IMWBF, G=6, max_iter=1, alpha=0.25)["E0"]
+            want = S - 0.25 * a
+        else:
+            mw = O.decode_trace(c, y, weights=O.MWBF, G=6, max_iter=1, alpha_num=1, alpha_den=4)["E0"]
+            im = O.decode_trace(c, y, weights=O.IMWBF, G=6, max_iter=1, alpha_num=1, alpha_den=4)["E0"]
+            want = 4 * S - a
+        if np.isnan(S).all():
+            continue  # zero initial syndrome: no metric evaluated
+        assert np.array_equal(mw, want)
+        differs += int((im != mw).any())
+    assert differs > 0
+
+
 @pytest.mark.parametrize("dtype,A", [(np.float32, 1.0), (np.int8, 16), (np.int16, 256)])
 def test_noiseless_zero_iterations(ocodes, dtype, A):
     """Noiseless y = A(1-2c): z_0 = c, zero syndrome, stop before any round
@@ -272,28 +304,37 @@ def test_eg_error_patterns_closed_form(s, dtype, A):
         assert (ok == 1).all() and it.tolist() == [-(-len(p) // 5) for p in pats]
 
 
-# Tab. 1 of the paper: averaged iterations on EG(1023,781), K_max = 10
-TAB1 = {11: (1.0, {3.5: 7.37, 4.0: 6.06, 4.5: 5.12}),   # p = 93
-        33: (1.5, {3.5: 5.60, 4.0: 4.19, 4.5: 3.64})}   # p = 31
+# Tab. 1 of the paper: averaged iterations on EG(1023,781), K_max = 10,
+# FWBF with p = 93 (11 blocks) and p = 31 (33 blocks), 3.0 to 4.5 dB
+TAB1 = {11: {3.0: 9.29, 3.5: 7.37, 4.0: 6.06, 4.5: 5.12},   # p = 93
+        33: {3.0: 8.62, 3.5: 5.60, 4.0: 4.19, 4.5: 3.64}}   # p = 31
+TAB1_ALPHA = 1.5
 
 
 @pytest.mark.parametrize("G", [11, 33])
 def test_table1_statistical(G):
-    """Averaged iterations of FWBF on EG(1023,781) against the values printed
-    in Tab. 1 (3.5 to 4.5 dB; float inputs, IMWBF metric).  Two readings make
-    the comparison: an iteration is a pass of Step 1 (a syndrome evaluation),
-    so a frame that stops on a zero syndrome after r flip rounds counts
-    min(r + 1, K_max) and every other frame K_max; alpha, which the paper
-    does not give, is the one value per row that fits it (1.0 for p=93, 1.5
-    for p=31).  2000 frames per point (standard error about 0.03)."""
+    """Averaged iterations of FWBF on EG(1023,781) against every value printed
+    in Tab. 1 for the two FWBF rows (3.0 to 4.5 dB; float inputs, IMWBF
+    metric).  Two readings make the comparison: an iteration is a pass of
+    Step 1 (a syndrome evaluation), so a frame that stops on a zero syndrome
+    after r flip rounds counts min(r + 1, K_max) and every other frame K_max;
+    alpha, which the paper does not give, is one value (1.5) for the whole
+    table.  2000 frames per point.  Tolerance: 0.2, or three standard errors
+    of the difference where that is larger -- Section V simulates each point
+    until 100 frame errors, so near FER 0.5 (3.0 dB) the printed average
+    rests on about 200 frames."""
     c = O.Code.from_text(synth.eg_code_text(5))
-    al, pts = TAB1[G]
-    for eb, want in pts.items():
-        y = synth.awgn_frames(c.N, 2000, synth.sigma_for(eb, c.K / c.N), int(eb * 10) + G, None,
+    F = 2000
+    for eb, want in TAB1[G].items():
+        y = synth.awgn_frames(c.N, F, synth.sigma_for(eb, c.K / c.N), int(eb * 10) + G, None,
                               np.float32)
-        z, it, ok = O.decode(c, y, G=G, max_iter=10, alpha=al, weights=O.IMWBF)
+        z, it, ok = O.decode(c, y, G=G, max_iter=10, alpha=TAB1_ALPHA, weights=O.IMWBF)
         passes = np.where(ok == 1, np.minimum(it + 1, 10), 10)
-        assert abs(passes.mean() - want) < 0.2, (G, eb, passes.mean(), want)
+        fer = float(((ok == 0) | O.unpack(z, c.N).any(1)).mean())
+        n_paper = 100.0 / max(fer, 1e-6)
+        se = float(np.sqrt(passes.var() / n_paper + passes.var() / F))
+        tol = max(0.2, 3.0 * se)
+        assert abs(passes.mean() - want) < tol, (G, eb, passes.mean(), want, tol)
 
 
 def _permuted_code_text(H, perm):

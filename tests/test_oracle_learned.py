@@ -115,3 +115,48 @@ def test_zero_scorer_never_flips():
     z, rounds, ok, recs = R.learned_decode_frame(code, y, params, T, 6, 2, 16.0, 3)
     assert rounds == 0 and not ok and (z == (y < 0)).all()
     assert len(recs) == 6 * 2
+
+
+# ---- the Adam step (Kingma & Ba, Algorithm 1) against closed forms --------
+def test_adam_first_step_closed_form():
+    """From zero moments the bias-corrected moments of step 1 are g and g^2,
+    so the first step moves every parameter by -lr g / (|g| + eps)."""
+    rng = np.random.default_rng(21)
+    p0 = rng.normal(size=500)
+    g = rng.normal(size=500) * 10.0 ** rng.uniform(-6, 2, 500)
+    for lr, b1, b2, eps in [(1e-3, 0.9, 0.999, 1e-8), (0.3, 0.5, 0.25, 1e-3)]:
+        p1, m1, v1 = R.adam_step(p0, g, np.zeros(500), np.zeros(500), 1, lr, b1, b2, eps)
+        np.testing.assert_allclose(p1, p0 - lr * g / (np.abs(g) + eps), rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(m1, (1 - b1) * g, rtol=1e-15)
+        np.testing.assert_allclose(v1, (1 - b2) * g * g, rtol=1e-15)
+
+
+def test_adam_constant_gradient_and_zero_gradient():
+    """A constant gradient keeps the corrected moments at g and g^2 in every
+    step: after t steps p = p0 - t lr g / (|g| + eps).  A zero gradient
+    never moves the parameters."""
+    g = np.array([2.0, -0.5, 1e-4, -3e3])
+    p = np.array([1.0, 2.0, -3.0, 0.5])
+    m = np.zeros(4)
+    v = np.zeros(4)
+    lr, eps = 1e-2, 1e-8
+    for t in range(1, 21):
+        p, m, v = R.adam_step(p, g, m, v, t, lr, 0.9, 0.999, eps)
+        np.testing.assert_allclose(p, np.array([1.0, 2.0, -3.0, 0.5]) - t * lr * g / (np.abs(g) + eps),
+                                   rtol=1e-11, atol=1e-13)
+    q, _, _ = R.adam_step(np.ones(3), np.zeros(3), np.zeros(3), np.zeros(3), 1, 0.1)
+    assert (q == 1.0).all()
+
+
+def test_adam_two_steps_by_hand_and_eps_placement():
+    """beta1 = beta2 = 1/2, lr = 0.3, eps = 0: gradient 1 then -1 from zero
+    moments.  Step 1: m = 1/2, v = 1/2, corrected 1 and 1, p = -0.3.
+    Step 2: m = -1/4, v = 3/4, corrected -1/3 and 1, p = -0.3 + 0.1 = -0.2.
+    eps sits outside the square root: with g = eps = 1e-8 the first step is
+    lr / 2 (inside the root it would be about lr 1e-4)."""
+    p, m, v = R.adam_step([0.0], [1.0], [0.0], [0.0], 1, 0.3, 0.5, 0.5, 0.0)
+    assert abs(p[0] + 0.3) < 1e-15 and m[0] == 0.5 and v[0] == 0.5
+    p, m, v = R.adam_step(p, [-1.0], m, v, 2, 0.3, 0.5, 0.5, 0.0)
+    assert abs(p[0] + 0.2) < 1e-15 and m[0] == -0.25 and v[0] == 0.75
+    p, _, _ = R.adam_step([0.0], [1e-8], [0.0], [0.0], 1, 0.5, 0.9, 0.999, 1e-8)
+    assert abs(p[0] + 0.25) < 1e-12
