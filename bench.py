@@ -45,6 +45,8 @@ def parse():
                     help="target CPU time of the oracle baseline sample (0 = skip)")
     ap.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "traffic_decode_n1008_i8_4db.json"))
     ap.add_argument("--learned", type=int, default=1, help="also time the learned decoder (1/0)")
+    ap.add_argument("--fer-table", type=int, default=1,
+                    help="also time plain FWBF at G = 1, 2, 4, 8 and SINGLE on the same frames (1/0)")
     ap.add_argument("--scorer", type=str,
                     default=os.path.join(ROOT, "paper_1206_3362_amd", "scorer_n1008_g32_t16.npz"))
     ap.add_argument("--workload", default="n1008_i8",
@@ -176,8 +178,21 @@ def main():
                      "bytes_per_frame": bytes_per_frame},
         "wall_s": round(wall, 3),
     }
+    # rounds the kernel actually runs (the repeated-state shortcut reports
+    # K_max for frames whose state repeats): an untimed diagnostic decode
+    pe = fwbf.DecodeParams(**{**params.__dict__, "flags": params.flags | fwbf.FLAG_EXECUTED_ROUNDS})
+    fwbf.decode_into(code, ys[0], pe, z, it, ok)
+    out["executed_rounds"] = round(float(it.double().mean().item()), 3)
+    prof = valu_profile()
+    if prof:
+        issue = F * prof["valu_insts_per_frame"] * 4 / (1024 * 2.4e9) / (dec_avg * 1e-3)
+        out["valu_issue_frac"] = round(issue, 3)
+        out["valu_note"] = ("wave64 VALU instructions per frame from %s x frames x 4 cycles over "
+                            "1024 SIMDs at 2.4 GHz, divided by the decode time" % prof["source"])
     if a.learned:
         out["learned"] = learned_leg(code, ys, pool, params, a, N, F, ms_step, c)
+    if a.fer_table:
+        out["fer_vs_gbps"] = fer_table(code, ys, pool, params, a, N, F, out)
     if a.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(code, ys[0], params, a, N)
     print(json.dumps(out), flush=True)
@@ -223,6 +238,56 @@ def learned_leg(code, ys, pool, params, a, N, F, plain_ms, plain_counts):
             "learned_pass_only": float(lok.float().mean().item()),
             "scorer": os.path.basename(a.scorer), "rounds": lp.rounds, "groups": lp.groups,
             "topk": lp.topk}
+
+
+def fer_table(code, ys, pool, params, a, N, F, out):
+    """Decoded Gb/s against FER on the same resident frames: plain FWBF with
+    fewer, longer blocks (G = 1, 2, 4, 8) and the single-bit rule (SINGLE),
+    beside the learned decoder, so that Gb/s can be read at a fixed FER.
+    Each row: 3 timed steps after 1 warm-up, counts over the first batch."""
+    import torch
+
+    from paper_1206_3362_amd import fwbf
+    rows = []
+    z = torch.empty((F, (N + 31) // 32), dtype=torch.int32, device="cuda")
+    it = torch.empty(F, dtype=torch.int32, device="cuda")
+    ok = torch.empty(F, dtype=torch.uint8, device="cuda")
+    cases = [(f"plain G={G}", dict(groups=G)) for G in (1, 2, 4, 8)] + [("plain SINGLE", dict(select=fwbf.SINGLE))]
+    for name, kw in cases:
+        p = fwbf.DecodeParams(**{**params.__dict__, **kw})
+        ms = _timed(lambda: fwbf.decode_into(code, ys[0], p, z, it, ok), 3, 1)
+        r = fwbf.count(N, z, pool, 0, it, ok, a.max_iter)
+        pe = fwbf.DecodeParams(**{**p.__dict__, "flags": p.flags | fwbf.FLAG_EXECUTED_ROUNDS})
+        fwbf.decode_into(code, ys[0], pe, z, it, ok)
+        rows.append({"decoder": name, "fer": round(r["frame_err"] / F, 5),
+                     "gbps": round(F * N / (ms * 1e-3) / 1e9, 3), "ms": round(ms, 4),
+                     "mean_rounds": round(r["iter_sum"] / F, 3),
+                     "executed_rounds": round(float(it.double().mean().item()), 3)})
+    if "learned" in out:
+        L = out["learned"]
+        rows.append({"decoder": "learned + plain fallback", "fer": round(L["fer"], 5), "gbps": L["value"],
+                     "ms": L["ms_per_step"]})
+        fer_l = L["fer"]
+        sd = 3.0 * (fer_l * (1 - fer_l) * 2.0 / F) ** 0.5
+        reach = [r for r in rows[:-1] if r["fer"] <= fer_l + sd]
+        rows.append({"at_learned_fer": {
+            "learned_gbps": L["value"], "learned_fer": round(fer_l, 5),
+            "fastest_plain_at_or_below": max(reach, key=lambda r: r["gbps"]) if reach else None,
+            "note": ("no plain configuration in the table reaches the learned decoder's FER at this "
+                     "Eb/N0" if not reach else "plain configurations within 3 sigma of the learned FER")}})
+    return rows
+
+
+def valu_profile():
+    """VALU instructions per frame of the timed kernel from the committed
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_decode_n1008_i8_4db.json")
+    if not os.path.exists(path):
+        return None
+    tr = json.load(open(path))
+    if tr.get("kernel_source_sha") != kernel_sha() or "valu_insts_per_frame" not in tr:
+        return None
+    return {"valu_insts_per_frame": tr["valu_insts_per_frame"], "source": "profiles/" + os.path.basename(path)}
 
 
 def _timed(fn, steps, warmup):
@@ -330,7 +395,7 @@ def other_workload(a):
         code = fwbf.Code.from_seed(3, 6, 168, 2)
         pool = torch.from_numpy(code.encode(1001, 0, 1024).view(np.int32)).to(dev)
         ebs = np.arange(2.0, 6.01, 0.5)
-        F = 1 << 18
+        F = 1 << 20
         sw = fwbf.Sweep(code, fwbf.DecodeParams(dtype=fwbf.I8, groups=8, max_iter=100),
                         synth.sigma_for(ebs, code.rate), F, pool=pool, seed=1100, scale=16.0)
         ms = _timed(sw.launch, a.steps, a.warmup)
@@ -340,7 +405,7 @@ def other_workload(a):
                     dtype="int32",
                     fer={f"{e:.1f}": float(c[k, 1] / c[k, 4]) for k, e in enumerate(ebs)},
                     ber={f"{e:.1f}": float(c[k, 0] / (c[k, 4] * code.N)) for k, e in enumerate(ebs)},
-                    config={"workload": "N=1008 int8 G=8, 9 points 2..6 dB, 2^18 frames per point",
+                    config={"workload": "N=1008 int8 G=8, 9 points 2..6 dB, 2^20 frames per point",
                             "frames": int(len(ebs) * F)})
     print(json.dumps(line), flush=True)
 
@@ -562,28 +627,50 @@ def kernel_sha():
     return h.hexdigest()[:16]
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(code, y_dev, params, a, N):
-    """The CPU oracle (unchanged) on a bounded sample of the same frames."""
+    """The CPU oracle (unchanged) on a bounded sample of the same frames:
+    once on the host's CPU share (every CPU this process may run on, at most
+    16, the share of one GPU on the GPU hosts), once on one thread."""
     import numpy as np
 
     import oracle as O
     oc = O.Code.from_seed(3, 6, 168, 2)
-    threads = min(os.cpu_count() or 1, 16)
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    threads = max(1, min(avail, 16))
     y = y_dev[:1 << 18].cpu().numpy()
     kw = dict(weights=O.IMWBF, select=O.GROUPS, G=params.groups, max_iter=params.max_iter,
-              alpha_num=1, alpha_den=5, threads=threads)
-    n0 = 512
-    t = time.perf_counter()
-    O.decode(oc, y[:n0], **kw)
-    dt = time.perf_counter() - t
-    n = int(min(len(y), max(n0, n0 * a.cpu_seconds / max(dt, 1e-6))))
-    t = time.perf_counter()
-    O.decode(oc, y[:n], **kw)
-    dt = time.perf_counter() - t
+              alpha_num=1, alpha_den=5)
+
+    def rate(nthreads, seconds):
+        n0 = 64 * nthreads
+        t = time.perf_counter()
+        O.decode(oc, y[:n0], threads=nthreads, **kw)
+        dt = time.perf_counter() - t
+        n = int(min(len(y), max(n0, n0 * seconds / max(dt, 1e-6))))
+        t = time.perf_counter()
+        O.decode(oc, y[:n], threads=nthreads, **kw)
+        dt = time.perf_counter() - t
+        return n, dt
+
+    n, dt = rate(threads, a.cpu_seconds)
+    n1, dt1 = rate(1, a.cpu_seconds / 2)
     return {"value": round(n * N / dt / 1e9, 6), "unit": "Gb/s", "cores": threads,
             "kind": "oracle",
             "sample": f"first {n} frames of the timed batch, literal oracle, {threads} threads, "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s; single thread: first {n1} frames, {dt1:.1f} s",
+            "single_thread_gbps": round(n1 * N / dt1 / 1e9, 6),
+            "cpus_available": avail, "nproc": os.cpu_count(), "cpu_model": _cpu_model()}
 
 
 if __name__ == "__main__":

@@ -54,6 +54,18 @@ enum { FWBF_GROUPS = 0, FWBF_SINGLE = 1, FWBF_TOPL = 2, FWBF_STRIDED = 3 };
                                       the state repeats (for verification) */
 #define FWBF_FLAG_GENERIC_KERNEL 2u /* use the general kernel even where the
                                        specialised one applies (verification) */
+#define FWBF_FLAG_SPECIALISED_ONLY 4u /* fail with FWBF_E_UNSUPPORTED (enqueue
+                                         nothing) unless a one-wave specialised
+                                         kernel (regular full-base codes with
+                                         fixed-point inputs, or single
+                                         circulants) takes the call: lets a
+                                         test pin the kernel it exercises */
+#define FWBF_FLAG_EXECUTED_ROUNDS 8u /* diagnostic: iters_dev receives, for a
+                                        frame whose state repeats (a round
+                                        with no flip, or with the previous
+                                        round's flips), the rounds run before
+                                        that round instead of the equivalent
+                                        max_iter; z and ok are unchanged */
 
 typedef struct fwbf_code fwbf_code;
 
@@ -220,9 +232,11 @@ typedef struct fwbf_sweep fwbf_sweep;
 /* Records, for each of n_points noise levels sigma_host[i], frame generation
  * (fwbf_channel with stream_id i, frames 0 .. frames_per_point-1) ->
  * fwbf_decode -> fwbf_count into one HIP graph, instantiated for the
- * current device.  The sweep owns its frame, output and counter buffers
- * (counters cleared by a kernel at the start of every replay, never by a
- * memset node).  pool_dev must stay valid while the sweep is used. */
+ * current device.  The sweep owns its frame, output and counter buffers,
+ * one set of frames and outputs per point (n_points * frames_per_point
+ * frames in all; counters cleared by a kernel at the start of every replay,
+ * never by a memset node).  pool_dev must stay valid while the sweep is
+ * used. */
 int fwbf_sweep_create(const fwbf_code *code, const fwbf_params *params, const float *sigma_host, int n_points,
                       int64_t frames_per_point, const uint32_t *pool_dev, int64_t pool_n, uint64_t seed,
                       float scale, fwbf_sweep **out);
@@ -231,6 +245,12 @@ int fwbf_sweep_launch(fwbf_sweep *sweep, void *stream);
 /* Copies the counters (n_points x (max_iter + 7) int64, layout of
  * fwbf_count) to host memory after the work queued on `stream`; waits. */
 int fwbf_sweep_counters(fwbf_sweep *sweep, int64_t *counters_host, void *stream);
+/* Copies point `point`'s received frames (y_dev: [frames_per_point][N] of
+ * the sweep's dtype) and the decoder outputs of the last replay (layouts of
+ * fwbf_decode) into caller device buffers, stream-ordered after the work on
+ * `stream`; any destination may be NULL. */
+int fwbf_sweep_outputs(const fwbf_sweep *sweep, int point, void *y_dev, uint32_t *z_dev, int32_t *iters_dev,
+                       uint8_t *ok_dev, void *stream);
 void fwbf_sweep_free(fwbf_sweep *sweep);
 
 /* ---- learned flip scorer (extension; keeps the per-block choice) -------- */

@@ -272,3 +272,123 @@ def learned_decode_frame(code, y, params, T, G, k, A, dv, adj=None, trace=None):
             z[n] ^= 1
         prev = flips
         t += 1
+
+
+def learned_decode_batch(code, Y, params, T, G, k, A, dv):
+    """The learned pass of learned_decode_frame over many frames at once (the
+    frames are independent and all live frames are in the same round, so
+    each step of a round is one array operation over the frames).  Returns
+    (z bits [F][N], rounds [F], ok [F], trace): trace[t] = (frames, cand,
+    score) for round t, with cand and score [frames][G'][k'] (G' blocks, k'
+    candidates per block) for the frames that ran round t."""
+    rp, rb = code.rows()
+    N, M = code.N, code.M
+    Y = np.asarray(Y, np.int64)
+    if Y.ndim == 1:
+        Y = Y[None]
+    F = Y.shape[0]
+    deg = np.diff(rp)
+    dcm = int(deg.max())
+    members = np.full((M, dcm), N, np.int64)           # column N: a zero pad
+    for m in range(M):
+        members[m, :deg[m]] = rb[rp[m]:rp[m + 1]]
+    # the checks of every bit (ascending m) and the bit's place in each check
+    chk_of = [[] for _ in range(N)]
+    for m in range(M):
+        for j in range(deg[m]):
+            chk_of[members[m, j]].append((m, j))
+    dvm = max(len(c) for c in chk_of)
+    bm = np.full((N, dvm), M, np.int64)                # row M: a zero pad
+    bj = np.zeros((N, dvm), np.int64)
+    for n in range(N):
+        for t_, (m, j) in enumerate(chk_of[n]):
+            bm[n, t_], bj[n, t_] = m, j
+    a = np.abs(Y)
+    apad = np.concatenate([a, np.zeros((F, 1), np.int64)], 1)
+    # IMWBF weight of edge (m, j): minimum of |y| over the other members of m
+    am = apad[:, members]                               # [F][M][dcm]
+    big = np.iinfo(np.int64).max
+    w = np.zeros((F, M + 1, dcm), np.int64)
+    for j in range(dcm):
+        others = [i for i in range(dcm) if i != j]
+        if others:
+            vals = am[:, :, others].copy()
+            pad = members[None, :, others] == N
+            vals[np.broadcast_to(pad, vals.shape)] = big
+            mn = vals.min(-1)
+            w[:, :M, j] = np.where(mn == big, 0, mn)
+    W1, b1, W2, b2, W3, b3, al, be = unpack_params(params, T)
+    z = (Y < 0).astype(np.int64)
+    rounds = np.zeros(F, np.int64)
+    ok = np.zeros(F, bool)
+    live = np.ones(F, bool)
+    prev = [None] * F
+    trace = []
+    p = -(-N // G)
+    blocks = [(lo, min(N, lo + p)) for lo in range(0, N, p)]
+    t = 0
+    fr = np.arange(F)
+    while live.any():
+        idx = fr[live]
+        zp = np.concatenate([z[idx], np.zeros((idx.size, 1), np.int64)], 1)
+        s = zp[:, members].sum(-1) % 2                  # syndrome [F'][M]
+        zero = s.sum(1) == 0
+        ok[idx[zero]] = True
+        live[idx[zero]] = False
+        if t == T:
+            live[:] = False
+            break
+        idx = idx[~zero]
+        if idx.size == 0:
+            break
+        s = np.concatenate([s[~zero], np.zeros((idx.size, 1), np.int64)], 1)
+        sb = s[:, bm]                                    # [F'][N][dvm]
+        wb = w[idx][:, bm, bj]                           # [F'][N][dvm]
+        S = np.where(sb == 1, wb, -wb).sum(-1)
+        u = sb.sum(-1)
+        E = metric_t(a[idx], S, al[t], be[t])
+        kmax = min(k, p)
+        cand = np.full((idx.size, len(blocks), kmax), -1, np.int64)
+        score = np.full((idx.size, len(blocks), kmax), np.nan)
+        flip_n = np.full((idx.size, len(blocks)), -1, np.int64)
+        for b, (lo, hi) in enumerate(blocks):
+            kk = min(k, hi - lo)
+            order = np.argsort(-E[:, lo:hi], axis=1, kind="stable")[:, :kk] + lo   # ties: lower index
+            ai = np.take_along_axis(a[idx], order, 1)
+            Si = np.take_along_axis(S, order, 1)
+            ui = np.take_along_axis(u, order, 1)
+            x = features(ai.ravel(), Si.ravel(), ui.ravel(), t, T, A, dv, al, be)
+            sc, _ = forward(x, params, T)
+            sc = sc.reshape(idx.size, kk)
+            # the block's best score, ties to the lower bit index
+            best = np.zeros(idx.size, np.int64)
+            for j in range(1, kk):
+                sb_, ob_ = sc[np.arange(idx.size), best], order[np.arange(idx.size), best]
+                better = (sc[:, j] > sb_) | ((sc[:, j] == sb_) & (order[:, j] < ob_))
+                best = np.where(better, j, best)
+            bs = sc[np.arange(idx.size), best]
+            flip_n[:, b] = np.where(bs > 0, order[np.arange(idx.size), best], -1)
+            cand[:, b, :kk] = order
+            score[:, b, :kk] = sc
+        trace.append((idx.copy(), cand, score))
+        for q, f in enumerate(idx):
+            fl = flip_n[q][flip_n[q] >= 0]
+            if fl.size == 0 or (prev[f] is not None and np.array_equal(fl, prev[f])):
+                live[f] = False
+                continue
+            z[f, fl] ^= 1
+            prev[f] = fl
+            rounds[f] = t + 1
+        t += 1
+    return z, rounds, ok, trace
+
+
+def trace_of_frame(trace, f):
+    """Per round run by frame f: (candidates [G'][k'], scores [G'][k'])."""
+    out = []
+    for idx, cand, score in trace:
+        q = np.nonzero(idx == f)[0]
+        if q.size == 0:
+            break
+        out.append((cand[q[0]], score[q[0]]))
+    return out

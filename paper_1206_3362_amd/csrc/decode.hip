@@ -570,7 +570,7 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
                 const int flags = s.ctl[CTL_FLAGS];
                 if (!(a.flags & FWBF_FLAG_NO_CYCLE_EXIT)) {
                     if (!(flags & F_ANY)) {  // no flip: fixed point until K_max
-                        k = a.max_iter;
+                        k = (a.flags & FWBF_FLAG_EXECUTED_ROUNDS) ? k : a.max_iter;
                         break;
                     }
                     if (!(flags & F_DIFF)) {
@@ -581,7 +581,7 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
                                 const uint32_t n = s.win[u];
                                 if (n != NONE) atomicXor(&s.zw[n >> 5], 1u << (n & 31));
                             }
-                        k = a.max_iter;
+                        k = (a.flags & FWBF_FLAG_EXECUTED_ROUNDS) ? k : a.max_iter;
                         break;
                     }
                 }
@@ -615,7 +615,7 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
                 const int flags = s.ctl[CTL_FLAGS];
                 if (!(a.flags & FWBF_FLAG_NO_CYCLE_EXIT)) {
                     if (!(flags & F_ANY)) {  // no flip: fixed point until K_max
-                        k = a.max_iter;
+                        k = (a.flags & FWBF_FLAG_EXECUTED_ROUNDS) ? k : a.max_iter;
                         break;
                     }
                     if (!(flags & F_DIFF)) {
@@ -626,7 +626,7 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
                                 const uint32_t n = s.win[u];
                                 if (n != NONE) atomicXor(&s.zw[n >> 5], 1u << (n & 31));
                             }
-                        k = a.max_iter;
+                        k = (a.flags & FWBF_FLAG_EXECUTED_ROUNDS) ? k : a.max_iter;
                         break;
                     }
                 }
@@ -1106,6 +1106,8 @@ extern "C" int fwbf_decode(const fwbf_code *code, const fwbf_params *params, con
                              t.shift, nullptr, 0);
         if (rc != 0) return rc < 0 ? rc : FWBF_OK;
     }
+    if (params->flags & FWBF_FLAG_SPECIALISED_ONLY)
+        return fail(FWBF_E_UNSUPPORTED, "no specialised kernel takes these parameters");
     int dev = 0, cus = 0, blocks = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);

@@ -52,6 +52,7 @@ struct CycArgs {
     // 32-bit keys (integer metrics): block << (vb + pb) | metric << pb | pmask - pos
     int key32, vb, pb;
     int single, imwbf, max_iter, cycle_exit;
+    int exec_rounds;  // report the rounds run before a repeated state (diagnostic)
     float alpha;
     int aden, anum;
     uint32_t bias, zero_val;
@@ -387,7 +388,7 @@ __global__ __launch_bounds__(64) void cyclic_kernel(CycArgs a)
                 const bool anyf = __ballot(any) != 0, diff = __ballot(dif) != 0;
                 if (a.cycle_exit) {
                     if (!anyf) {  // no flip: fixed point until K_max
-                        k = a.max_iter;
+                        k = a.exec_rounds ? k : a.max_iter;
                         break;
                     }
                     if (!diff) {
@@ -398,7 +399,7 @@ __global__ __launch_bounds__(64) void cyclic_kernel(CycArgs a)
                                 const uint32_t n = prv[g];
                                 if (n != NONE) atomicXor(&zw[n >> 5], 1u << (n & 31));
                             }
-                        k = a.max_iter;
+                        k = a.exec_rounds ? k : a.max_iter;
                         break;
                     }
                 }
@@ -506,6 +507,7 @@ int try_cyclic_decode(const fwbf_code *c, const fwbf_params *p, const void *y, i
     a.imwbf = p->weights == FWBF_IMWBF;
     a.max_iter = p->max_iter;
     a.cycle_exit = !(p->flags & FWBF_FLAG_NO_CYCLE_EXIT);
+    a.exec_rounds = (p->flags & FWBF_FLAG_EXECUTED_ROUNDS) != 0;
     a.alpha = p->weights == FWBF_WBF ? 0.0f : p->alpha;
     a.aden = p->alpha_den;
     a.anum = p->weights == FWBF_WBF ? 0 : p->alpha_num;

@@ -50,6 +50,7 @@ struct FastArgs {
     int strided;  // block g = {n : n mod G = g}: bit n = pos G + g
     int p, L, logL, Geff, Lc;
     int single, imwbf, max_iter, cycle_exit, vec_ok;
+    int exec_rounds;  // report the rounds run before a repeated state (diagnostic)
     int aden, anum, idxb;
     uint32_t idxmask, bias, zero_val;
     // LDS offsets in bytes
@@ -315,14 +316,14 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                 prv = lead ? cur : prv;
                 if (a.cycle_exit) {
                     if (fmask == 0) {  // no flip: fixed point until K_max
-                        k = a.max_iter;
+                        k = a.exec_rounds ? k : a.max_iter;
                         break;
                     }
                     if (dmask == 0) {
                         // same flips as the round before: states alternate,
                         // z_{K_max} = z_k if K_max - k is even, else z_k ^ flips
                         if (((a.max_iter - k) & 1) && flip) atomicXor(&zw[n >> 5], 1u << (n & 31));
-                        k = a.max_iter;
+                        k = a.exec_rounds ? k : a.max_iter;
                         break;
                     }
                 }
@@ -502,6 +503,7 @@ int try_fast_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int
     a.imwbf = p->weights == FWBF_IMWBF;
     a.max_iter = p->max_iter;
     a.cycle_exit = !(p->flags & FWBF_FLAG_NO_CYCLE_EXIT);
+    a.exec_rounds = (p->flags & FWBF_FLAG_EXECUTED_ROUNDS) != 0;
     a.aden = p->alpha_den;
     a.anum = p->weights == FWBF_WBF ? 0 : p->alpha_num;
     const int64_t maxmag = p->dtype == FWBF_I8 ? 128 : 32768;

@@ -484,7 +484,9 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
                 x = pack4(fa, fe, fu, nbias[96 + t]);
             }
             const float score = net_score(net, x);
-            if (a.rec && lane < 32 && j < (uint32_t)NC) {
+            // every one of the 32 slots is written in each round run; slots
+            // j >= NC (no proposal) get valid = 0
+            if (a.rec && lane < 32) {
                 fwbf_record r;
                 r.S = (int16_t)cS;
                 r.a = (uint8_t)ca;
@@ -941,35 +943,60 @@ extern "C" int fwbf_decode_learned(const fwbf_code *code, const fwbf_params *pla
     return rc < 0 ? rc : FWBF_OK;
 }
 
-extern "C" int fwbf_scorer_grad(const fwbf_record *records_dev, int64_t n_tiles, const fwbf_learned_params *lp,
-                                const float *scorer_dev, float pos_weight, float *out_dev, float *scores_dev,
-                                float *workspace_dev, int64_t workspace_floats, void *stream)
+namespace fwbf {
+namespace {
+constexpr int GRAD_PARTS = 1024;  // workgroups of grad_kernel = partial gradient rows
+
+// Forward / backward over n_tiles tiles into `partial` (GRAD_PARTS rows of
+// P + 2 floats, every entry written by the kernel), then the fixed-order
+// reduction into out_dev.
+int launch_grad(const fwbf_record *records_dev, int64_t n_tiles, const fwbf_learned_params *lp,
+                const float *scorer_dev, float pos_weight, float *out_dev, float *scores_dev, float *partial,
+                hipStream_t st)
 {
-    int rc = check_lp(lp);
-    if (rc) return rc;
-    if (n_tiles < 0) return fail(FWBF_E_INVALID, "n_tiles must be >= 0");
-    if (!scorer_dev || (!out_dev && !scores_dev)) return fail(FWBF_E_INVALID, "null buffer");
     const int P = 1249 + 2 * lp->rounds;
-    const int parts = 1024;
-    if (out_dev && (!workspace_dev || workspace_floats < (int64_t)parts * (P + 2)))
-        return fail(FWBF_E_INVALID, "workspace too small (need 1024 * (P + 2) floats)");
-    if (n_tiles > 0 && !records_dev) return fail(FWBF_E_INVALID, "null records");
     GradArgs g;
     g.rec = records_dev; g.n_tiles = n_tiles; g.params = scorer_dev;
     g.pos_weight = pos_weight; g.A = lp->scale; g.dv = 3.0f;
     g.T = lp->rounds; g.P = P;
-    g.partial = workspace_dev; g.scores = scores_dev; g.backward = out_dev != nullptr;
-    hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(grad_kernel, dim3(parts), dim3(64), 0, st, g);
+    g.partial = partial; g.scores = scores_dev; g.backward = out_dev != nullptr;
+    hipLaunchKernelGGL(grad_kernel, dim3(GRAD_PARTS), dim3(64), 0, st, g);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "scorer gradient launch");
     if (out_dev) {
-        hipLaunchKernelGGL(reduce_kernel, dim3((P + 2 + 63) / 64), dim3(64 * RED_W), 0, st, workspace_dev, parts, P,
+        hipLaunchKernelGGL(reduce_kernel, dim3((P + 2 + 63) / 64), dim3(64 * RED_W), 0, st, partial, GRAD_PARTS, P,
                            out_dev);
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "gradient reduction launch");
     }
     return FWBF_OK;
+}
+
+int check_grad_args(const fwbf_record *records_dev, int64_t n_tiles, const fwbf_learned_params *lp,
+                    const float *scorer_dev, const float *out_dev, const float *scores_dev)
+{
+    int rc = check_lp(lp);
+    if (rc) return rc;
+    if (n_tiles < 0) return fail(FWBF_E_INVALID, "n_tiles must be >= 0");
+    if (!scorer_dev || (!out_dev && !scores_dev)) return fail(FWBF_E_INVALID, "null buffer");
+    if (n_tiles > 0 && !records_dev) return fail(FWBF_E_INVALID, "null records");
+    return FWBF_OK;
+}
+
+}  // namespace
+}  // namespace fwbf
+
+extern "C" int fwbf_scorer_grad(const fwbf_record *records_dev, int64_t n_tiles, const fwbf_learned_params *lp,
+                                const float *scorer_dev, float pos_weight, float *out_dev, float *scores_dev,
+                                float *workspace_dev, int64_t workspace_floats, void *stream)
+{
+    int rc = check_grad_args(records_dev, n_tiles, lp, scorer_dev, out_dev, scores_dev);
+    if (rc) return rc;
+    const int P = 1249 + 2 * lp->rounds;
+    if (out_dev && (!workspace_dev || workspace_floats < (int64_t)GRAD_PARTS * (P + 2)))
+        return fail(FWBF_E_INVALID, "workspace too small (need 1024 * (P + 2) floats)");
+    return launch_grad(records_dev, n_tiles, lp, scorer_dev, pos_weight, out_dev, scores_dev, workspace_dev,
+                       (hipStream_t)stream);
 }
 
 extern "C" int fwbf_adam(float *params_dev, const float *grad_dev, float *m_dev, float *v_dev, int P, int step,

@@ -1,7 +1,9 @@
 // Eb/N0 sweep captured in a HIP graph: for every noise level, frame
 // generation (channel kernel) -> decoding -> error accounting, recorded once
 // on a capture stream and replayed with one launch.  Counters are cleared by
-// a fill kernel inside the graph (no memset nodes).
+// a fill kernel inside the graph (no memset nodes).  Every point has its own
+// frame and output buffers, so after a replay each point's frames and
+// decisions can be read back (fwbf_sweep_outputs).
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -73,10 +75,11 @@ extern "C" int fwbf_sweep_create(const fwbf_code *code, const fwbf_params *param
     const int NW = (code->N + 31) / 32;
     const int64_t nc = (int64_t)n_points * (7 + params->max_iter);
     hipError_t e = hipGetDevice(&s->device);
-    if (e == hipSuccess) e = hipMalloc(&s->y, (size_t)s->F * code->N * s->esz);
-    if (e == hipSuccess) e = hipMalloc((void **)&s->z, (size_t)s->F * NW * 4);
-    if (e == hipSuccess) e = hipMalloc((void **)&s->iters, (size_t)s->F * 4);
-    if (e == hipSuccess) e = hipMalloc((void **)&s->ok, (size_t)s->F);
+    const size_t PF = (size_t)n_points * s->F;
+    if (e == hipSuccess) e = hipMalloc(&s->y, PF * code->N * s->esz);
+    if (e == hipSuccess) e = hipMalloc((void **)&s->z, PF * NW * 4);
+    if (e == hipSuccess) e = hipMalloc((void **)&s->iters, PF * 4);
+    if (e == hipSuccess) e = hipMalloc((void **)&s->ok, PF);
     if (e == hipSuccess) e = hipMalloc((void **)&s->counters, (size_t)nc * 8);
     if (e != hipSuccess) {
         release(s);
@@ -94,11 +97,16 @@ extern "C" int fwbf_sweep_create(const fwbf_code *code, const fwbf_params *param
     hipLaunchKernelGGL(fill_i64, dim3(1), dim3(256), 0, cs, s->counters, nc);
     rc = hipGetLastError() == hipSuccess ? FWBF_OK : fail(FWBF_E_HIP, "fill launch");
     for (int pnt = 0; pnt < n_points && rc == FWBF_OK; pnt++) {
+        const size_t f0 = (size_t)pnt * s->F;
+        void *y = (char *)s->y + f0 * code->N * s->esz;
+        uint32_t *z = s->z + f0 * NW;
+        int32_t *it = s->iters + f0;
+        uint8_t *ok = s->ok + f0;
         rc = fwbf_channel(code->N, s->F, 0, pool_dev, pool_n, seed, (uint32_t)pnt, sigma_host[pnt], nullptr, scale,
-                          params->dtype, s->y, code->N, cs);
-        if (rc == FWBF_OK) rc = fwbf_decode(code, params, s->y, s->F, code->N, s->z, s->iters, s->ok, cs);
+                          params->dtype, y, code->N, cs);
+        if (rc == FWBF_OK) rc = fwbf_decode(code, params, y, s->F, code->N, z, it, ok, cs);
         if (rc == FWBF_OK)
-            rc = fwbf_count(code->N, s->F, 0, s->z, pool_dev, pool_n, s->iters, s->ok, params->max_iter,
+            rc = fwbf_count(code->N, s->F, 0, z, pool_dev, pool_n, it, ok, params->max_iter,
                             s->counters + (int64_t)pnt * (7 + params->max_iter), cs);
     }
     hipGraph_t g = nullptr;
@@ -131,6 +139,23 @@ extern "C" int fwbf_sweep_counters(fwbf_sweep *s, int64_t *host, void *stream)
     hipError_t e = hipMemcpyAsync(host, s->counters, bytes, hipMemcpyDeviceToHost, (hipStream_t)stream);
     if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
     return e == hipSuccess ? FWBF_OK : hip_fail(e, "counter copy");
+}
+
+extern "C" int fwbf_sweep_outputs(const fwbf_sweep *s, int point, void *y_dev, uint32_t *z_dev, int32_t *iters_dev,
+                                  uint8_t *ok_dev, void *stream)
+{
+    if (!s) return fail(FWBF_E_INVALID, "null sweep");
+    if (point < 0 || point >= s->n_points) return fail(FWBF_E_INVALID, "point out of range");
+    const size_t f0 = (size_t)point * s->F, F = (size_t)s->F;
+    const size_t NW = (size_t)(s->N + 31) / 32;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (y_dev)
+        e = hipMemcpyAsync(y_dev, (const char *)s->y + f0 * s->N * s->esz, F * s->N * s->esz, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && z_dev) e = hipMemcpyAsync(z_dev, s->z + f0 * NW, F * NW * 4, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && iters_dev) e = hipMemcpyAsync(iters_dev, s->iters + f0, F * 4, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && ok_dev) e = hipMemcpyAsync(ok_dev, s->ok + f0, F, hipMemcpyDeviceToDevice, st);
+    return e == hipSuccess ? FWBF_OK : hip_fail(e, "sweep output copy");
 }
 
 extern "C" void fwbf_sweep_free(fwbf_sweep *s) { release(s); }

@@ -22,6 +22,8 @@ WBF, MWBF, IMWBF = 0, 1, 2
 GROUPS, SINGLE, TOPL, STRIDED = 0, 1, 2, 3
 FLAG_NO_CYCLE_EXIT = 1
 FLAG_GENERIC_KERNEL = 2
+FLAG_SPECIALISED_ONLY = 4
+FLAG_EXECUTED_ROUNDS = 8
 
 OK, E_INVALID, E_PARSE, E_GIRTH, E_UNSUPPORTED, E_NOMEM, E_HIP = 0, -1, -2, -3, -4, -5, -6
 _NAMES = {-1: "E_INVALID", -2: "E_PARSE", -3: "E_GIRTH", -4: "E_UNSUPPORTED", -5: "E_NOMEM",
@@ -34,7 +36,7 @@ EXPORTS = [
     "fwbf_encode", "fwbf_channel", "fwbf_decode", "fwbf_count", "fwbf_last_error", "fwbf_version",
     "fwbf_scorer_size", "fwbf_decode_learned", "fwbf_scorer_grad", "fwbf_adam",
     "fwbf_decode_batched", "fwbf_sweep_create", "fwbf_sweep_launch", "fwbf_sweep_counters",
-    "fwbf_sweep_free", "fwbf_decode_minsum",
+    "fwbf_sweep_free", "fwbf_decode_minsum", "fwbf_sweep_outputs",
 ]
 
 
@@ -116,6 +118,7 @@ def lib():
                                         C.POINTER(vp)]
         L.fwbf_sweep_launch.argtypes = [vp, vp]
         L.fwbf_sweep_counters.argtypes = [vp, vp, vp]
+        L.fwbf_sweep_outputs.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         L.fwbf_sweep_free.argtypes = [vp]
         L.fwbf_sweep_free.restype = None
         _lib = L
@@ -417,6 +420,7 @@ class Sweep:
                  seed: int = 1, scale: float = 1.0):
         self.code, self.params = code, params
         self.n_points = len(sigmas)
+        self.frames_per_point = frames_per_point
         self._p = params.c()
         sig = np.ascontiguousarray(sigmas, np.float32)
         h = C.c_void_p()
@@ -434,6 +438,19 @@ class Sweep:
         out = np.zeros((self.n_points, 7 + self.params.max_iter), np.int64)
         _check(lib().fwbf_sweep_counters(self._h, _np_ptr(out), _stream()))
         return out
+
+    def outputs(self, point: int):
+        """Point `point`'s frames and the outputs of the last replay, copied
+        into new device tensors: (y [F][N], z [F][ceil(N/32)], iters, ok)."""
+        torch = _torch()
+        F, N = self.frames_per_point, self.code.N
+        dt = {F32: torch.float32, I8: torch.int8, I16: torch.int16}[self.params.dtype]
+        y = torch.empty((F, N), dtype=dt, device="cuda")
+        z = torch.empty((F, (N + 31) // 32), dtype=torch.int32, device="cuda")
+        it = torch.empty(F, dtype=torch.int32, device="cuda")
+        ok = torch.empty(F, dtype=torch.uint8, device="cuda")
+        _check(lib().fwbf_sweep_outputs(self._h, point, _ptr(y), _ptr(z), _ptr(it), _ptr(ok), _stream()))
+        return y, z, it, ok
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -135,6 +135,94 @@ def test_specialised_and_generic_kernels_agree(codes, dt):
             assert_same(fast, oracle_decode(o, y, max_iter=80, **sel, **v), f"oracle {sel} {v}")
 
 
+RAGGED = {"n1008": (4.0, [5, 10, 11, 37, 50, 61]), "n186": (3.0, [4, 5, 7])}
+
+
+@pytest.mark.parametrize("name", ["n1008", "n186"])
+@pytest.mark.parametrize("dt", [np.int8, np.int16])
+def test_specialised_kernel_ragged_blocks(codes, name, dt):
+    """The one-wave kernel that the benchmark times, pinned with
+    FLAG_SPECIALISED_ONLY, on block counts that do not divide N: a short
+    last block (the null-metric padding of footnote 1), fewer blocks than G
+    where ceil(N/p) < G (N = 1008: G = 37 gives 36 blocks of 28, G = 50 gives
+    48 of 21), and strided classes of unequal size; every weight variant,
+    against the oracle.  N = 186 adds every single-error pattern (one round
+    for any blocks, by the closed form)."""
+    g, o = codes(name)
+    eb, Gs = RAGGED[name]
+    F = 512
+    y = synth.awgn_frames(g.N, F, synth.sigma_for(eb, g.rate), 61, None, dt)
+    if name == "n186":
+        A = 16 if dt == np.int8 else 256
+        y = np.concatenate([y, synth.error_pattern_frames(g.N, [[e] for e in range(g.N)], A, dt)])
+    for G in Gs:
+        for sel in (0, 3):
+            for v in VARIANTS:
+                kw = dict(select=sel, groups=G, max_iter=60, **v)
+                a = gpu_decode(g, y, flags=4, **kw)
+                assert_same(a, oracle_decode(o, y, **kw), f"{name} {dt} G={G} select={sel} {v}")
+                if name == "n186":
+                    assert (a[1][F:] == 1).all() and (a[2][F:] == 1).all()
+
+
+def test_specialised_only_flag_refuses_other_shapes(codes):
+    """G = 100 on N = 1008 (92 blocks of 11) does not fit one wave's lanes:
+    with FLAG_SPECIALISED_ONLY the call fails and enqueues nothing."""
+    from paper_1206_3362_amd import fwbf
+    g, o = codes("n1008")
+    y = torch.zeros((4, g.N), dtype=torch.int8, device="cuda")
+    with pytest.raises(fwbf.FwbfError, match="E_UNSUPPORTED"):
+        fwbf.decode(g, y, fwbf.DecodeParams(dtype=fwbf.I8, groups=100, flags=4))
+    with pytest.raises(fwbf.FwbfError, match="E_UNSUPPORTED"):
+        fwbf.decode(g, y.float(), fwbf.DecodeParams(dtype=fwbf.F32, groups=8, flags=4))
+
+
+def _executed_rounds(ocode, y, **kw):
+    """Rounds run before the decoder's state repeats, from the oracle's
+    literal trace: the first round with no flip or with the previous
+    round's flips; a frame that never repeats runs all its rounds."""
+    out = []
+    for f in range(y.shape[0]):
+        tr = O.decode_trace(ocode, y[f], **kw)
+        fl = [sorted(x.tolist()) for x in tr["flips"]]
+        ex = tr["iters"]
+        for r in range(len(fl)):
+            if not fl[r] or (r > 0 and fl[r] == fl[r - 1]):
+                ex = r
+                break
+        out.append(ex)
+    return np.array(out)
+
+
+def test_executed_rounds_flag(codes, eg):
+    """FLAG_EXECUTED_ROUNDS reports the rounds run before the state repeats
+    (the work the repeated-state shortcut leaves) and changes nothing else:
+    the specialised, general and cyclic kernels against the oracle's trace."""
+    cases = [("n1008", np.int8, 4.0, dict(groups=8, max_iter=100), 0),
+             ("n1008", np.int8, 4.0, dict(groups=8, max_iter=100), 2),
+             ("n1008", np.int16, 3.0, dict(select=1, max_iter=70), 0),
+             ("n186", np.float32, 3.0, dict(groups=6, max_iter=50, weights=0), 0)]
+    for name, dt, eb, kw, extra in cases:
+        g, o = codes(name)
+        y = synth.awgn_frames(g.N, 192, synth.sigma_for(eb, g.rate), 71, None, dt)
+        base = gpu_decode(g, y, flags=extra, **kw)
+        ex = gpu_decode(g, y, flags=extra | 8, **kw)
+        assert np.array_equal(base[0], ex[0]) and np.array_equal(base[2], ex[2])
+        okm = base[2] == 1
+        assert np.array_equal(base[1][okm], ex[1][okm])
+        m = dict(kw)
+        m["G"] = m.pop("groups", 8)
+        want = _executed_rounds(o, y, **m)
+        assert np.array_equal(ex[1], want), (name, dt, kw, extra)
+        assert (ex[1] < base[1]).any()
+    ge, oe = eg(4)
+    y = synth.awgn_frames(ge.N, 128, synth.sigma_for(3.0, ge.rate), 72, None, np.float32)
+    base = gpu_decode(ge, y, groups=16, max_iter=30, alpha=1.0)
+    ex = gpu_decode(ge, y, groups=16, max_iter=30, alpha=1.0, flags=8)
+    assert np.array_equal(base[0], ex[0]) and np.array_equal(base[2], ex[2])
+    assert np.array_equal(ex[1], _executed_rounds(oe, y, G=16, max_iter=30, alpha=1.0))
+
+
 def test_degenerate_calls(codes):
     from paper_1206_3362_amd import fwbf
     g, o = codes("n186")

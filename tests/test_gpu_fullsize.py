@@ -172,3 +172,35 @@ def test_eg1023_full_size(dt):
     torch.cuda.synchronize()
     check_sampled(oc, y, z, it, ok, sample_rows(F, 256, 4), f"eg1023 {DT_OF[dt].__name__} 2^16", **kw)
     check_properties(oc, z, it, ok, 10, f"eg1023 {DT_OF[dt].__name__} 2^16")
+
+
+def test_sweep_graph_every_point_full_size():
+    """The Eb/N0 sweep as the benchmark runs it: one HIP graph over the nine
+    points 2.0 ... 6.0 dB of the N = 1008 int8 code, 2^20 frames per point,
+    G = 8, K_max = 100.  After one replay every point's frames and outputs
+    are read back: the oracle decodes 256 sampled frames per point, every
+    frame is checked against the flag and K_max properties, and the graph's
+    counters equal a recount of the outputs."""
+    need_gpu()
+    from paper_1206_3362_amd import fwbf
+    code = fwbf.Code.from_seed(3, 6, 168, 2)
+    oc = O.Code.from_seed(*CODES["n1008"])
+    N, F = code.N, 1 << 20
+    pool = torch.from_numpy(code.encode(1001, 0, 1024).view(np.int32)).cuda()
+    ebs = np.arange(2.0, 6.01, 0.5)
+    sw = fwbf.Sweep(code, fwbf.DecodeParams(dtype=fwbf.I8, groups=8, max_iter=100),
+                    synth.sigma_for(ebs, code.rate), F, pool=pool, seed=1100, scale=16.0)
+    sw.launch()
+    c = sw.counters()
+    for k, eb in enumerate(ebs):
+        y, z, it, ok = sw.outputs(k)
+        torch.cuda.synchronize()
+        what = f"sweep point {eb:.1f} dB"
+        check_sampled(oc, y, z, it, ok, sample_rows(F, 256, 100 + k), what, weights=2, groups=8,
+                      max_iter=100, alpha_num=1, alpha_den=5)
+        check_properties(oc, z, it, ok, 100, what)
+        r = fwbf.count(N, z, pool, 0, it, ok, 100)
+        assert (r["bit_err"], r["frame_err"], r["undetected"], r["iter_sum"], r["frames"]) == \
+            tuple(int(v) for v in c[k, :5]), what
+        del y, z, it, ok
+    del sw

@@ -160,3 +160,24 @@ def test_adam_two_steps_by_hand_and_eps_placement():
     assert abs(p[0] + 0.2) < 1e-15 and m[0] == -0.25 and v[0] == 0.75
     p, _, _ = R.adam_step([0.0], [1e-8], [0.0], [0.0], 1, 0.5, 0.9, 0.999, 1e-8)
     assert abs(p[0] + 0.25) < 1e-12
+
+
+@pytest.mark.parametrize("mbnbZ,G,k,T", [((3, 6, 31, 1), 6, 4, 8), ((3, 6, 31, 1), 7, 1, 12),
+                                          ((3, 6, 168, 2), 32, 1, 16)])
+def test_batched_learned_pass_equals_per_frame(mbnbZ, G, k, T):
+    """The frame-batched learned pass takes the same steps as the literal
+    one-frame loop: identical bits, rounds, flags and candidate lists."""
+    from paper_1206_3362_amd import synth
+    code = O.Code.from_seed(*mbnbZ)
+    rng = np.random.default_rng(G + k)
+    p = rng.normal(0, 0.75, R.n_params(T))
+    p[-2 * T:-T] = 0.2
+    p[-T:] = 1.0
+    y = synth.awgn_frames(code.N, 24, synth.sigma_for(4.5, 0.5), 17, None, np.int8)
+    z, r, ok, tr = R.learned_decode_batch(code, y, p, T, G, k, 16.0, 3)
+    adj = R._adjacency(code)
+    for f in range(y.shape[0]):
+        zf, rf, okf, recs = R.learned_decode_frame(code, y[f], p, T, G, k, 16.0, 3, adj)
+        assert (z[f] == zf).all() and r[f] == rf and ok[f] == okf
+        cands = [int(n) for c, _ in R.trace_of_frame(tr, f) for blk in c for n in blk if n >= 0]
+        assert cands == [rc[4] for rc in recs]
