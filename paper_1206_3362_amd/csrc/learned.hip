@@ -1003,7 +1003,10 @@ extern "C" int fwbf_adam(float *params_dev, const float *grad_dev, float *m_dev,
                          float lr, float beta1, float beta2, float eps, void *stream)
 {
     if (!params_dev || !grad_dev || !m_dev || !v_dev || P < 1 || step < 1) return fail(FWBF_E_INVALID, "invalid argument");
-    const float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
+    // bias corrections 1 - beta^step of the single-precision betas, formed
+    // in double: in float, 1 - powf(0.999f, t) loses ~1e-5 to cancellation
+    const float c1 = (float)(1.0 - pow((double)beta1, (double)step));
+    const float c2 = (float)(1.0 - pow((double)beta2, (double)step));
     hipLaunchKernelGGL(adam_kernel, dim3((P + 255) / 256), dim3(256), 0, (hipStream_t)stream, params_dev, grad_dev,
                        m_dev, v_dev, P, lr, beta1, beta2, eps, c1, c2);
     hipError_t e = hipGetLastError();
