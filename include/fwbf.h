@@ -213,6 +213,26 @@ typedef struct {
 int fwbf_decode_batched(const fwbf_batch_item *items, int n_items, int threads_per_frame, int blocks_per_cu,
                         void *workspace_dev, size_t workspace_bytes, void *stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Decodes as
+ * fwbf_decode_batched does (same kernel, same results, same argument
+ * checks), but calls no hipMalloc, hipFree or other allocating routine:
+ *  - the ticket counter lives in a library-owned device array of 256 bytes
+ *    (one copy per device, held until the process ends); the call needs 8
+ *    of them whatever the batch, so no input size can exceed it;
+ *  - the first call on a device looks up that device's copy
+ *    (hipGetSymbolAddress) with the device current;
+ *  - every item's code must already have its tables on the current device,
+ *    uploaded by an earlier allocating call with that code there
+ *    (fwbf_decode or fwbf_decode_batched); otherwise FWBF_E_INVALID and
+ *    nothing is enqueued.
+ * The counter is cleared by a kernel at the start of each call (no memset
+ * node).  All calls on one device share its array: calls that overlap on
+ * one device (other streams or host threads) race on the counter and must
+ * be serialised by the caller. */
+int fwbf_decode_batched_noalloc(const fwbf_batch_item *items, int n_items, int threads_per_frame,
+                                int blocks_per_cu, void *stream);
+
 /* ---- error accounting (Section V) --------------------------------------- */
 
 /* Adds, for frames f0 .. f0+F-1 against pool row (f % pool_n) (pool NULL:

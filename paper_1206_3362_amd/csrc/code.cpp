@@ -262,6 +262,21 @@ int ensure_rref(fwbf_code *c)
     return FWBF_OK;
 }
 
+int device_tables_resident(const fwbf_code *c, DeviceTables *out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    fwbf_code *m = const_cast<fwbf_code *>(c);
+    std::lock_guard<std::mutex> lk(m->mu);
+    auto it = m->dev.find(dev);
+    if (it == m->dev.end())
+        return fail(FWBF_E_INVALID, "code tables are not on this device yet: decode with this code once "
+                                    "(fwbf_decode or fwbf_decode_batched) before a no-allocation call");
+    *out = it->second;
+    return FWBF_OK;
+}
+
 int device_tables(fwbf_code *c, DeviceTables *out)
 {
     int dev = 0;

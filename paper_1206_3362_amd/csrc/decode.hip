@@ -1209,12 +1209,25 @@ hipError_t occupancy_batched(int T, int lds, int *blocks)
 }  // namespace
 }  // namespace fwbf
 
-extern "C" int fwbf_decode_batched(const fwbf_batch_item *items, int n_items, int threads_per_frame,
-                                   int blocks_per_cu, void *workspace_dev, size_t workspace_bytes, void *stream)
+// Scratch of the no-allocation entry point: the ticket counter lives here
+// instead of in a caller workspace.  Each device holds its own copy until
+// the process ends.  In host code `scratch` only stands for the symbol; its
+// device address comes from hipGetSymbolAddress, looked up once per device.
+constexpr size_t SCRATCH_BYTES = 256;
+constexpr size_t SCRATCH_NEED = sizeof(unsigned long long);  // one counter, whatever the batch
+static_assert(SCRATCH_NEED <= SCRATCH_BYTES, "scratch too small for the ticket counter");
+static __device__ __align__(256) unsigned long long scratch[SCRATCH_BYTES / sizeof(unsigned long long)];
+
+namespace fwbf {
+namespace {
+// The batched launch behind both entry points.  `counter` is the ticket
+// counter (device memory, cleared here by a kernel).  With resident_only,
+// the code tables must already be on the device (nothing is allocated).
+int batched_impl(const fwbf_batch_item *items, int n_items, int threads_per_frame, int blocks_per_cu,
+                 unsigned long long *counter, void *stream, bool resident_only)
 {
     if (!items || n_items < 1 || n_items > MAX_JOBS)
         return fail(FWBF_E_INVALID, "n_items must be in [1, 8]");
-    if (!workspace_dev || workspace_bytes < 256) return fail(FWBF_E_INVALID, "workspace must hold 256 bytes");
     if (blocks_per_cu < 0) return fail(FWBF_E_INVALID, "blocks_per_cu must be >= 0");
     const int dtype = items[0].params ? items[0].params->dtype : -1;
     int T = threads_per_frame;
@@ -1260,7 +1273,8 @@ extern "C" int fwbf_decode_batched(const fwbf_batch_item *items, int n_items, in
             b.lds_job[i] = b.job[i].lds_bytes;
             b.chunk[i] = b.wave[i] ? 4 * (T / 64) : 2;
             DeviceTables tb;
-            const int rc = device_tables(const_cast<fwbf_code *>(it.code), &tb);
+            const int rc = resident_only ? device_tables_resident(it.code, &tb)
+                                         : device_tables(const_cast<fwbf_code *>(it.code), &tb);
             if (rc) return rc;
             DecodeArgs &a = b.job[i];
             a.y = it.y_dev; a.F = it.F; a.stride = it.y_stride;
@@ -1304,7 +1318,7 @@ extern "C" int fwbf_decode_batched(const fwbf_batch_item *items, int n_items, in
             blocks = blocks2;
         }
     }
-    b.counter = (unsigned long long *)workspace_dev;
+    b.counter = counter;
     if (blocks < 1) return fail(FWBF_E_UNSUPPORTED, "batched kernel does not fit on a compute unit");
     if (blocks_per_cu > 0) blocks = std::min(blocks, blocks_per_cu);
     const int64_t grid = std::min<int64_t>(b.cbase[n_items], (int64_t)blocks * cus);
@@ -1315,4 +1329,45 @@ extern "C" int fwbf_decode_batched(const fwbf_batch_item *items, int n_items, in
             : dtype == FWBF_I8 ? launch_batched<FWBF_I8>(T, b, lds, (int)grid, st)
                                : launch_batched<FWBF_I16>(T, b, lds, (int)grid, st);
     return e == hipSuccess ? FWBF_OK : hip_fail(e, "batched decode launch");
+}
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_dev[MAX_DEVICES];  // per device: address of that device's copy
+
+int scratch_ptr(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(FWBF_E_UNSUPPORTED, "device index above 63");
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(FWBF_E_HIP, "hipGetSymbolAddress(scratch) returned null");
+        scratch_dev[dev] = ptr;
+    }
+    *out = scratch_dev[dev];
+    return FWBF_OK;
+}
+}  // namespace
+}  // namespace fwbf
+
+extern "C" int fwbf_decode_batched(const fwbf_batch_item *items, int n_items, int threads_per_frame,
+                                   int blocks_per_cu, void *workspace_dev, size_t workspace_bytes, void *stream)
+{
+    if (!workspace_dev || workspace_bytes < 256) return fail(FWBF_E_INVALID, "workspace must hold 256 bytes");
+    return batched_impl(items, n_items, threads_per_frame, blocks_per_cu, (unsigned long long *)workspace_dev,
+                        stream, false);
+}
+
+extern "C" int fwbf_decode_batched_noalloc(const fwbf_batch_item *items, int n_items, int threads_per_frame,
+                                           int blocks_per_cu, void *stream)
+{
+    void *ptr = nullptr;
+    const int rc = scratch_ptr(&ptr);
+    if (rc) return rc;
+    return batched_impl(items, n_items, threads_per_frame, blocks_per_cu, (unsigned long long *)ptr, stream, true);
 }

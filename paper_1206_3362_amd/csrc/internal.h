@@ -59,5 +59,8 @@ namespace fwbf {
 // Returns the device tables of `code` on the current device (uploaded on
 // first use; synchronous upload, done once per code and device).
 int device_tables(fwbf_code *code, DeviceTables *out);
+// The same tables only if already uploaded to the current device (never
+// allocates); FWBF_E_INVALID otherwise.
+int device_tables_resident(const fwbf_code *code, DeviceTables *out);
 int ensure_rref(fwbf_code *code);
 }  // namespace fwbf

@@ -36,7 +36,7 @@ EXPORTS = [
     "fwbf_encode", "fwbf_channel", "fwbf_decode", "fwbf_count", "fwbf_last_error", "fwbf_version",
     "fwbf_scorer_size", "fwbf_decode_learned", "fwbf_scorer_grad", "fwbf_adam",
     "fwbf_decode_batched", "fwbf_sweep_create", "fwbf_sweep_launch", "fwbf_sweep_counters",
-    "fwbf_sweep_free", "fwbf_decode_minsum", "fwbf_sweep_outputs",
+    "fwbf_sweep_free", "fwbf_decode_minsum", "fwbf_sweep_outputs", "fwbf_decode_batched_noalloc",
 ]
 
 
@@ -114,6 +114,7 @@ def lib():
         L.fwbf_adam.argtypes = [vp, vp, vp, vp, i32, i32, C.c_float, C.c_float, C.c_float, C.c_float,
                                 vp]
         L.fwbf_decode_batched.argtypes = [vp, i32, i32, i32, vp, C.c_size_t, vp]
+        L.fwbf_decode_batched_noalloc.argtypes = [vp, i32, i32, i32, vp]
         L.fwbf_sweep_create.argtypes = [vp, C.POINTER(Params), vp, i32, i64, vp, i64, u64, C.c_float,
                                         C.POINTER(vp)]
         L.fwbf_sweep_launch.argtypes = [vp, vp]
@@ -411,6 +412,21 @@ def decode_batched(jobs, threads_per_frame: int = 0, blocks_per_cu: int = 0, wor
     _check(lib().fwbf_decode_batched(arr, len(items), threads_per_frame, blocks_per_cu,
                                      _ptr(workspace), workspace.numel() * 4, _stream()))
     return outs
+
+
+def decode_batched_noalloc(jobs, threads_per_frame: int = 0, blocks_per_cu: int = 0):
+    """jobs: list of (code, y, DecodeParams, z, iters, ok) with caller-made
+    output tensors.  The library call allocates nothing (its ticket counter
+    is a library-owned device array); each code must have been decoded on
+    this device before."""
+    keep, items = [], []
+    for code, y, params, z, it, ok in jobs:
+        pc = params.c()
+        keep.append(pc)
+        items.append(BatchItem(code._h.value, C.addressof(pc), y.data_ptr(), y.shape[0], y.stride(0),
+                               z.data_ptr(), it.data_ptr(), ok.data_ptr()))
+    arr = (BatchItem * len(items))(*items)
+    _check(lib().fwbf_decode_batched_noalloc(arr, len(items), threads_per_frame, blocks_per_cu, _stream()))
 
 
 class Sweep:
