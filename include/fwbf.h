@@ -289,33 +289,46 @@ void fwbf_sweep_free(fwbf_sweep *sweep);
  * beta[rounds]. */
 typedef struct {
     int32_t rounds; /* 1..64 */
-    int32_t groups; /* blocks of the learned pass; groups * topk <= 32 */
+    int32_t groups; /* blocks of the learned pass; groups * topk <= 512 */
     int32_t topk;   /* proposals per block: 1, 2 or 4 */
-    float scale;    /* fixed-point scale of y (16 for the int8 inputs) */
+    float scale;    /* fixed-point scale of y (16 for int8, 256 for int16 inputs) */
 } fwbf_learned_params;
 
+/* Proposal slots per round in the record layout: 32 * ceil(groups * topk /
+ * 32), i.e. whole tiles of 32 (one tile when groups * topk <= 32). */
+#define FWBF_RECORD_SLOTS(groups, topk) (32 * (((groups) * (topk) + 31) / 32))
+
 /* One scored proposal, emitted by fwbf_decode_learned for training:
- * records[frame][round][slot], slot = block * topk + rank (32 slots). */
+ * records[frame][round][slot], slot = block * topk + rank, with
+ * FWBF_RECORD_SLOTS(groups, topk) slots per round (12 bytes each). */
 typedef struct {
-    int16_t S;      /* check sum S_n of eq. (1) when scored */
-    uint8_t a;      /* |y_n| */
+    int32_t S;      /* check sum S_n of eq. (1) when scored */
+    uint16_t a;     /* |y_n| */
+    uint16_t n;     /* bit index (codes with N <= 65536) */
     uint8_t u;      /* unsatisfied checks of bit n */
     uint8_t label;  /* z_n xor c_n when scored: 1 if the bit is wrong */
     uint8_t valid;  /* 0 for empty slots and rounds not run */
-    uint16_t n;     /* bit index */
+    uint8_t pad;
 } fwbf_record;
 
 /* Number of scorer parameters for `rounds` rounds (or a negative error). */
 int fwbf_scorer_size(int rounds);
 
-/* Learned decoding of int8 frames on a full (3,6) base, then plain FWBF
- * (params `plain`: FWBF_GROUPS, int8) from the original y for every frame
- * whose syndrome is still nonzero; such frames report the learned rounds
- * plus the plain rounds.  Outputs as fwbf_decode; learned_ok_dev (optional,
- * F bytes) receives 1 for frames decoded by the learned pass alone.
- * records_dev (optional, F * rounds * 32 records) receives the proposals;
- * labels compare with pool_dev row ((f0 + f) % pool_n) (NULL: all-zero
- * codeword).  scorer_dev: device float32 parameters, read only. */
+/* Learned decoding, then plain FWBF (params `plain`: FWBF_GROUPS, same
+ * dtype) from the original y for every frame whose syndrome is still
+ * nonzero; such frames report the learned rounds plus the plain rounds.
+ * Codes: a full base (no zero blocks) of single circulant shifts with column
+ * weight 3 and N <= 65536; inputs int8 or int16 (plain->dtype).  int8 frames
+ * of (3,6) codes whose proposals fit one tile (groups * topk <= 32) run one
+ * frame per wavefront; every other case (and any call with
+ * FWBF_FLAG_GENERIC_KERNEL in plain->flags) runs one frame per workgroup of
+ * 1024 threads, with groups * topk <= 512 and the frame state within
+ * 160 KiB of LDS (N = 32400 fits).  Outputs as fwbf_decode; learned_ok_dev
+ * (optional, F bytes) receives 1 for frames decoded by the learned pass
+ * alone.  records_dev (optional, F * rounds * FWBF_RECORD_SLOTS(groups,
+ * topk) records) receives the proposals; labels compare with pool_dev row
+ * ((f0 + f) % pool_n) (NULL: all-zero codeword).  scorer_dev: device
+ * float32 parameters, read only. */
 int fwbf_decode_learned(const fwbf_code *code, const fwbf_params *plain, const fwbf_learned_params *lp,
                         const float *scorer_dev, const void *y_dev, int64_t F, int64_t y_stride,
                         uint32_t *z_dev, int32_t *iters_dev, uint8_t *ok_dev, uint8_t *learned_ok_dev,
@@ -323,7 +336,8 @@ int fwbf_decode_learned(const fwbf_code *code, const fwbf_params *plain, const f
                         void *stream);
 
 /* Scorer forward and backward over n_tiles tiles of 32 records (records laid
- * out as emitted, tile index = frame * rounds + round).  scores_dev
+ * out as emitted: tile index = (frame * rounds + round) * tiles_per_round +
+ * tile of the round, tiles_per_round = ceil(groups * topk / 32)).  scores_dev
  * (optional, n_tiles * 32 floats) receives the scores.  out_dev (optional,
  * P + 2 floats) receives the gradient of the mean weighted binary
  * cross-entropy with logits over the valid records (positives weighted by

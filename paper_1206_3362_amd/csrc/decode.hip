@@ -81,6 +81,9 @@ struct DecodeArgs {
     int multi;    // some block holds several shifts
     int strided;  // block g = {n : n mod G = g}: bit n = pos G + g
     uint32_t magG, maskG;
+    // frames with skip[f] != 0 are left alone; the others add their rounds to
+    // iters[f] (the plain fallback after the learned pass)
+    const uint8_t *skip;
 };
 
 // bit of position pos in block g, and block / position of bit n
@@ -337,6 +340,7 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
     const int N = a.N, M = a.M;
     Mag *mag = (Mag *)s.mag;
     Chk *chk = (Chk *)s.chk;
+    if (a.skip && a.skip[f]) return;  // the same answer for every thread of the frame
 
     // ---- Initialization: |y|, z_0 = [y < 0] (Section III) ----------------
     const Y *yrow = (const Y *)a.y + f * a.stride;
@@ -739,7 +743,7 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
     uint32_t *zo = a.z + f * NW;
     for (int w = tid; w < NW; w += T) zo[w] = s.zw[w];
     if (tid == 0) {
-        a.iters[f] = k;
+        a.iters[f] = k + (a.skip ? a.iters[f] : 0);
         a.ok[f] = (uint8_t)okf;
     }
     frame_sync<WAVE>();
@@ -973,6 +977,10 @@ int try_fast_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int
                     const uint8_t *skip, int iters_add);
 int try_cyclic_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int64_t F, int64_t stride,
                       uint32_t *z, int32_t *iters, uint8_t *ok, hipStream_t st);
+// The general kernel (any code, dtype and selection); with a skip list, only
+// frames with skip[f] == 0 are decoded and their rounds add to iters[f].
+int decode_general(const fwbf_code *code, const fwbf_params *params, const void *y_dev, int64_t F, int64_t y_stride,
+                   uint32_t *z_dev, int32_t *iters_dev, uint8_t *ok_dev, hipStream_t stream, const uint8_t *skip);
 
 int prepare_decode(const fwbf_code *c, const fwbf_params *p, DecodeArgs *out, int *T_out, bool force_key64,
                    bool force_alias)
@@ -1108,6 +1116,20 @@ extern "C" int fwbf_decode(const fwbf_code *code, const fwbf_params *params, con
     }
     if (params->flags & FWBF_FLAG_SPECIALISED_ONLY)
         return fail(FWBF_E_UNSUPPORTED, "no specialised kernel takes these parameters");
+    return decode_general(code, params, y_dev, F, y_stride, z_dev, iters_dev, ok_dev, (hipStream_t)stream, nullptr);
+}
+
+namespace fwbf {
+int decode_general(const fwbf_code *code, const fwbf_params *params, const void *y_dev, int64_t F, int64_t y_stride,
+                   uint32_t *z_dev, int32_t *iters_dev, uint8_t *ok_dev, hipStream_t stream, const uint8_t *skip)
+{
+    DecodeArgs a;
+    int T = 0;
+    const int k = prepare_decode(code, params, &a, &T);
+    if (k < 0) return k;
+    DeviceTables t;
+    int rc = device_tables(const_cast<fwbf_code *>(code), &t);
+    if (rc) return rc;
     int dev = 0, cus = 0, blocks = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -1158,9 +1180,11 @@ extern "C" int fwbf_decode(const fwbf_code *code, const fwbf_params *params, con
     a.y = y_dev; a.F = F; a.stride = y_stride;
     a.z = z_dev; a.iters = iters_dev; a.ok = ok_dev;
     a.col = t.col; a.row = t.row; a.coldeg = t.coldeg; a.rowdeg = t.rowdeg;
+    a.skip = skip;
     const int64_t grid = std::min<int64_t>(F, (int64_t)blocks * cus);
-    return dispatch(params->dtype, key32, T, a, (int)grid, (hipStream_t)stream);
+    return dispatch(params->dtype, key32, T, a, (int)grid, stream);
 }
+}  // namespace fwbf
 
 // ---------------------------------------------------------------------------
 // mixed-code batch

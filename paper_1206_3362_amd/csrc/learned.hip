@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "frames.h"
 #include "internal.h"
@@ -28,6 +29,8 @@ namespace fwbf {
 int try_fast_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int64_t F, int64_t stride,
                     uint32_t *z, int32_t *iters, uint8_t *ok, hipStream_t st, const uint32_t *shift_dev,
                     const uint8_t *skip, int iters_add);
+int decode_general(const fwbf_code *code, const fwbf_params *params, const void *y_dev, int64_t F, int64_t y_stride,
+                   uint32_t *z_dev, int32_t *iters_dev, uint8_t *ok_dev, hipStream_t stream, const uint8_t *skip);
 
 namespace {
 
@@ -202,7 +205,7 @@ struct LearnArgs {
     int32_t *iters;
     uint8_t *ok;
     uint8_t *learned_ok;  // optional
-    fwbf_record *rec;     // optional [F][T][32]
+    fwbf_record *rec;     // optional [F][T][32] (one tile per round)
     const uint32_t *pool; // labels for records (pool row f % pool_n, NULL: all-zero)
     int64_t pool_n, f0;
     const float *params;
@@ -488,9 +491,10 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
             // j >= NC (no proposal) get valid = 0
             if (a.rec && lane < 32) {
                 fwbf_record r;
-                r.S = (int16_t)cS;
-                r.a = (uint8_t)ca;
+                r.S = cS;
+                r.a = (uint16_t)ca;
                 r.u = (uint8_t)cu;
+                r.pad = 0;
                 uint32_t lab = 0;
                 if (realc) {
                     const uint32_t zb = (zw[cj.x >> 5] >> (cj.x & 31)) & 1u;
@@ -582,6 +586,354 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
 }
 
 // ---------------------------------------------------------------------------
+// Learned pass with one frame per workgroup (larger codes, int8 or int16)
+// ---------------------------------------------------------------------------
+// The same rounds as learned_kernel for any full base of single shifts with
+// three block rows.  Slot word of bit n: S << 14 | min(|y_n|, 4095) << 2 | u
+// (S signed, |S| <= 3 * 32768 < 2^17; u <= 3): adds to S and u never carry
+// across the fields, and a saturated magnitude field means that |y_n| is read
+// from the frame's row in global memory.  Block g (p bits) is padded to
+// Lc = L*C slots: thread (g, l) holds positions l, l + L, ..., and the column
+// kk = pos / L is XORed with g mod B (B = 64/L blocks per wavefront) so that a
+// wavefront's slot reads use distinct LDS banks.  Proposal c = block * k +
+// rank is scored by lane c % 32 of wavefront c / 32.
+constexpr int WIDE_T = 1024;
+constexpr uint32_t WSAT = 4095;
+constexpr int CW_WEIGHT = 0, CW_FLAGS = 1, CW_NTOG = 2;
+
+struct WideArgs {
+    const void *y;
+    int64_t F, stride;
+    uint32_t *z;
+    int32_t *iters;
+    uint8_t *ok;
+    uint8_t *learned_ok;  // optional
+    fwbf_record *rec;     // optional [F][T][32 tpr]
+    const uint32_t *pool; // labels for records (pool row f % pool_n, NULL: all-zero)
+    int64_t pool_n, f0;
+    const float *params;
+    const uint32_t *shift;  // 3 x nb raw shifts
+    int N, M, Z, nb;
+    uint32_t magZ, maskZ, magP, maskP, magD, maskD;  // n / Z, n / p, n / nb
+    int p, L, logL, Lc, B, Geff, k, T, NC, tpr;
+    float A, invA, dv;
+    int o_chk, o_chkp, o_z, o_syn, o_cand, o_list, o_ctl, o_sh, o_net, o_netw, lds_bytes;
+};
+
+__device__ __forceinline__ uint32_t wide_slot(const WideArgs &a, uint32_t n)
+{
+    const uint32_t g = fdiv(n, a.magP, a.maskP), pos = n - g * (uint32_t)a.p;
+    return g * (uint32_t)a.Lc + (pos ^ ((g & (uint32_t)(a.B - 1)) << a.logL));
+}
+
+template <int DT>
+__device__ __forceinline__ uint32_t wide_mag(const void *yrow, uint32_t n)
+{
+    if constexpr (DT == FWBF_I8) {
+        const int v = ((const int8_t *)yrow)[n];
+        return (uint32_t)(v < 0 ? -v : v);
+    } else {
+        const int v = ((const int16_t *)yrow)[n];
+        return (uint32_t)(v < 0 ? -v : v);
+    }
+}
+
+template <int DT, int C>
+__global__ __launch_bounds__(WIDE_T) void learned_wide_kernel(WideArgs a)
+{
+    using Y = typename std::conditional<DT == FWBF_I8, int8_t, int16_t>::type;
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t *slots = (uint32_t *)smem;
+    uint32_t *chk = (uint32_t *)(smem + a.o_chk);    // min1 | min2 << 16
+    uint8_t *chkp = smem + a.o_chkp;                  // lowest position holding min1
+    uint32_t *zw = (uint32_t *)(smem + a.o_z);
+    uint32_t *syn = (uint32_t *)(smem + a.o_syn);
+    uint32_t *cand = (uint32_t *)(smem + a.o_cand);  // proposals: bit index or NONE
+    uint32_t *list = (uint32_t *)(smem + a.o_list);  // toggles: check | new bit << 31
+    int *ctl = (int *)(smem + a.o_ctl);
+    uint32_t *sh = (uint32_t *)(smem + a.o_sh);
+    float *nbias = (float *)(smem + a.o_net);
+    bf16x4 *nw = (bf16x4 *)(smem + a.o_netw);
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const uint32_t Z = a.Z;
+    const int N = a.N, M = a.M, dc = a.nb;
+
+    for (int t = tid; t < 3 * dc; t += WIDE_T) sh[t] = a.shift[t];
+    for (int t = tid; t < 32; t += WIDE_T) {
+        nbias[t] = a.params[O_B1 + t];
+        nbias[32 + t] = a.params[O_B2 + t];
+        nbias[64 + t] = a.params[O_W3 + t];
+    }
+    for (int t = tid; t < a.T; t += WIDE_T) nbias[96 + t] = (float)t / (float)a.T;
+    if (tid < 64) {
+        const int i = lane & 31, hi = lane >> 5;
+        const float *p = a.params;
+        nw[5 * lane] = hi == 0 ? pack4(p[O_W1 + i * 4 + 0], p[O_W1 + i * 4 + 1], p[O_W1 + i * 4 + 2], p[O_W1 + i * 4 + 3])
+                               : pack4(0.f, 0.f, 0.f, 0.f);
+        for (int c = 0; c < 4; c++) {
+            const float *r = p + O_W2 + i * H + 8 * c + 4 * hi;
+            nw[5 * lane + 1 + c] = pack4(r[0], r[1], r[2], r[3]);
+        }
+    }
+    __syncthreads();
+    NetL net;
+    net.wq = nw;
+    net.b1 = nbias;
+    net.b2 = nbias + 32;
+    net.w3 = nbias + 64;
+    net.b3 = a.params[O_B3];
+
+    const float qu1 = 1.0f / a.dv, qu2 = 2.0f / a.dv, qu3 = 3.0f / a.dv;
+    const uint32_t g = tid >> a.logL, l = tid & (uint32_t)(a.L - 1);
+    const bool gact = (int)g < a.Geff;
+    const uint32_t gp = g * (uint32_t)a.p;
+    const uint32_t swk = g & (uint32_t)(a.B - 1);  // column swizzle of this block
+    const uint32_t sbase = gact ? g * (uint32_t)a.Lc + l : 0u;  // idle threads read block 0 (never live)
+    uint64_t realm = 0;
+#pragma unroll
+    for (int kk = 0; kk < C; kk++) {
+        const uint32_t pos = l + ((uint32_t)kk << a.logL);
+        realm |= (uint64_t)(gact && (int)pos < a.p && (int)(gp + pos) < N) << kk;
+    }
+    const bool scorer = (int)wv < a.tpr;  // wavefront-uniform
+    const uint32_t j = lane & 31, c = 32 * wv + j;
+    const bool blead = scorer && lane < 32 && (j % a.k) == 0 && (int)c < a.NC;
+    const int NW = (N + 31) >> 5;
+    const int Nr = (N + 63) & ~63, Mr = (M + 63) & ~63;
+
+    const FrameRange fr = xcd_frames(a.F);
+    for (int64_t f = fr.first; f < fr.end; f += fr.step) {
+        const Y *yrow = (const Y *)a.y + f * a.stride;
+        if (tid == 0) { ctl[CW_WEIGHT] = 0; ctl[CW_FLAGS] = 0; ctl[CW_NTOG] = 0; }
+        // ---- z_0 = [y < 0] and the magnitude field of every slot (S = u = 0)
+        constexpr int UNR = 4;
+        for (int n0 = tid; n0 < Nr; n0 += UNR * WIDE_T) {
+            Y v[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; u++) {
+                const int n = n0 + u * WIDE_T;
+                v[u] = n < N ? yrow[n] : (Y)0;
+            }
+#pragma unroll
+            for (int u = 0; u < UNR; u++) {
+                const int n = n0 + u * WIDE_T;
+                if (n >= Nr) break;  // uniform per wavefront (Nr is a multiple of 64)
+                const unsigned long long b = __ballot(v[u] < 0);
+                if (lane == 0) {
+                    zw[n >> 5] = (uint32_t)b;
+                    zw[(n >> 5) + 1] = (uint32_t)(b >> 32);
+                }
+                if (n < N) {
+                    const int x = v[u];
+                    slots[wide_slot(a, n)] = min((uint32_t)(x < 0 ? -x : x), WSAT) << 2;
+                }
+            }
+        }
+        __syncthreads();
+        // ---- check minima, syndrome s_0, initial S and u pushed to the members
+        for (int m0 = tid; m0 < Mr; m0 += WIDE_T) {
+            bool par = false;
+            if (m0 < M) {
+                const uint32_t i = fdiv(m0, a.magZ, a.maskZ), r = m0 - i * Z;
+                const uint32_t *si = sh + i * dc;
+                // the two smallest keys |y| << 5 | q: min1 and min2 (with
+                // multiplicity) and the lowest position holding min1
+                uint32_t k1 = 0xFFFFFFFFu, k2 = 0xFFFFFFFFu, sx = 0;
+                for (int q0 = 0; q0 < dc; q0 += 4) {
+                    int v[4];
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        const int q = q0 + u < dc ? q0 + u : dc - 1;
+                        v[u] = yrow[q * Z + addmod(r, si[q], Z)];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        if (q0 + u >= dc) break;
+                        sx ^= (uint32_t)v[u];  // bit 31: parity of the negative members
+                        const uint32_t key = ((uint32_t)(v[u] < 0 ? -v[u] : v[u]) << 5) | (uint32_t)(q0 + u);
+                        k2 = min(k2, max(k1, key));
+                        k1 = min(k1, key);
+                    }
+                }
+                par = (sx >> 31) != 0;
+                const uint32_t m1 = k1 >> 5, m2 = k2 >> 5, pos = k1 & 31u;
+                chk[m0] = m1 | (m2 << 16);
+                chkp[m0] = (uint8_t)pos;
+                const uint32_t d1 = ((uint32_t)(par ? (int)m1 : -(int)m1) << 14) + (par ? 1u : 0u);
+                const uint32_t d2 = ((uint32_t)(par ? (int)m2 : -(int)m2) << 14) + (par ? 1u : 0u);
+                for (int q = 0; q < dc; q++)
+                    atomicAdd(&slots[wide_slot(a, q * Z + addmod(r, si[q], Z))], (uint32_t)q == pos ? d2 : d1);
+            }
+            const unsigned long long b = __ballot(par);
+            if (lane == 0) {
+                syn[m0 >> 5] = (uint32_t)b;
+                syn[(m0 >> 5) + 1] = (uint32_t)(b >> 32);
+                if (b) atomicAdd(&ctl[CW_WEIGHT], __popcll(b));
+            }
+        }
+        __syncthreads();
+
+        int t = 0, okf = 0, rec_end = 0;
+        uint32_t prv = NONE;
+        const uint32_t *cw = a.pool ? a.pool + (size_t)((a.f0 + f) % a.pool_n) * NW : nullptr;
+        for (;;) {
+            if (ctl[CW_WEIGHT] == 0) { okf = 1; break; }
+            if (t == a.T) break;
+            const float al = a.params[O_AL + t], be = a.params[O_AL + a.T + t];
+            // ---- the k best live slots of each block by E_t (ties: lower index)
+            uint64_t excl = 0;
+            for (int rk = 0; rk < a.k; rk++) {
+                const uint64_t livem = realm & ~excl;
+                float bE = -__builtin_huge_valf();
+                uint32_t bi = NONE;
+                // four slot reads in flight at a time (the loop itself is not
+                // unrolled: register pressure at 1024 threads per workgroup)
+#pragma unroll 1
+                for (int kk = 0; kk < C; kk += 4) {
+                    uint32_t v[4];
+#pragma unroll
+                    for (int u = 0; u < 4; u++) v[u] = slots[sbase + ((((uint32_t)(kk + u)) ^ swk) << a.logL)];
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        const bool live = (livem >> (kk + u)) & 1;
+                        uint32_t av = (v[u] >> 2) & WSAT;
+                        if constexpr (DT == FWBF_I16)
+                            if (live && av == WSAT) av = wide_mag<DT>(yrow, gp + l + ((uint32_t)(kk + u) << a.logL));
+                        const float E = __builtin_fmaf(-al, (float)av, be * (float)((int32_t)v[u] >> 14));
+                        const bool take = live && E > bE;
+                        bE = take ? E : bE;
+                        bi = take ? (uint32_t)(kk + u) : bi;
+                    }
+                }
+                const uint32_t nme = gp + l + (bi << a.logL);
+                unsigned long long best = bi == NONE ? 0ull : (((unsigned long long)orderable(bE) << 32) | (0xFFFFFFFFu - nme));
+                best = group_max64(best, a.L);
+                const bool real = (best >> 32) != 0;
+                const uint32_t bn = 0xFFFFFFFFu - (uint32_t)best;
+                if (real && bi != NONE && bn == nme) excl |= 1ull << bi;
+                if (gact && l == 0) cand[g * a.k + rk] = real ? bn : NONE;
+            }
+            if (tid == 0) { ctl[CW_FLAGS] = 0; ctl[CW_NTOG] = 0; }
+            __syncthreads();
+            // ---- scores of the proposals, the flip decision of every block
+            uint32_t nsel = NONE;
+            bool flip = false;
+            if (scorer) {
+                const uint32_t cn = (lane < 32 && (int)c < a.NC) ? cand[c] : NONE;
+                const bool realc = cn != NONE;
+                uint32_t word = 0, ca = 0;
+                if (realc) {
+                    word = slots[wide_slot(a, cn)];
+                    ca = (word >> 2) & WSAT;
+                    if (DT == FWBF_I16 && ca == WSAT) ca = wide_mag<DT>(yrow, cn);
+                }
+                const int cS = (int32_t)word >> 14;
+                const uint32_t cu = word & 3u;
+                bf16x4 x = pack4(0.f, 0.f, 0.f, 0.f);
+                if (realc) {
+                    const float E = __builtin_fmaf(-al, (float)ca, be * (float)cS);
+                    float fa, fe;
+                    if (a.invA != 0.0f) { fa = (float)ca * a.invA; fe = E * a.invA; }
+                    else { fa = (float)ca / a.A; fe = E / a.A; }
+                    const float fu = cu == 0 ? 0.0f : cu == 1 ? qu1 : cu == 2 ? qu2 : qu3;
+                    x = pack4(fa, fe, fu, nbias[96 + t]);
+                }
+                const float score = net_score(net, x);
+                if (a.rec && lane < 32) {
+                    fwbf_record r;
+                    r.S = cS;
+                    r.a = (uint16_t)ca;
+                    r.u = (uint8_t)cu;
+                    r.pad = 0;
+                    uint32_t lab = 0;
+                    if (realc) {
+                        const uint32_t zb = (zw[cn >> 5] >> (cn & 31)) & 1u;
+                        const uint32_t cb = cw ? (cw[cn >> 5] >> (cn & 31)) & 1u : 0u;
+                        lab = zb ^ cb;
+                    }
+                    r.label = (uint8_t)lab;
+                    r.valid = realc ? 1 : 0;
+                    r.n = (uint16_t)(realc ? cn : 0xFFFF);
+                    a.rec[(((size_t)f * a.T + t) * a.tpr + wv) * 32 + j] = r;
+                }
+                // best score among the k proposals of each block (ties: lower index)
+                unsigned long long sk = realc ? (((unsigned long long)orderable(score) << 32) | (0xFFFFFFFFu - cn)) : 0ull;
+                if (a.k > 1) sk = group_max64(sk, a.k);
+                nsel = 0xFFFFFFFFu - (uint32_t)sk;
+                flip = blead && sk != 0 && (uint32_t)(sk >> 32) > orderable(0.0f);
+                const uint32_t cur = flip ? nsel : NONE;
+                const unsigned long long fm = __ballot(flip), dm = __ballot(blead && cur != prv);
+                prv = blead ? cur : prv;
+                if (lane == 0 && (fm | dm)) atomicOr(&ctl[CW_FLAGS], (fm ? 1 : 0) | (dm ? 2 : 0));
+            }
+            rec_end = t + 1;
+            __syncthreads();
+            const int flg = ctl[CW_FLAGS];
+            if (!(flg & 1) || !(flg & 2)) break;  // no flip, or the previous round's flips: stop
+            // ---- flips: z, the three syndrome toggles, the toggle list
+            if (scorer) {
+                const unsigned long long fm = __ballot(flip);
+                if (fm) {
+                    int base = 0;
+                    if (lane == 0) base = atomicAdd(&ctl[CW_NTOG], 3 * __popcll(fm));
+                    base = __shfl(base, 0, 64);
+                    const int rank = __popcll(fm & ((1ull << lane) - 1));
+                    uint32_t ones = 0;
+                    if (flip) {
+                        const uint32_t n = nsel;
+                        atomicXor(&zw[n >> 5], 1u << (n & 31));
+                        const uint32_t jb = fdiv(n, a.magZ, a.maskZ), cc = n - jb * Z;
+                        uint32_t mm[3], old[3];
+#pragma unroll
+                        for (int tt = 0; tt < 3; tt++) mm[tt] = tt * Z + submod(cc, sh[tt * dc + jb], Z);
+#pragma unroll
+                        for (int tt = 0; tt < 3; tt++) old[tt] = atomicXor(&syn[mm[tt] >> 5], 1u << (mm[tt] & 31));
+#pragma unroll
+                        for (int tt = 0; tt < 3; tt++) {
+                            const uint32_t nb1 = ((old[tt] >> (mm[tt] & 31)) & 1u) ^ 1u;
+                            ones += nb1;
+                            list[base + 3 * rank + tt] = mm[tt] | (nb1 << 31);
+                        }
+                    }
+                    // unsatisfied checks: +1 per toggle to 1, -1 per toggle to 0
+                    int dw = flip ? 2 * (int)ones - 3 : 0;
+#pragma unroll
+                    for (int d = 32; d >= 1; d >>= 1) dw += __shfl_xor(dw, d, 64);
+                    if (lane == 0 && dw) atomicAdd(&ctl[CW_WEIGHT], dw);
+                }
+            }
+            t += 1;
+            __syncthreads();
+            // ---- +-(2w, 1) to S and u of every member of every toggled check
+            const int ntask = ctl[CW_NTOG] * dc;
+            for (int id = tid; id < ntask; id += WIDE_T) {
+                const uint32_t e0 = fdiv(id, a.magD, a.maskD), q = id - e0 * dc;
+                const uint32_t ent = list[e0];
+                const uint32_t m = ent & 0x7FFFFFFFu;
+                const uint32_t i = fdiv(m, a.magZ, a.maskZ), r = m - i * Z;
+                const uint32_t n = q * Z + addmod(r, sh[i * dc + q], Z);
+                const uint32_t cwd = chk[m];
+                const uint32_t w = chkp[m] == q ? (cwd >> 16) : (cwd & 0xFFFFu);
+                const uint32_t d = ((2u * w) << 14) + 1u;
+                atomicAdd(&slots[wide_slot(a, n)], (ent >> 31) ? d : 0u - d);
+            }
+            __syncthreads();
+        }
+        // records of the rounds not run are marked invalid
+        if (a.rec && scorer && lane < 32)
+            for (int s = rec_end; s < a.T; s++) a.rec[(((size_t)f * a.T + s) * a.tpr + wv) * 32 + j].valid = 0;
+        uint32_t *zo = a.z + f * NW;
+        for (int w = tid; w < NW; w += WIDE_T) zo[w] = zw[w];
+        if (tid == 0) {
+            a.iters[f] = t;
+            a.ok[f] = (uint8_t)okf;
+            if (a.learned_ok) a.learned_ok[f] = (uint8_t)okf;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // training kernels
 // ---------------------------------------------------------------------------
 struct GradArgs {
@@ -589,7 +941,7 @@ struct GradArgs {
     int64_t n_tiles;
     const float *params;
     float pos_weight, A, dv;
-    int T, P;
+    int T, P, tpr;   // tpr: tiles of 32 records per round
     float *partial;  // [gridDim][P + 2]
     float *scores;   // optional forward output [n_tiles][32]
     int backward;
@@ -631,7 +983,7 @@ __global__ __launch_bounds__(64) void grad_kernel(GradArgs g)
     if (l < 32) sw1c[l] = bf16_f(bf16_rne(g.params[O_W1 + l * 4 + 1]));
     __syncthreads();
     for (int64_t tile = blockIdx.x; tile < g.n_tiles; tile += gridDim.x) {
-        const int t = (int)(tile % g.T);
+        const int t = (int)((tile / g.tpr) % g.T);
         const fwbf_record r = g.rec[tile * 32 + j];
         const bool valid = r.valid != 0;
         if (!__ballot(valid)) {  // empty tile
@@ -826,6 +1178,7 @@ int check_lp(const fwbf_learned_params *lp)
     if (lp->topk < 1 || lp->topk > 4 || (lp->topk & (lp->topk - 1)))
         return fail(FWBF_E_INVALID, "topk must be 1, 2 or 4");
     if (lp->groups < 1) return fail(FWBF_E_INVALID, "groups must be >= 1");
+    if (lp->groups * lp->topk > 512) return fail(FWBF_E_INVALID, "groups * topk must be <= 512");
     if (!(lp->scale > 0.0f)) return fail(FWBF_E_INVALID, "scale must be > 0");
     return FWBF_OK;
 }
@@ -837,6 +1190,100 @@ using namespace fwbf;
 
 extern "C" int fwbf_scorer_size(int rounds) { return rounds < 1 ? fail(FWBF_E_INVALID, "rounds must be >= 1") : 1249 + 2 * rounds; }
 
+namespace fwbf {
+namespace {
+// The learned pass with one frame per workgroup, then plain FWBF (general
+// kernel) for the frames it leaves with a nonzero syndrome.
+int learned_wide(const fwbf_code *code, const fwbf_params *plain, const fwbf_learned_params *lp,
+                 const float *scorer_dev, const void *y_dev, int64_t F, int64_t y_stride, uint32_t *z_dev,
+                 int32_t *iters_dev, uint8_t *ok_dev, uint8_t *learned_ok_dev, fwbf_record *records_dev,
+                 const uint32_t *pool_dev, int64_t pool_n, int64_t f0, hipStream_t st)
+{
+    WideArgs a;
+    memset(&a, 0, sizeof a);
+    a.p = (code->N + lp->groups - 1) / lp->groups;
+    a.Geff = (code->N + a.p - 1) / a.p;
+    a.k = lp->topk;
+    a.NC = a.Geff * a.k;
+    a.tpr = (lp->groups * lp->topk + 31) / 32;
+    if (a.tpr > WIDE_T / 64) return fail(FWBF_E_UNSUPPORTED, "groups * topk must be <= 512");
+    // the smallest C with L = 2^ceil(log2(ceil(p / C))) <= 64 lanes per block,
+    // L * C >= 64 (the bank swizzle) and a thread for every (block, lane)
+    int C = 0, L = 0;
+    for (int cc : {8, 16, 32, 64}) {
+        const int l = 1 << ilog2l((uint32_t)((a.p + cc - 1) / cc));
+        if (l > 64 || cc * l < 64 || (int64_t)a.Geff * l > WIDE_T) continue;
+        C = cc;
+        L = l;
+        break;
+    }
+    if (!C) return fail(FWBF_E_UNSUPPORTED, "blocks do not fit one workgroup of 1024 threads");
+    a.L = L; a.logL = ilog2l(L); a.Lc = L * C; a.B = 64 / L;
+    a.N = code->N; a.M = code->M; a.Z = code->Z; a.nb = code->nb;
+    magic_l(a.Z, &a.magZ, &a.maskZ);
+    magic_l(a.p, &a.magP, &a.maskP);
+    magic_l(a.nb, &a.magD, &a.maskD);
+    a.T = lp->rounds;
+    a.A = lp->scale;
+    {
+        int ex = 0;
+        const float mant = std::frexp(lp->scale, &ex);
+        a.invA = (mant == 0.5f && ex > -120 && ex < 120) ? std::ldexp(1.0f, 1 - ex) : 0.0f;
+    }
+    a.dv = 3.0f;
+    int off = a.Geff * a.Lc * 4;  // slots at offset 0
+    auto take = [&](int bytes, int align) { off = (off + align - 1) / align * align; int o = off; off += bytes; return o; };
+    a.o_chk = take(4 * code->M, 4);
+    a.o_chkp = take(code->M, 1);
+    a.o_z = take(((code->N + 63) / 64) * 8, 8);
+    a.o_syn = take(((code->M + 63) / 64) * 8, 8);
+    a.o_cand = take(4 * 32 * a.tpr, 4);
+    a.o_list = take(4 * 3 * a.Geff, 4);
+    a.o_ctl = take(16, 4);
+    a.o_sh = take(4 * 3 * code->nb, 4);
+    a.o_net = take(4 * (96 + 64), 16);
+    a.o_netw = take(64 * 5 * 8, 16);
+    a.lds_bytes = (off + 15) / 16 * 16;
+    if (a.lds_bytes > 160 * 1024) return fail(FWBF_E_UNSUPPORTED, "frame state exceeds 160 KiB of LDS");
+    DeviceTables tb;
+    int rc = device_tables(const_cast<fwbf_code *>(code), &tb);
+    if (rc) return rc;
+    a.y = y_dev; a.F = F; a.stride = y_stride;
+    a.z = z_dev; a.iters = iters_dev; a.ok = ok_dev; a.learned_ok = learned_ok_dev;
+    a.rec = records_dev; a.pool = pool_dev; a.pool_n = pool_n; a.f0 = f0;
+    a.params = scorer_dev; a.shift = tb.shift;
+    auto launch = [&](auto kern) -> int {
+        int blocks = 0, dev = 0, cus = 0;
+        if (a.lds_bytes > 65536)
+            (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, a.lds_bytes);
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kern, WIDE_T, a.lds_bytes);
+        if (e == hipSuccess) e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return hip_fail(e, "learned decode occupancy");
+        if (blocks < 1) return fail(FWBF_E_UNSUPPORTED, "learned kernel does not fit");
+        const int64_t grid = std::min<int64_t>(F, (int64_t)blocks * cus);
+        hipLaunchKernelGGL(kern, dim3((int)grid), dim3(WIDE_T), a.lds_bytes, st, a);
+        e = hipGetLastError();
+        return e == hipSuccess ? FWBF_OK : hip_fail(e, "learned decode launch");
+    };
+#define FWBF_WIDE(DT)                                                    \
+    switch (C) {                                                         \
+    case 8: rc = launch(learned_wide_kernel<DT, 8>); break;              \
+    case 16: rc = launch(learned_wide_kernel<DT, 16>); break;            \
+    case 32: rc = launch(learned_wide_kernel<DT, 32>); break;            \
+    default: rc = launch(learned_wide_kernel<DT, 64>); break;            \
+    }
+    if (plain->dtype == FWBF_I8) { FWBF_WIDE(FWBF_I8) }
+    else { FWBF_WIDE(FWBF_I16) }
+#undef FWBF_WIDE
+    if (rc) return rc;
+    // plain FWBF from the original y for every frame the learned pass left
+    // with a nonzero syndrome; its rounds add to the learned ones
+    return decode_general(code, plain, y_dev, F, y_stride, z_dev, iters_dev, ok_dev, st, ok_dev);
+}
+}  // namespace
+}  // namespace fwbf
+
 extern "C" int fwbf_decode_learned(const fwbf_code *code, const fwbf_params *plain, const fwbf_learned_params *lp,
                                    const float *scorer_dev, const void *y_dev, int64_t F, int64_t y_stride,
                                    uint32_t *z_dev, int32_t *iters_dev, uint8_t *ok_dev, uint8_t *learned_ok_dev,
@@ -846,17 +1293,25 @@ extern "C" int fwbf_decode_learned(const fwbf_code *code, const fwbf_params *pla
     int rc = check_lp(lp);
     if (rc) return rc;
     if (!code || !plain) return fail(FWBF_E_INVALID, "null code or params");
-    if (plain->dtype != FWBF_I8) return fail(FWBF_E_UNSUPPORTED, "the learned decoder takes int8 inputs");
-    if (code->mb != 3 || code->nb != 6 || code->multi)
-        return fail(FWBF_E_UNSUPPORTED, "the learned decoder covers (3,6) base matrices of single shifts");
+    if (plain->dtype != FWBF_I8 && plain->dtype != FWBF_I16)
+        return fail(FWBF_E_UNSUPPORTED, "the learned decoder takes int8 or int16 inputs");
+    if (code->mb != 3 || code->nb < 2 || code->nb > 32 || code->multi)
+        return fail(FWBF_E_UNSUPPORTED, "the learned decoder covers bases of 3 block rows, 2..32 block columns "
+                                        "and single shifts");
     for (int v : code->shift)
         if (v < 0) return fail(FWBF_E_UNSUPPORTED, "the learned decoder needs a full base (no zero blocks)");
+    if (code->N > 65536) return fail(FWBF_E_UNSUPPORTED, "the learned decoder takes N <= 65536");
     if (plain->select != FWBF_GROUPS || plain->threads_per_frame != 0)
         return fail(FWBF_E_UNSUPPORTED, "the fallback must be plain FWBF (GROUPS)");
     if (F < 0 || y_stride < code->N || f0 < 0 || (pool_dev && pool_n < 1)) return fail(FWBF_E_INVALID, "invalid size");
     if (lp->groups > code->N) return fail(FWBF_E_INVALID, "groups must be <= N");
     if (F == 0) return FWBF_OK;
     if (!scorer_dev || !y_dev || !z_dev || !iters_dev || !ok_dev) return fail(FWBF_E_INVALID, "null buffer");
+    const bool wave = plain->dtype == FWBF_I8 && code->nb == 6 && lp->groups * lp->topk <= 32 &&
+                      !(plain->flags & FWBF_FLAG_GENERIC_KERNEL);
+    if (!wave)
+        return learned_wide(code, plain, lp, scorer_dev, y_dev, F, y_stride, z_dev, iters_dev, ok_dev, learned_ok_dev,
+                            records_dev, pool_dev, pool_n, f0, (hipStream_t)stream);
     LearnArgs a;
     memset(&a, 0, sizeof a);
     a.p = (code->N + lp->groups - 1) / lp->groups;
@@ -869,7 +1324,9 @@ extern "C" int fwbf_decode_learned(const fwbf_code *code, const fwbf_params *pla
         const int l = 1 << ilog2l(need);
         if ((int64_t)a.Geff * l <= 64) { C = cc; L = l; break; }
     }
-    if (!C) return fail(FWBF_E_UNSUPPORTED, "block too long for one wave");
+    if (!C)  // blocks too long for one wavefront: one frame per workgroup
+        return learned_wide(code, plain, lp, scorer_dev, y_dev, F, y_stride, z_dev, iters_dev, ok_dev, learned_ok_dev,
+                            records_dev, pool_dev, pool_n, f0, (hipStream_t)stream);
     a.L = L; a.logL = ilog2l(L);
     a.N = code->N; a.M = code->M; a.Z = code->Z; a.nb = code->nb;
     // a 24-bit reciprocal of Z that divides every bit index exactly (so for
@@ -959,6 +1416,7 @@ int launch_grad(const fwbf_record *records_dev, int64_t n_tiles, const fwbf_lear
     g.rec = records_dev; g.n_tiles = n_tiles; g.params = scorer_dev;
     g.pos_weight = pos_weight; g.A = lp->scale; g.dv = 3.0f;
     g.T = lp->rounds; g.P = P;
+    g.tpr = (lp->groups * lp->topk + 31) / 32;
     g.partial = partial; g.scores = scores_dev; g.backward = out_dev != nullptr;
     hipLaunchKernelGGL(grad_kernel, dim3(GRAD_PARTS), dim3(64), 0, st, g);
     hipError_t e = hipGetLastError();

@@ -69,8 +69,15 @@ class LearnedParams(C.Structure):
                 ("scale", C.c_float)]
 
 
-RECORD_DTYPE = np.dtype([("S", "<i2"), ("a", "u1"), ("u", "u1"), ("label", "u1"), ("valid", "u1"),
-                         ("n", "<u2")])
+# fwbf_record (12 bytes)
+RECORD_DTYPE = np.dtype([("S", "<i4"), ("a", "<u2"), ("n", "<u2"), ("u", "u1"), ("label", "u1"),
+                         ("valid", "u1"), ("pad", "u1")])
+assert RECORD_DTYPE.itemsize == 12
+
+
+def record_slots(groups: int, topk: int) -> int:
+    """Proposal slots per round in the record layout (FWBF_RECORD_SLOTS)."""
+    return 32 * ((groups * topk + 31) // 32)
 
 
 _lib = None
@@ -366,10 +373,18 @@ def decode_learned(code: Code, y, plain: DecodeParams, lp: LearnedParams, scorer
     return z, it, ok, lok
 
 
-def record_buffer(F: int, rounds: int, device="cuda"):
-    """Device buffer for F * rounds * 32 records (8 bytes each)."""
+def record_buffer(F: int, rounds: int, groups: int = 32, topk: int = 1, device="cuda"):
+    """Device buffer for F * rounds * record_slots(groups, topk) records (12
+    bytes each), shaped [F][rounds][slots][12]."""
     torch = _torch()
-    return torch.empty((F, rounds, 32, 8), dtype=torch.uint8, device=device)
+    return torch.empty((F, rounds, record_slots(groups, topk), RECORD_DTYPE.itemsize), dtype=torch.uint8,
+                       device=device)
+
+
+def records_host(rec):
+    """Records of a record_buffer copied to the host as a structured array
+    [F][rounds][slots]."""
+    return rec.cpu().numpy().view(RECORD_DTYPE)[..., 0]
 
 
 def scorer_grad(records, n_tiles: int, lp: LearnedParams, scorer, pos_weight: float, out=None,

@@ -51,6 +51,7 @@ class TrainConfig:
     pool_size: int = 1024
     plain_groups: int = 8
     max_iter: int = 100
+    int16: bool = False    # int16 frames (scale 256) instead of int8 (scale 16)
 
 
 class Trainer:
@@ -60,7 +61,8 @@ class Trainer:
         self.code, self.cfg, self.dev = code, cfg, device
         # the device comes up through torch before the library's first call
         self.params = torch.from_numpy(init_params(cfg.rounds, seed=cfg.seed)).to(device)
-        self.lp = fwbf.LearnedParams(cfg.rounds, cfg.groups, cfg.topk, 16.0)
+        self.scale = 256.0 if cfg.int16 else 16.0
+        self.lp = fwbf.LearnedParams(cfg.rounds, cfg.groups, cfg.topk, self.scale)
         self.P = fwbf.scorer_size(cfg.rounds)
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)
@@ -69,12 +71,12 @@ class Trainer:
         self.step_count = 0
         pool = code.encode(seed=cfg.seed * 1000 + 1, first=0, count=cfg.pool_size)
         self.pool = torch.from_numpy(pool.view(np.int32)).to(device)
-        self.plain = fwbf.DecodeParams(dtype=fwbf.I8, groups=cfg.plain_groups,
+        self.plain = fwbf.DecodeParams(dtype=fwbf.I16 if cfg.int16 else fwbf.I8, groups=cfg.plain_groups,
                                        max_iter=cfg.max_iter, alpha_num=1, alpha_den=5)
         B = cfg.batch
-        self.y = torch.empty((B, code.N), dtype=torch.int8, device=device)
+        self.y = torch.empty((B, code.N), dtype=torch.int16 if cfg.int16 else torch.int8, device=device)
         self.sig = torch.empty(B, dtype=torch.float32, device=device)
-        self.rec = fwbf.record_buffer(B, cfg.rounds, device)
+        self.rec = fwbf.record_buffer(B, cfg.rounds, cfg.groups, cfg.topk, device)
         self.z = torch.empty((B, (code.N + 31) // 32), dtype=torch.int32, device=device)
         self.it = torch.empty(B, dtype=torch.int32, device=device)
         self.ok = torch.empty(B, dtype=torch.uint8, device=device)
@@ -87,7 +89,7 @@ class Trainer:
         sig = synth.sigma_for(eb, self.code.rate).astype(np.float32)
         self.sig.copy_(self.torch.from_numpy(sig))
         fwbf.channel_into(self.code.N, self.y, f0, self.pool, seed=cfg.seed * 7919, stream_id=9,
-                          sigma=0.0, sigma_per_frame=self.sig, scale=16.0)
+                          sigma=0.0, sigma_per_frame=self.sig, scale=self.scale)
 
     def step(self):
         cfg = self.cfg
@@ -95,7 +97,8 @@ class Trainer:
         self._frames(f0)
         fwbf.decode_learned_into(self.code, self.y, self.plain, self.lp, self.params, self.z,
                                  self.it, self.ok, self.lok, self.rec, self.pool, f0)
-        fwbf.scorer_grad(self.rec, cfg.batch * cfg.rounds, self.lp, self.params, cfg.pos_weight,
+        tiles = cfg.batch * cfg.rounds * fwbf.record_slots(cfg.groups, cfg.topk) // 32
+        fwbf.scorer_grad(self.rec, tiles, self.lp, self.params, cfg.pos_weight,
                          out=self.grad, workspace=self.work)
         self.step_count += 1
         fwbf.adam(self.params, self.grad, self.m, self.v, self.step_count, cfg.lr)
@@ -122,25 +125,38 @@ class Trainer:
         self.step_count = int(d["step"])
 
 
+# the codes a scorer is trained for: (mb, nb, Z, seed) and their defaults
+CODES = {
+    "n1008": dict(code=(3, 6, 168, 2), int16=False, groups=32, plain_groups=8, batch=1 << 13,
+                  ebn0_lo=3.0, ebn0_hi=5.0),
+    "n32400": dict(code=(3, 30, 1080, 5), int16=True, groups=512, plain_groups=64, batch=1 << 10,
+                   ebn0_lo=5.0, ebn0_hi=7.0),
+}
+
+
 def main(argv=None):
-    """Train the scorer of the N=1008 (3,6) code on the GPU and write a
-    checkpoint: python -m paper_1206_3362_amd.learned --steps 512 --out x.npz"""
+    """Train the scorer of one code on the GPU and write a checkpoint:
+    python -m paper_1206_3362_amd.learned --code n1008 --steps 512 --out x.npz"""
     import argparse
     ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--code", choices=sorted(CODES), default="n1008",
+                    help="n1008: (3,6) Z=168 int8; n32400: (3,30) Z=1080 int16")
     ap.add_argument("--steps", type=int, default=512, help="steps of --batch frames (512 x 8192 = 2^22)")
-    ap.add_argument("--batch", type=int, default=1 << 13)
+    ap.add_argument("--batch", type=int, default=0, help="frames per step (0: the code's default)")
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--rounds", type=int, default=16)
-    ap.add_argument("--groups", type=int, default=32)
+    ap.add_argument("--groups", type=int, default=0, help="blocks of the learned pass (0: the code's default)")
     ap.add_argument("--topk", type=int, default=1)
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     import torch
     torch.zeros(1, device="cuda")  # bring the device up before the library loads
-    code = fwbf.Code.from_seed(3, 6, 168, 2)
-    cfg = TrainConfig(rounds=a.rounds, groups=a.groups, topk=a.topk, batch=a.batch, steps=a.steps,
-                      lr=a.lr, seed=a.seed)
+    d = CODES[a.code]
+    code = fwbf.Code.from_seed(*d["code"])
+    cfg = TrainConfig(rounds=a.rounds, groups=a.groups or d["groups"], topk=a.topk, batch=a.batch or d["batch"],
+                      steps=a.steps, lr=a.lr, seed=a.seed, int16=d["int16"], plain_groups=d["plain_groups"],
+                      ebn0_lo=d["ebn0_lo"], ebn0_hi=d["ebn0_hi"])
     tr = Trainer(code, cfg).train(log_every=max(1, a.steps // 16))
     tr.torch.cuda.synchronize()
     for step, loss, records, lpass in tr.history:

@@ -36,7 +36,7 @@ def random_records(n_tiles, T, seed):
 
 
 def to_dev(rec):
-    return torch.from_numpy(rec.view(np.uint8).reshape(rec.shape[0], 32, 8).copy()).cuda()
+    return torch.from_numpy(rec.view(np.uint8).reshape(rec.shape[0], 32, fwbf.RECORD_DTYPE.itemsize).copy()).cuda()
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -129,7 +129,7 @@ def test_learned_pass_matches_reference(name, mbnbZ, G, k, T, A):
     y = synth.awgn_frames(g.N, Fn, synth.sigma_for(4.5, g.rate), 9, None, np.int8)
     lp = fwbf.LearnedParams(T, G, k, A)
     plain = fwbf.DecodeParams(dtype=fwbf.I8, groups=8, max_iter=100)
-    rec = fwbf.record_buffer(Fn, T)
+    rec = fwbf.record_buffer(Fn, T, G, k)
     z, it, ok, lok = fwbf.decode_learned(g, torch.from_numpy(y).cuda(), plain, lp,
                                          torch.from_numpy(p).cuda(), records=rec)
     torch.cuda.synchronize()
@@ -141,7 +141,7 @@ def test_learned_pass_matches_reference(name, mbnbZ, G, k, T, A):
           f"learned-pass successes {int(lok.sum())}", flush=True)
     assert same.mean() >= 0.95
     # round-0 proposals depend only on exact single-precision metrics
-    rg = rec.cpu().numpy().reshape(Fn, T, 32, 8).view(fwbf.RECORD_DTYPE)[..., 0]
+    rg = fwbf.records_host(rec)
     for f in range(Fn):
         r0 = [r for r in recs[f] if r[3] == 0]
         n_gpu = [int(x) for x in rg[f, 0, :len(r0)]["n"]]
@@ -268,14 +268,14 @@ def test_empty_record_slots_are_invalid(mbnbZ, G, k):
     P = R.n_params(T)
     grads, recs = [], []
     for fill in (0xFF, 0x00):
-        rec = fwbf.record_buffer(Fn, T)
+        rec = fwbf.record_buffer(Fn, T, G, k)
         rec.fill_(fill)
         fwbf.decode_learned(g, torch.from_numpy(y).cuda(), plain, lp, pd, records=rec)
         out = torch.zeros(P + 2, dtype=torch.float32, device="cuda")
         fwbf.scorer_grad(rec, Fn * T, lp, pd, 1.0, out=out)
         torch.cuda.synchronize()
         grads.append(out.cpu().numpy())
-        recs.append(rec.cpu().numpy().reshape(Fn, T, 32, 8).view(fwbf.RECORD_DTYPE)[..., 0])
+        recs.append(fwbf.records_host(rec))
     p_ = -(-g.N // G)
     nc = (-(-g.N // p_)) * k
     assert nc < 32
@@ -344,13 +344,13 @@ def test_checkpoint_learned_pass_frame_by_frame():
     y = synth.awgn_frames(o.N, Fn, synth.sigma_for(4.0, o.K / o.N), 77, cw, np.int8)
     lp = fwbf.LearnedParams(T, G, k, 16.0)
     plain = fwbf.DecodeParams(dtype=fwbf.I8, groups=8, max_iter=100)
-    rec = fwbf.record_buffer(Fn, T)
+    rec = fwbf.record_buffer(Fn, T, G, k)
     z, it, ok, lok = fwbf.decode_learned(g, torch.from_numpy(y).cuda(), plain, lp,
                                          torch.from_numpy(p).cuda(), records=rec)
     torch.cuda.synchronize()
     zg = O.unpack(z.cpu().numpy().view(np.uint32), o.N)
     itg, okg, lokg = it.cpu().numpy(), ok.cpu().numpy().astype(bool), lok.cpu().numpy().astype(bool)
-    rg = rec.cpu().numpy().reshape(Fn, T, 32, 8).view(fwbf.RECORD_DTYPE)[..., 0]
+    rg = fwbf.records_host(rec)
     zr, rr, okr, tr = R.learned_decode_batch(o, y, p.astype(np.float64), T, G, k, 16.0, 3)
     same_pass = (zg == zr).all(1) & (lokg == okr)
     # plain fallback for the frames the reference's learned pass leaves
