@@ -129,7 +129,7 @@ class Trainer:
 CODES = {
     "n1008": dict(code=(3, 6, 168, 2), int16=False, groups=32, plain_groups=8, batch=1 << 13,
                   ebn0_lo=3.0, ebn0_hi=5.0),
-    "n32400": dict(code=(3, 30, 1080, 5), int16=True, groups=512, plain_groups=64, batch=1 << 10,
+    "n32400": dict(code=(3, 30, 1080, 5), int16=True, groups=512, plain_groups=16, batch=1 << 10,
                    ebn0_lo=5.0, ebn0_hi=7.0),
 }
 

@@ -216,3 +216,64 @@ def test_wide_zero_scorer_falls_back_everywhere_n32400():
     assert np.array_equal(it.cpu().numpy(), itp.cpu().numpy()) and np.array_equal(ok.cpu().numpy(), okp.cpu().numpy())
     # only frames with a zero syndrome from the start count as learned successes
     assert int(lok.sum()) == int(((itp == 0) & (okp == 1)).sum())
+
+
+def test_checkpoint_n32400_frame_by_frame():
+    """The committed N = 32400 scorer (T = 16, 512 blocks, k = 1, int16 at
+    scale 256) on 24 frames at 6 dB, where its learned pass decides almost
+    every frame: z, rounds and flags frame by frame against the float64
+    learned pass plus the plain oracle fallback (G = 16); differences only
+    at near-ties, as for the random scorers."""
+    g = fwbf.Code.from_seed(3, 30, 1080, 5)
+    o = O.Code.from_seed(3, 30, 1080, 5)
+    ck = np.load(os.path.join(os.path.dirname(fwbf.__file__), "scorer_n32400_g512_t16.npz"), allow_pickle=False)
+    p = ck["params"].astype(np.float32)
+    T, G, k, Fn, pG = 16, 512, 1, 24, 16
+    y = _frames(o, Fn, 6.0, 13, fwbf.I16)
+    lp = fwbf.LearnedParams(T, G, k, 256.0)
+    plain = fwbf.DecodeParams(dtype=fwbf.I16, groups=pG, max_iter=100)
+    rec = fwbf.record_buffer(Fn, T, G, k)
+    print(f"N=32400 checkpoint: {Fn} frames", flush=True)
+    z, it, ok, lok = fwbf.decode_learned(g, torch.from_numpy(y).cuda(), plain, lp, torch.from_numpy(p).cuda(),
+                                         records=rec)
+    torch.cuda.synchronize()
+    zg = O.unpack(z.cpu().numpy().view(np.uint32), o.N)
+    itg, okg, lokg = it.cpu().numpy(), ok.cpu().numpy().astype(bool), lok.cpu().numpy().astype(bool)
+    zf, itf, okf, okr, tr = _reference(o, y, p, T, G, k, 256.0, pG)
+    rg = fwbf.records_host(rec)
+    for f in range(Fn):
+        assert _round0_matches(rg, tr, f), f
+    same = (zg == zf).all(1) & (itg == itf) & (okg == okf) & (lokg == okr)
+    for f in np.nonzero(~same)[0]:
+        rounds = R.trace_of_frame(tr, f)
+        decide = len(rounds) - 1
+        for t_, (cand, _) in enumerate(rounds):
+            n_gpu = rg[f, t_]["n"][rg[f, t_]["valid"] == 1].astype(np.int64)
+            if not np.array_equal(n_gpu, cand.ravel()[cand.ravel() >= 0]):
+                decide = t_ - 1
+                break
+        assert decide >= 0 and _near_tie(rounds[decide][1]), (f, decide)
+    print(f"N=32400 checkpoint: {int(same.sum())}/{Fn} identical, learned pass decoded {int(lokg.sum())} "
+          f"(reference {int(okr.sum())})", flush=True)
+    assert okr.sum() >= Fn // 2
+    assert same.mean() >= 0.9
+
+
+def test_checkpoint_n32400_beats_plain_at_6db():
+    """Ablation on 4096 fresh frames at 6 dB: the retrained learned decoder
+    (with fallback) has a lower frame error rate than plain FWBF at G = 16
+    (the autotuned G) by far more than three standard errors."""
+    g = fwbf.Code.from_seed(3, 30, 1080, 5)
+    ck = np.load(os.path.join(os.path.dirname(fwbf.__file__), "scorer_n32400_g512_t16.npz"), allow_pickle=False)
+    sc = torch.from_numpy(ck["params"].astype(np.float32)).cuda()
+    F = 4096
+    pool = torch.from_numpy(g.encode(71, 0, 64).view(np.int32)).cuda()
+    y = fwbf.channel(g.N, F, 0, pool, 8080, 6, float(synth.sigma_for(6.0, g.rate)), dtype=torch.int16, scale=256.0)
+    plain = fwbf.DecodeParams(dtype=fwbf.I16, groups=16, max_iter=100)
+    zl, itl, okl, lokl = fwbf.decode_learned(g, y, plain, fwbf.LearnedParams(16, 512, 1, 256.0), sc)
+    zp, itp, okp = fwbf.decode(g, y, plain)
+    rl = fwbf.count(g.N, zl, pool, 0, itl, okl, 116)["frame_err"] / F
+    rp = fwbf.count(g.N, zp, pool, 0, itp, okp, 100)["frame_err"] / F
+    print(f"N=32400 6 dB: FER learned {rl:.4f} plain {rp:.4f}", flush=True)
+    pooled = (rl + rp) / 2
+    assert rp - rl > 3 * np.sqrt(pooled * (1 - pooled) * 2 / F)
