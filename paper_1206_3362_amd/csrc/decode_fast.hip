@@ -145,6 +145,7 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
     uint32_t *zw = (uint32_t *)(wbase + a.o_z);
     uint32_t *syn = (uint32_t *)(wbase + a.o_syn);
     uint32_t *list = (uint32_t *)(wbase + a.o_list);
+    uint32_t *flips = (uint32_t *)(wbase + a.o_y);  // the rounds' winners (over the received values)
     uint32_t *sh = (uint32_t *)(smem + a.o_sh);
     uint16_t *slotof = (uint16_t *)(smem + a.o_slot);  // slot word of every bit (frame-independent)
 
@@ -167,6 +168,15 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
     // bit at position pos of this lane's block
     auto bit_at = [&](uint32_t pos) { return a.strided ? mul24(pos, (uint32_t)a.Geff) + g : gp + pos; };
     const int NW = (N + 31) >> 5;
+    // this lane's slots that hold a bit are its first nreal (positions pos0,
+    // pos0 + 1, ...), and the initial key of position pos0 + j is key0 - j:
+    // the bias (metric 0) above the reversed position (bias << idxb | idxmask - pos)
+    int nreal = 0;
+    if ((int)g < a.Geff) {
+        const int lim = min(a.p, a.strided ? (N - (int)g + a.Geff - 1) / a.Geff : N - (int)gp);
+        nreal = max(0, min(C, lim - (int)pos0));
+    }
+    const uint32_t key0 = (a.bias << a.idxb) | (a.idxmask - pos0);
 
     const FrameRange fr = xcd_frames_waves(a.F, FAST_WAVES, (int)wv);
     for (int64_t f = fr.first; f < fr.end; f += fr.step) {
@@ -204,11 +214,7 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
             uint4 v;
             uint32_t *vp = (uint32_t *)&v;
 #pragma unroll
-            for (int u = 0; u < 4; u++) {
-                const uint32_t pos = pos0 + kk + u;
-                const bool real = (int)g < a.Geff && (int)pos < a.p && (int)bit_at(pos) < N;
-                vp[u] = real ? ((a.bias << a.idxb) | (a.idxmask - pos)) : 0u;
-            }
+            for (int u = 0; u < 4; u++) vp[u] = kk + u < nreal ? key0 - (uint32_t)(kk + u) : 0u;
             ((uint4 *)keys)[chunk_of(lane, kk >> 2)] = v;
         }
         wave_sync();
@@ -300,12 +306,13 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
         } else {
             for (;;) {
                 // ---- Step 2: block maxima ----------------------------------
+                // every chunk read is issued before any is compared
+                uint4 kv[C / 4];
+#pragma unroll
+                for (int kk = 0; kk < C; kk += 4) kv[kk >> 2] = ((const uint4 *)keys)[chunk_of(lane, kk >> 2)];
                 uint32_t best = 0;
 #pragma unroll
-                for (int kk = 0; kk < C; kk += 4) {
-                    const uint4 v = ((const uint4 *)keys)[chunk_of(lane, kk >> 2)];
-                    best = max(best, max(max(v.x, v.y), max(v.z, v.w)));
-                }
+                for (int kk = 0; kk < C / 4; kk++) best = max(best, max(max(kv[kk].x, kv[kk].y), max(kv[kk].z, kv[kk].w)));
                 best = group_max(best, a.L);
                 const uint32_t val = best >> a.idxb;
                 const uint32_t n = bit_at(a.idxmask - (best & a.idxmask));
@@ -328,33 +335,36 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                     }
                 }
                 // ---- flip, toggle the syndrome, queue member updates -------
+                // the winners flip their bits and list them; then one lane per
+                // (winner, check) pair toggles the check (all lanes at once
+                // rather than DV toggles in turn on the winners' lanes)
                 const int rank = __popcll(fmask & ((1ull << lane) - 1));
-                uint32_t onesm = 0;
                 if (flip) {
                     atomicXor(&zw[n >> 5], 1u << (n & 31));
-                    const uint32_t j = mul24(n, a.rZ24) >> 20;  // block column: n / Z
-                    const uint32_t c = n - mul24(j, Z);
-                    uint32_t rr[DV], old[DV];
-#pragma unroll
-                    for (int t = 0; t < DV; t++) rr[t] = submod(c, sh[t * a.nb + j], Z);
-#pragma unroll
-                    for (int t = 0; t < DV; t++) {
-                        const uint32_t m = t * Z + rr[t];
-                        old[t] = atomicXor(&syn[m >> 5], 1u << (m & 31));
-                    }
-#pragma unroll
-                    for (int t = 0; t < DV; t++) {
-                        const uint32_t m = t * Z + rr[t];
-                        const uint32_t nb1 = ((old[t] >> (m & 31)) & 1u) ^ 1u;
-                        onesm |= nb1 << t;
-                        list[rank * DV + t] = rr[t] | ((uint32_t)t << 16) | (nb1 << 31);
-                    }
+                    flips[rank] = n;
                 }
-                // unsatisfied-check count: +1 per toggle to 1, -1 per toggle to 0
-                int sum_ones = 0;
-#pragma unroll
-                for (int t = 0; t < DV; t++) sum_ones += __popcll(__ballot((onesm >> t) & 1));
+                wave_sync();
                 const int nflip = __popcll(fmask);
+                const int ntog = nflip * DV;
+                int sum_ones = 0;  // toggles that leave their check unsatisfied
+                constexpr uint32_t DVM = ((1u << 16) + DV - 1) / DV;  // i / DV = (i * DVM) >> 16 for i < 2^12
+                for (int base = 0; base < ntog; base += 64) {
+                    const int i = base + (int)lane;
+                    uint32_t nb1 = 0;
+                    if (i < ntog) {
+                        const uint32_t u = mul24((uint32_t)i, DVM) >> 16;
+                        const uint32_t t = (uint32_t)i - mul24(u, (uint32_t)DV);
+                        const uint32_t nf = flips[u];
+                        const uint32_t j = mul24(nf, a.rZ24) >> 20;  // block column: nf / Z
+                        const uint32_t c = nf - mul24(j, Z);
+                        const uint32_t rr = submod(c, sh[mul24(t, (uint32_t)a.nb) + j], Z);
+                        const uint32_t m = mul24(t, Z) + rr;
+                        const uint32_t old = atomicXor(&syn[m >> 5], 1u << (m & 31));
+                        nb1 = ((old >> (m & 31)) & 1u) ^ 1u;
+                        list[i] = rr | (t << 16) | (nb1 << 31);
+                    }
+                    sum_ones += __popcll(__ballot(nb1));
+                }
                 weight += 2 * sum_ones - DV * nflip;
                 k += 1;
                 if (weight == 0) { okf = 1; break; }
@@ -526,7 +536,9 @@ int try_fast_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int
     off = 64 * C * 4;  // keys, then the rest of one wavefront's frame state
     a.o_chk = take(4 * c->M, 4);
     a.o_chkp = take(p->dtype == FWBF_I16 ? c->M : 0, 4);
-    a.o_y = take(esz * ((c->N + 15) / 16 * 16), 16);
+    // the received values, needed only while initialising; in the rounds the
+    // same bytes hold the flipped bits (Geff words)
+    a.o_y = take(std::max(esz * ((c->N + 15) / 16 * 16), 4 * a.Geff), 16);
     a.o_z = take(((c->N + 63) / 64) * 8, 8);
     a.o_syn = take(((c->M + 63) / 64) * 8, 8);
     a.o_list = take(4 * dv * a.Geff, 4);
