@@ -136,7 +136,9 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
     using Y = typename FT<DT>::Y;
     constexpr int QB = DC <= 2 ? 1 : DC <= 4 ? 2 : DC <= 8 ? 3 : DC <= 16 ? 4 : DC <= 32 ? 5 : 6;  // bits of q
     extern __shared__ __align__(16) unsigned char smem[];
-    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // the wavefront index is uniform across the wavefront: in a scalar
+    // register, so LDS base addresses derived from it are scalar too
+    const uint32_t lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     unsigned char *wbase = smem + a.o_wave0 + wv * a.wave_bytes;
     uint32_t *keys = (uint32_t *)wbase;
     uint32_t *chk = (uint32_t *)(wbase + a.o_chk);
@@ -248,27 +250,59 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                     // every LDS read of the check first (its members' values
                     // and slots), so that they are in flight together and
                     // none waits behind the atomic pushes below
+                    // member q is bit q Z + ((r + s_q) mod Z): the block
+                    // offsets q Z are uniform, only the rotation is per lane
 #pragma unroll
-                    for (int q = 0; q < DC; q++) nn[q] = q * Z + addmod(r, js[q], Z);
+                    for (int q = 0; q < DC; q++) nn[q] = addmod(r, js[q], Z);
 #pragma unroll
-                    for (int q = 0; q < DC; q++) yq[q] = (int)yv[nn[q]];
+                    for (int q = 0; q < DC; q++) yq[q] = (int)yv[q * Z + nn[q]];
 #pragma unroll
-                    for (int q = 0; q < DC; q++) sl[q] = slotof[nn[q]];
+                    for (int q = 0; q < DC; q++) sl[q] = slotof[q * Z + nn[q]];
                     // the two smallest keys |y| << QB | q: their magnitudes are
                     // min1 and min2 (with multiplicity), the first one's q is
                     // the lowest position holding min1
-                    uint32_t k1 = 0xFFFFFFFFu, k2 = 0xFFFFFFFFu, sx = 0;
+                    uint32_t k1 = 0xFFFFFFFFu, k2 = 0xFFFFFFFFu;
+                    if constexpr (DT == FWBF_I8 && DC == 6) {
+                        // int8 keys fit 16 bits (|y| <= 128): three pairs of
+                        // members in packed 16-bit lanes; per half the
+                        // smallest and second smallest of three, then the two
+                        // halves merged (second smallest of six = the smaller
+                        // of the larger first minimum and the smaller second
+                        // minimum)
+                        typedef short s16x2 __attribute__((ext_vector_type(2)));
+                        typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+                        u16x2 P[3];
+                        uint32_t px = 0;
 #pragma unroll
-                    for (int q = 0; q < DC; q++) {
-                        const int v = yq[q];
-                        const uint32_t av_ = (uint32_t)(v < 0 ? -v : v);
-                        av[q] = av_;
-                        sx ^= (uint32_t)v;  // bit 31: parity of the negative members
-                        const uint32_t key = (av_ << QB) | (uint32_t)q;
-                        k2 = min(k2, max(k1, key));
-                        k1 = min(k1, key);
+                        for (int j = 0; j < 3; j++) {
+                            const s16x2 v = {(short)yq[2 * j], (short)yq[2 * j + 1]};
+                            px ^= __builtin_bit_cast(uint32_t, v);
+                            const s16x2 av2 = __builtin_elementwise_max(v, -v);
+                            const u16x2 qq = {(unsigned short)(2 * j), (unsigned short)(2 * j + 1)};
+                            P[j] = (__builtin_bit_cast(u16x2, av2) << (unsigned short)QB) | qq;
+                            av[2 * j] = (uint32_t)av2.x;
+                            av[2 * j + 1] = (uint32_t)av2.y;
+                        }
+                        const u16x2 A = __builtin_elementwise_min(P[0], P[1]), B = __builtin_elementwise_max(P[0], P[1]);
+                        const u16x2 S1 = __builtin_elementwise_min(A, P[2]);
+                        const u16x2 S2 = __builtin_elementwise_min(B, __builtin_elementwise_max(A, P[2]));
+                        k1 = min((uint32_t)S1.x, (uint32_t)S1.y);
+                        k2 = min(max((uint32_t)S1.x, (uint32_t)S1.y), min((uint32_t)S2.x, (uint32_t)S2.y));
+                        par = ((px >> 15) ^ (px >> 31)) & 1u;  // parity of the negative members
+                    } else {
+                        uint32_t sx = 0;
+#pragma unroll
+                        for (int q = 0; q < DC; q++) {
+                            const int v = yq[q];
+                            const uint32_t av_ = (uint32_t)(v < 0 ? -v : v);
+                            av[q] = av_;
+                            sx ^= (uint32_t)v;  // bit 31: parity of the negative members
+                            const uint32_t key = (av_ << QB) | (uint32_t)q;
+                            k2 = min(k2, max(k1, key));
+                            k1 = min(k1, key);
+                        }
+                        par = sx >> 31;
                     }
-                    par = sx >> 31;
                     const uint32_t m1 = k1 >> QB, pos = k1 & ((1u << QB) - 1);
                     const uint32_t m2 = DC < 2 ? 0u : (k2 >> QB);
                     const uint32_t m = i * Z + r;
