@@ -56,7 +56,7 @@ struct FastArgs {
     // LDS offsets in bytes
     // LDS: tables shared by the workgroup (o_sh, o_slot), then one region of
     // wave_bytes per wavefront (offsets relative to the region; keys at 0)
-    int o_chk, o_chkp, o_y, o_z, o_syn, o_list, o_sh, o_slot, o_wave0, wave_bytes, lds_bytes;
+    int o_chk, o_chkp, o_y, o_z, o_syn, o_sh, o_slot, o_wave0, wave_bytes, lds_bytes;
 };
 
 __device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t mag, uint32_t mask)
@@ -146,7 +146,6 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
     Y *yv = (Y *)(wbase + a.o_y);
     uint32_t *zw = (uint32_t *)(wbase + a.o_z);
     uint32_t *syn = (uint32_t *)(wbase + a.o_syn);
-    uint32_t *list = (uint32_t *)(wbase + a.o_list);
     uint32_t *flips = (uint32_t *)(wbase + a.o_y);  // the rounds' winners (over the received values)
     uint32_t *sh = (uint32_t *)(smem + a.o_sh);
     uint16_t *slotof = (uint16_t *)(smem + a.o_slot);  // slot word of every bit (frame-independent)
@@ -368,10 +367,12 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                         break;
                     }
                 }
-                // ---- flip, toggle the syndrome, queue member updates -------
+                // ---- flip, toggle the syndrome, update the member metrics --
                 // the winners flip their bits and list them; then one lane per
-                // (winner, check) pair toggles the check (all lanes at once
-                // rather than DV toggles in turn on the winners' lanes)
+                // (winner, check) pair toggles the check and adds +-2 a_den w
+                // to the metrics of the check's members, the sign given by
+                // the check's new bit (two winners toggling one check are
+                // serialised by the atomics: their changes cancel exactly)
                 const int rank = __popcll(fmask & ((1ull << lane) - 1));
                 if (flip) {
                     atomicXor(&zw[n >> 5], 1u << (n & 31));
@@ -391,11 +392,29 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                         const uint32_t nf = flips[u];
                         const uint32_t j = mul24(nf, a.rZ24) >> 20;  // block column: nf / Z
                         const uint32_t c = nf - mul24(j, Z);
-                        const uint32_t rr = submod(c, sh[mul24(t, (uint32_t)a.nb) + j], Z);
+                        const uint32_t *st = sh + mul24(t, (uint32_t)a.nb);
+                        const uint32_t rr = submod(c, st[j], Z);
                         const uint32_t m = mul24(t, Z) + rr;
                         const uint32_t old = atomicXor(&syn[m >> 5], 1u << (m & 31));
                         nb1 = ((old >> (m & 31)) & 1u) ^ 1u;
-                        list[i] = rr | (t << 16) | (nb1 << 31);
+                        // the check's two weights and the position of its minimum
+                        uint32_t w1, w2, pos;
+                        if constexpr (DT == FWBF_I8) {
+                            const uint32_t cw = chk[m];
+                            w1 = cw & 0xFF; w2 = (cw >> 8) & 0xFF; pos = (cw >> 16) & 0xFF;
+                        } else {
+                            const uint32_t cw = chk[m];
+                            w1 = cw & 0xFFFF; w2 = cw >> 16; pos = chkp[m];
+                        }
+                        const uint32_t e1 = mul24(2u * (uint32_t)a.aden, w1) << a.idxb;
+                        const uint32_t e2 = a.imwbf ? mul24(2u * (uint32_t)a.aden, w2) << a.idxb : e1;
+                        const uint32_t d1 = nb1 ? e1 : 0u - e1, d2 = nb1 ? e2 : 0u - e2;
+                        // every member's slot first, then the adds
+                        uint32_t sl[DC];
+#pragma unroll
+                        for (int q = 0; q < DC; q++) sl[q] = slotof[mul24((uint32_t)q, Z) + addmod(rr, st[q], Z)];
+#pragma unroll
+                        for (int q = 0; q < DC; q++) atomicAdd(&keys[sl[q]], pos == (uint32_t)q ? d2 : d1);
                     }
                     sum_ones += __popcll(__ballot(nb1));
                 }
@@ -403,35 +422,6 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                 k += 1;
                 if (weight == 0) { okf = 1; break; }
                 if (k == a.max_iter) break;
-                wave_sync();
-                // ---- member metric updates ---------------------------------
-                // (check, member) tasks, 64 per pass.  ntask <= 64 blocks *
-                // DV * DC, and t / DC = (t * DM) >> 16 is exact for
-                // t < 65536 / (DM * DC - 65536) (>= 1170 for DC <= 56)
-                const int ntask = nflip * DV * DC;
-                constexpr uint32_t DM = ((1u << 16) + DC - 1) / DC;
-                static_assert(DC <= 56 && 64 * DV * DC < 65536 / (DM * DC - 65536), "task index range");
-                for (int base = 0; base < ntask; base += 64) {
-                    const int t = base + (int)lane;
-                    if (t < ntask) {
-                        const uint32_t u = mul24((uint32_t)t, DM) >> 16;
-                        const uint32_t q = (uint32_t)t - mul24(u, (uint32_t)DC);
-                        const uint32_t e = list[u];
-                        const uint32_t r = e & 0xFFFFu, i = (e >> 16) & 0x7FFFu;
-                        const uint32_t m = mul24(i, Z) + r;
-                        const uint32_t nq = mul24(q, Z) + addmod(r, sh[mul24(i, (uint32_t)a.nb) + q], Z);
-                        uint32_t w;
-                        if constexpr (DT == FWBF_I8) {
-                            const uint32_t cw = chk[m];
-                            w = (a.imwbf && ((cw >> 16) & 0xFF) == q) ? ((cw >> 8) & 0xFF) : (cw & 0xFF);
-                        } else {
-                            const uint32_t cw = chk[m];
-                            w = (a.imwbf && chkp[m] == q) ? (cw >> 16) : (cw & 0xFFFF);
-                        }
-                        const uint32_t dm = mul24(2u * (uint32_t)a.aden, w) << a.idxb;
-                        atomicAdd(&keys[slotof[nq]], (e >> 31) ? dm : 0u - dm);
-                    }
-                }
                 wave_sync();
             }
         }
@@ -575,7 +565,6 @@ int try_fast_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int
     a.o_y = take(std::max(esz * ((c->N + 15) / 16 * 16), 4 * a.Geff), 16);
     a.o_z = take(((c->N + 63) / 64) * 8, 8);
     a.o_syn = take(((c->M + 63) / 64) * 8, 8);
-    a.o_list = take(4 * dv * a.Geff, 4);
     a.wave_bytes = (off + 15) / 16 * 16;
     a.lds_bytes = a.o_wave0 + FAST_WAVES * a.wave_bytes;
     if (a.lds_bytes > 160 * 1024) return 0;
