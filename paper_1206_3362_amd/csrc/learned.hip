@@ -252,7 +252,7 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
     int8_t *yv = (int8_t *)(wbase + a.o_y);
     uint32_t *zw = (uint32_t *)(wbase + a.o_z);
     uint32_t *syn = (uint32_t *)(wbase + a.o_syn);
-    uint32_t *list = (uint32_t *)(wbase + a.o_list);
+    uint32_t *list = (uint32_t *)(wbase + a.o_list);  // the bits flipped in a round
     uint4 *cand = (uint4 *)(wbase + a.o_cand);  // 32 proposals: n, slot word
     uint32_t *sh = (uint32_t *)(smem + a.o_sh);
     uint16_t *slotof = (uint16_t *)(smem + a.o_slot);  // slot word of every bit
@@ -518,56 +518,48 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
             const unsigned long long dmask = __ballot(blead && cur != prv);
             prv = blead ? cur : prv;
             if (fmask == 0 || dmask == 0) break;  // no flip, or the previous round's flips: stop
+            // the winners flip their bits and list them; then one lane per
+            // (winner, check) pair toggles the check and adds +-(2w, 1) to S
+            // and u of the check's members, the sign given by the check's new
+            // bit (toggles of one check by two winners cancel exactly)
             const int rank = __popcll(fmask & ((1ull << lane) - 1));
-            uint32_t onesm = 0;
             if (flip) {
-                const uint32_t n = nsel;
-                atomicXor(&zw[n >> 5], 1u << (n & 31));
-                const uint32_t jb = mul24(n, a.rZ24) >> 22;  // block column: n / Z
-                const uint32_t c = n - mul24(jb, Z);
-                uint32_t rr[DV], old[DV];
-#pragma unroll
-                for (int tt = 0; tt < DV; tt++) rr[tt] = submod(c, sh[tt * a.nb + jb], Z);
-#pragma unroll
-                for (int tt = 0; tt < DV; tt++) {
-                    const uint32_t m = tt * Z + rr[tt];
-                    old[tt] = atomicXor(&syn[m >> 5], 1u << (m & 31));
-                }
-#pragma unroll
-                for (int tt = 0; tt < DV; tt++) {
-                    const uint32_t m = tt * Z + rr[tt];
-                    const uint32_t nb1 = ((old[tt] >> (m & 31)) & 1u) ^ 1u;
-                    onesm |= nb1 << tt;
-                    list[rank * DV + tt] = rr[tt] | ((uint32_t)tt << 16) | (nb1 << 31);
-                }
+                atomicXor(&zw[nsel >> 5], 1u << (nsel & 31));
+                list[rank] = nsel;
             }
-            int sum_ones = 0;
-#pragma unroll
-            for (int tt = 0; tt < DV; tt++) sum_ones += __popcll(__ballot((onesm >> tt) & 1));
+            lwave_sync();
             const int nflip = __popcll(fmask);
+            const int ntog = nflip * DV;
+            int sum_ones = 0;  // toggles that leave their check unsatisfied
+            constexpr uint32_t DVM = ((1u << 16) + DV - 1) / DV;  // i / DV = (i * DVM) >> 16 for i < 2^12
+            for (int base = 0; base < ntog; base += 64) {
+                const int i = base + (int)lane;
+                uint32_t nb1 = 0;
+                if (i < ntog) {
+                    const uint32_t u = mul24((uint32_t)i, DVM) >> 16;
+                    const uint32_t tt = (uint32_t)i - mul24(u, (uint32_t)DV);
+                    const uint32_t n = list[u];
+                    const uint32_t jb = mul24(n, a.rZ24) >> 22;  // block column: n / Z
+                    const uint32_t c = n - mul24(jb, Z);
+                    const uint32_t *st = sh + mul24(tt, (uint32_t)a.nb);
+                    const uint32_t rr = submod(c, st[jb], Z);
+                    const uint32_t m = mul24(tt, Z) + rr;
+                    const uint32_t old = atomicXor(&syn[m >> 5], 1u << (m & 31));
+                    nb1 = ((old >> (m & 31)) & 1u) ^ 1u;
+                    const uint32_t cwd = chk[m];
+                    const uint32_t e1 = ((2u * (cwd & 0xFFu)) << 16) + 1u, e2 = ((2u * ((cwd >> 8) & 0xFFu)) << 16) + 1u;
+                    const uint32_t d1 = nb1 ? e1 : 0u - e1, d2 = nb1 ? e2 : 0u - e2;
+                    const uint32_t pos = (cwd >> 16) & 0xFFu;
+                    uint32_t sl[DC];
+#pragma unroll
+                    for (int q = 0; q < DC; q++) sl[q] = slotof[mul24((uint32_t)q, Z) + addmod(rr, st[q], Z)];
+#pragma unroll
+                    for (int q = 0; q < DC; q++) atomicAdd(&slots[sl[q]], pos == (uint32_t)q ? d2 : d1);
+                }
+                sum_ones += __popcll(__ballot(nb1));
+            }
             weight += 2 * sum_ones - DV * nflip;
             t += 1;
-            lwave_sync();
-            // (check, member) tasks, 64 per pass: ntask <= 32 blocks * DV * DC,
-            // and t / DC = (t * DM) >> 16 is exact for t < 65536 / (DM * DC - 65536)
-            const int ntask = nflip * DV * DC;
-            constexpr uint32_t DM = ((1u << 16) + DC - 1) / DC;
-            static_assert(32 * DV * DC < 65536 / (DM * DC - 65536), "task index range");
-            for (int base = 0; base < ntask; base += 64) {
-                const int tk = base + (int)lane;
-                if (tk < ntask) {
-                    const uint32_t u = mul24((uint32_t)tk, DM) >> 16;
-                    const uint32_t q = (uint32_t)tk - mul24(u, (uint32_t)DC);
-                    const uint32_t e = list[u];
-                    const uint32_t r = e & 0xFFFFu, i = (e >> 16) & 0x7FFFu;
-                    const uint32_t m = mul24(i, Z) + r;
-                    const uint32_t nq = mul24(q, Z) + addmod(r, sh[mul24(i, (uint32_t)a.nb) + q], Z);
-                    const uint32_t cwd = chk[m];
-                    const uint32_t w = (((cwd >> 16) & 0xFF) == q) ? ((cwd >> 8) & 0xFF) : (cwd & 0xFF);
-                    const uint32_t d = (e >> 31) ? ((2u * w) << 16) + 1u : 0u - (((2u * w) << 16) + 1u);
-                    atomicAdd(&slots[slotof[nq]], (uint32_t)d);
-                }
-            }
             lwave_sync();
         }
         lwave_sync();
