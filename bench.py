@@ -45,6 +45,8 @@ def parse():
                     help="target CPU time of the oracle baseline sample (0 = skip)")
     ap.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "traffic_decode_n1008_i8_4db.json"))
     ap.add_argument("--learned", type=int, default=1, help="also time the learned decoder (1/0)")
+    ap.add_argument("--n32400", type=int, default=1,
+                    help="also compare learned and plain FWBF on the N=32400 int16 code at 6 and 7 dB (1/0)")
     ap.add_argument("--fer-table", type=int, default=1,
                     help="also time plain FWBF at G = 1, 2, 4, 8 and SINGLE on the same frames (1/0)")
     ap.add_argument("--scorer", type=str,
@@ -193,6 +195,14 @@ def main():
         out["learned"] = learned_leg(code, ys, pool, params, a, N, F, ms_step, c)
     if a.fer_table:
         out["fer_vs_gbps"] = fer_table(code, ys, pool, params, a, N, F, out)
+    if a.n32400:
+        # the high-rate code, where the retrained learned decoder is both
+        # faster and better than plain FWBF (6 and 7 dB, 3 timed steps each)
+        res, tuned, lp = n32400_compare(3, 1, (6.0, 7.0))
+        out["n32400_i16"] = {"points": res, "plain_G_tuned": int(tuned["G"]),
+                             "workload": "N=32400 (3,30) QC rate 0.9, int16 x256, K_max=100, 2^18 frames per point; "
+                                         "learned FWBF (scorer_n32400_g512_t16.npz, plain fallback) vs plain FWBF "
+                                         "at the autotuned G"}
     if a.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(code, ys[0], params, a, N)
     print(json.dumps(out), flush=True)
@@ -394,12 +404,13 @@ def other_workload(a):
     print(json.dumps(line), flush=True)
 
 
-def n32400_i16(a, line):
+def n32400_compare(steps, warmup, ebn0s):
     """The (3,30) rate-0.9 code, N = 32400, int16 frames (scale 256), 2^18
     frames per Eb/N0 point: plain FWBF at the autotuned G (FER-constrained
     against the reference G = 64 on frames with Eb/N0 uniform in [5, 7] dB)
     beside the learned decoder (checkpoint retrained on this code, plain
-    fallback at the same G), same frames, same timing protocol."""
+    fallback at the same G), same frames, same timing protocol.  Returns
+    (points, tuning result, learned parameters)."""
     import numpy as np
     import torch
 
@@ -420,12 +431,12 @@ def n32400_i16(a, line):
     ok = torch.empty(F, dtype=torch.uint8, device="cuda")
     lok = torch.empty(F, dtype=torch.uint8, device="cuda")
     res = {}
-    for eb in (5.0, 6.0, 7.0):
+    for eb in ebn0s:
         y = fwbf.channel(N, F, 0, pool, 900, int(eb), float(synth.sigma_for(eb, code.rate)),
                          dtype=torch.int16, scale=256.0)
-        ms_p = _timed(lambda: fwbf.decode_into(code, y, plain, z, it, ok), a.steps, a.warmup)
+        ms_p = _timed(lambda: fwbf.decode_into(code, y, plain, z, it, ok), steps, warmup)
         rp = fwbf.count(N, z, pool, 0, it, ok, 100)
-        ms_l = _timed(lambda: fwbf.decode_learned_into(code, y, plain, lp, sc, z, it, ok, lok), a.steps, a.warmup)
+        ms_l = _timed(lambda: fwbf.decode_learned_into(code, y, plain, lp, sc, z, it, ok, lok), steps, warmup)
         rl = fwbf.count(N, z, pool, 0, it, ok, 100 + lp.rounds)
         fp, fl = rp["frame_err"] / F, rl["frame_err"] / F
         pooled = (rp["frame_err"] + rl["frame_err"]) / (2 * F)
@@ -437,17 +448,23 @@ def n32400_i16(a, line):
             learned_fer_at_or_below_plain=bool(fl <= fp + 3.0 * np.sqrt(pooled * (1 - pooled) * 2.0 / F)),
             learned_over_plain_gbps=round(ms_p / ms_l, 3))
         del y
+    return res, tuned, lp
+
+
+def n32400_i16(a, line):
+    """Plain vs learned FWBF on the N = 32400 int16 code at 5, 6 and 7 dB."""
+    res, tuned, lp = n32400_compare(a.steps, a.warmup, (5.0, 6.0, 7.0))
     line.update(metric="decoded Gb/s, N=32400 (3,30) QC rate 0.9, int16: learned FWBF vs plain FWBF (tuned G)",
                 value=res["6dB"]["learned"]["gbps"], ms_per_step=res["6dB"]["learned"]["ms"], dtype="int32",
                 points=res,
-                tuned={"G": G, "G_ref": 64, "fer_ref": tuned["fer_ref"],
+                tuned={"G": int(tuned["G"]), "G_ref": 64, "fer_ref": tuned["fer_ref"],
                        "table": [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items()}
                                  for r in tuned["table"]]},
                 scorer={"file": "scorer_n32400_g512_t16.npz", "rounds": lp.rounds, "groups": lp.groups,
                         "topk": lp.topk},
                 config={"workload": "N=32400 (3,30) QC Z=1080 K=29162, int16 x256, K_max=100, 2^18 frames per "
                                     "point, 5/6/7 dB; plain FWBF at the autotuned G and learned FWBF (plain "
-                                    "fallback) on the same frames", "frames": F})
+                                    "fallback) on the same frames", "frames": 1 << 18})
 
 
 # averaged rounds printed in Tab. 1 (K_max = 10, EG(1023,781), 3.0/3.5/4.0/4.5 dB)
