@@ -606,16 +606,19 @@ struct WideArgs {
     const float *params;
     const uint32_t *shift;  // 3 x nb raw shifts
     int N, M, Z, nb;
-    uint32_t magZ, maskZ, magP, maskP, magD, maskD;  // n / Z, n / p, n / nb
+    // quotients by Z, p and nb as 24-bit multiplies: x / d = (x * r) >> s for
+    // every x below the kernel's bound (checked exhaustively on the host)
+    uint32_t rZ, sZ, rP, sP, rD, sD;
     int p, L, logL, Lc, B, Geff, k, T, NC, tpr;
+    int pref;   // rows are whole 4-byte words: loaded as words, the next one ahead
     float A, invA, dv;
     int o_chk, o_chkp, o_z, o_syn, o_cand, o_list, o_ctl, o_sh, o_net, o_netw, lds_bytes;
 };
 
 __device__ __forceinline__ uint32_t wide_slot(const WideArgs &a, uint32_t n)
 {
-    const uint32_t g = fdiv(n, a.magP, a.maskP), pos = n - g * (uint32_t)a.p;
-    return g * (uint32_t)a.Lc + (pos ^ ((g & (uint32_t)(a.B - 1)) << a.logL));
+    const uint32_t g = mul24(n, a.rP) >> a.sP, pos = n - mul24(g, (uint32_t)a.p);
+    return mul24(g, (uint32_t)a.Lc) + (pos ^ ((g & (uint32_t)(a.B - 1)) << a.logL));
 }
 
 template <int DT>
@@ -694,76 +697,136 @@ __global__ __launch_bounds__(WIDE_T) void learned_wide_kernel(WideArgs a)
     const int Nr = (N + 63) & ~63, Mr = (M + 63) & ~63;
 
     const FrameRange fr = xcd_frames(a.F);
+    // The next frame's row is loaded into registers while this frame
+    // decodes (rows of at most PW * WIDE_T words): with one frame per compute
+    // unit nothing else would hide the memory latency.
+    constexpr int PW = 16;
+    const int nwords = (N * (int)sizeof(Y)) >> 2;
+    uint32_t pre[PW];
+    bool have = false;  // pre[] holds this frame's row
     for (int64_t f = fr.first; f < fr.end; f += fr.step) {
         const Y *yrow = (const Y *)a.y + f * a.stride;
         if (tid == 0) { ctl[CW_WEIGHT] = 0; ctl[CW_FLAGS] = 0; ctl[CW_NTOG] = 0; }
-        // ---- z_0 = [y < 0] and the magnitude field of every slot (S = u = 0)
-        constexpr int UNR = 4;
-        for (int n0 = tid; n0 < Nr; n0 += UNR * WIDE_T) {
-            Y v[UNR];
+        {
+            // ---- the row into LDS, over the slots (y of bit n at element n)
+            uint32_t *stw = slots;
+            const Y *sty = (const Y *)slots;
+            if (have) {
 #pragma unroll
-            for (int u = 0; u < UNR; u++) {
-                const int n = n0 + u * WIDE_T;
-                v[u] = n < N ? yrow[n] : (Y)0;
+                for (int i = 0; i < PW; i++) {
+                    const int w = tid + i * WIDE_T;
+                    if (w < nwords) stw[w] = pre[i];
+                }
+            } else if (a.pref) {
+                const uint32_t *src = (const uint32_t *)yrow;
+#pragma unroll
+                for (int i = 0; i < PW; i++) {
+                    const int w = tid + i * WIDE_T;
+                    pre[i] = w < nwords ? src[w] : 0u;
+                }
+#pragma unroll
+                for (int i = 0; i < PW; i++) {
+                    const int w = tid + i * WIDE_T;
+                    if (w < nwords) stw[w] = pre[i];
+                }
+            } else {
+                for (int n0 = tid; n0 < N; n0 += 8 * WIDE_T) {
+                    Y v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; u++) v[u] = n0 + u * WIDE_T < N ? yrow[n0 + u * WIDE_T] : (Y)0;
+#pragma unroll
+                    for (int u = 0; u < 8; u++)
+                        if (n0 + u * WIDE_T < N) ((Y *)slots)[n0 + u * WIDE_T] = v[u];
+                }
             }
-#pragma unroll
-            for (int u = 0; u < UNR; u++) {
-                const int n = n0 + u * WIDE_T;
-                if (n >= Nr) break;  // uniform per wavefront (Nr is a multiple of 64)
-                const unsigned long long b = __ballot(v[u] < 0);
+            __syncthreads();
+            // ---- z_0 = [y < 0]
+            for (int n = tid; n - (int)lane < Nr; n += WIDE_T) {  // uniform per wavefront
+                const unsigned long long b = __ballot(n < N && sty[n] < (Y)0);
                 if (lane == 0) {
                     zw[n >> 5] = (uint32_t)b;
                     zw[(n >> 5) + 1] = (uint32_t)(b >> 32);
                 }
-                if (n < N) {
+            }
+            // ---- check minima and syndrome s_0 from the staged row
+            for (int m0 = tid; m0 < Mr; m0 += WIDE_T) {
+                bool par = false;
+                if (m0 < M) {
+                    const uint32_t i = mul24((uint32_t)m0, a.rZ) >> a.sZ, r = m0 - mul24(i, Z);
+                    const uint32_t *si = sh + i * dc;
+                    // the two smallest keys |y| << 5 | q: min1 and min2 (with
+                    // multiplicity) and the lowest position holding min1
+                    uint32_t k1 = 0xFFFFFFFFu, k2 = 0xFFFFFFFFu, sx = 0;
+                    constexpr int QL = 8;
+                    for (int q0 = 0; q0 < dc; q0 += QL) {
+                        int v[QL];
+#pragma unroll
+                        for (int u = 0; u < QL; u++) {
+                            const int q = q0 + u < dc ? q0 + u : dc - 1;
+                            v[u] = sty[mul24((uint32_t)q, Z) + addmod(r, si[q], Z)];
+                        }
+#pragma unroll
+                        for (int u = 0; u < QL; u++) {
+                            if (q0 + u >= dc) break;
+                            sx ^= (uint32_t)v[u];  // bit 31: parity of the negative members
+                            const uint32_t key = ((uint32_t)(v[u] < 0 ? -v[u] : v[u]) << 5) | (uint32_t)(q0 + u);
+                            k2 = min(k2, max(k1, key));
+                            k1 = min(k1, key);
+                        }
+                    }
+                    par = (sx >> 31) != 0;
+                    chk[m0] = (k1 >> 5) | ((k2 >> 5) << 16);
+                    chkp[m0] = (uint8_t)(k1 & 31u);
+                }
+                const unsigned long long b = __ballot(par);
+                if (lane == 0) {
+                    syn[m0 >> 5] = (uint32_t)b;
+                    syn[(m0 >> 5) + 1] = (uint32_t)(b >> 32);
+                    if (b) atomicAdd(&ctl[CW_WEIGHT], __popcll(b));
+                }
+            }
+            __syncthreads();
+            // ---- slot words: S and u gathered from each bit's three checks,
+            // |y| read again from the row in global memory (it is in L2): the
+            // staged copy is dead once the slots take its place
+            for (int n0 = tid; n0 < N; n0 += 8 * WIDE_T) {
+                Y v[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++) v[u] = n0 + u * WIDE_T < N ? yrow[n0 + u * WIDE_T] : (Y)0;
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    const uint32_t n = n0 + u * WIDE_T;
+                    if ((int)n >= N) break;
                     const int x = v[u];
-                    slots[wide_slot(a, n)] = min((uint32_t)(x < 0 ? -x : x), WSAT) << 2;
+                    const uint32_t av = (uint32_t)(x < 0 ? -x : x);
+                    const uint32_t jb = mul24(n, a.rZ) >> a.sZ, c = n - mul24(jb, Z);
+                    int S = 0;
+                    uint32_t uu = 0;
+#pragma unroll
+                    for (int tt = 0; tt < 3; tt++) {
+                        const uint32_t m = mul24((uint32_t)tt, Z) + submod(c, sh[tt * dc + jb], Z);
+                        const uint32_t cw = chk[m];
+                        const int w = (int)(chkp[m] == jb ? (cw >> 16) : (cw & 0xFFFFu));
+                        const uint32_t sb = (syn[m >> 5] >> (m & 31)) & 1u;
+                        S += sb ? w : -w;
+                        uu += sb;
+                    }
+                    slots[wide_slot(a, n)] = ((uint32_t)S << 14) | (min(av, WSAT) << 2) | uu;
                 }
             }
-        }
-        __syncthreads();
-        // ---- check minima, syndrome s_0, initial S and u pushed to the members
-        for (int m0 = tid; m0 < Mr; m0 += WIDE_T) {
-            bool par = false;
-            if (m0 < M) {
-                const uint32_t i = fdiv(m0, a.magZ, a.maskZ), r = m0 - i * Z;
-                const uint32_t *si = sh + i * dc;
-                // the two smallest keys |y| << 5 | q: min1 and min2 (with
-                // multiplicity) and the lowest position holding min1
-                uint32_t k1 = 0xFFFFFFFFu, k2 = 0xFFFFFFFFu, sx = 0;
-                for (int q0 = 0; q0 < dc; q0 += 4) {
-                    int v[4];
+            __syncthreads();
+            // ---- the next frame's row, loaded while this one decodes
+            have = false;
+            if (a.pref && f + fr.step < fr.end) {
+                const uint32_t *src = (const uint32_t *)((const Y *)a.y + (f + fr.step) * a.stride);
 #pragma unroll
-                    for (int u = 0; u < 4; u++) {
-                        const int q = q0 + u < dc ? q0 + u : dc - 1;
-                        v[u] = yrow[q * Z + addmod(r, si[q], Z)];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; u++) {
-                        if (q0 + u >= dc) break;
-                        sx ^= (uint32_t)v[u];  // bit 31: parity of the negative members
-                        const uint32_t key = ((uint32_t)(v[u] < 0 ? -v[u] : v[u]) << 5) | (uint32_t)(q0 + u);
-                        k2 = min(k2, max(k1, key));
-                        k1 = min(k1, key);
-                    }
+                for (int i = 0; i < PW; i++) {
+                    const int w = tid + i * WIDE_T;
+                    pre[i] = w < nwords ? src[w] : 0u;
                 }
-                par = (sx >> 31) != 0;
-                const uint32_t m1 = k1 >> 5, m2 = k2 >> 5, pos = k1 & 31u;
-                chk[m0] = m1 | (m2 << 16);
-                chkp[m0] = (uint8_t)pos;
-                const uint32_t d1 = ((uint32_t)(par ? (int)m1 : -(int)m1) << 14) + (par ? 1u : 0u);
-                const uint32_t d2 = ((uint32_t)(par ? (int)m2 : -(int)m2) << 14) + (par ? 1u : 0u);
-                for (int q = 0; q < dc; q++)
-                    atomicAdd(&slots[wide_slot(a, q * Z + addmod(r, si[q], Z))], (uint32_t)q == pos ? d2 : d1);
-            }
-            const unsigned long long b = __ballot(par);
-            if (lane == 0) {
-                syn[m0 >> 5] = (uint32_t)b;
-                syn[(m0 >> 5) + 1] = (uint32_t)(b >> 32);
-                if (b) atomicAdd(&ctl[CW_WEIGHT], __popcll(b));
+                have = true;
             }
         }
-        __syncthreads();
 
         int t = 0, okf = 0, rec_end = 0;
         uint32_t prv = NONE;
@@ -874,10 +937,10 @@ __global__ __launch_bounds__(WIDE_T) void learned_wide_kernel(WideArgs a)
                     if (flip) {
                         const uint32_t n = nsel;
                         atomicXor(&zw[n >> 5], 1u << (n & 31));
-                        const uint32_t jb = fdiv(n, a.magZ, a.maskZ), cc = n - jb * Z;
+                        const uint32_t jb = mul24(n, a.rZ) >> a.sZ, cc = n - mul24(jb, Z);
                         uint32_t mm[3], old[3];
 #pragma unroll
-                        for (int tt = 0; tt < 3; tt++) mm[tt] = tt * Z + submod(cc, sh[tt * dc + jb], Z);
+                        for (int tt = 0; tt < 3; tt++) mm[tt] = mul24((uint32_t)tt, Z) + submod(cc, sh[tt * dc + jb], Z);
 #pragma unroll
                         for (int tt = 0; tt < 3; tt++) old[tt] = atomicXor(&syn[mm[tt] >> 5], 1u << (mm[tt] & 31));
 #pragma unroll
@@ -899,11 +962,11 @@ __global__ __launch_bounds__(WIDE_T) void learned_wide_kernel(WideArgs a)
             // ---- +-(2w, 1) to S and u of every member of every toggled check
             const int ntask = ctl[CW_NTOG] * dc;
             for (int id = tid; id < ntask; id += WIDE_T) {
-                const uint32_t e0 = fdiv(id, a.magD, a.maskD), q = id - e0 * dc;
+                const uint32_t e0 = mul24((uint32_t)id, a.rD) >> a.sD, q = id - mul24(e0, (uint32_t)dc);
                 const uint32_t ent = list[e0];
                 const uint32_t m = ent & 0x7FFFFFFFu;
-                const uint32_t i = fdiv(m, a.magZ, a.maskZ), r = m - i * Z;
-                const uint32_t n = q * Z + addmod(r, sh[i * dc + q], Z);
+                const uint32_t i = mul24(m, a.rZ) >> a.sZ, r = m - mul24(i, Z);
+                const uint32_t n = mul24(q, Z) + addmod(r, sh[mul24(i, (uint32_t)dc) + q], Z);
                 const uint32_t cwd = chk[m];
                 const uint32_t w = chkp[m] == q ? (cwd >> 16) : (cwd & 0xFFFFu);
                 const uint32_t d = ((2u * w) << 14) + 1u;
@@ -1163,6 +1226,22 @@ void magic_l(uint32_t d, uint32_t *mag, uint32_t *mask)
     *mag = (uint32_t)(((1ULL << 32) + d - 1) / d);
     *mask = 0;
 }
+// r, s with x / d == (x * r) >> s for every x < limit, the product below 2^32
+// and r below 2^24 (a full-rate 24-bit multiply); checked for every x
+bool recip24(uint32_t d, uint32_t limit, uint32_t *r, uint32_t *s)
+{
+    for (int sh = 31; sh >= 0; sh--) {
+        const uint64_t rr = ((1ull << sh) + d - 1) / d;
+        if (rr >= (1u << 24) || (uint64_t)(limit - 1) * rr >= (1ull << 32)) continue;
+        bool ok = true;
+        for (uint32_t x = 0; x < limit && ok; x++) ok = (uint32_t)(((uint64_t)x * rr) >> sh) == x / d;
+        if (!ok) continue;
+        *r = (uint32_t)rr;
+        *s = (uint32_t)sh;
+        return true;
+    }
+    return false;
+}
 int check_lp(const fwbf_learned_params *lp)
 {
     if (!lp) return fail(FWBF_E_INVALID, "null learned params");
@@ -1212,9 +1291,10 @@ int learned_wide(const fwbf_code *code, const fwbf_params *plain, const fwbf_lea
     if (!C) return fail(FWBF_E_UNSUPPORTED, "blocks do not fit one workgroup of 1024 threads");
     a.L = L; a.logL = ilog2l(L); a.Lc = L * C; a.B = 64 / L;
     a.N = code->N; a.M = code->M; a.Z = code->Z; a.nb = code->nb;
-    magic_l(a.Z, &a.magZ, &a.maskZ);
-    magic_l(a.p, &a.magP, &a.maskP);
-    magic_l(a.nb, &a.magD, &a.maskD);
+    // bit and check indices stay below N; task indices below 3 Geff nb
+    if (!recip24(a.Z, (uint32_t)code->N, &a.rZ, &a.sZ) || !recip24(a.p, (uint32_t)code->N, &a.rP, &a.sP) ||
+        !recip24(a.nb, (uint32_t)(3 * a.Geff * a.nb), &a.rD, &a.sD))
+        return fail(FWBF_E_UNSUPPORTED, "no exact 24-bit reciprocal for this code's sizes");
     a.T = lp->rounds;
     a.A = lp->scale;
     {
@@ -1244,6 +1324,11 @@ int learned_wide(const fwbf_code *code, const fwbf_params *plain, const fwbf_lea
     a.z = z_dev; a.iters = iters_dev; a.ok = ok_dev; a.learned_ok = learned_ok_dev;
     a.rec = records_dev; a.pool = pool_dev; a.pool_n = pool_n; a.f0 = f0;
     a.params = scorer_dev; a.shift = tb.shift;
+    {
+        const int esz = plain->dtype == FWBF_I8 ? 1 : 2;
+        a.pref = ((uintptr_t)y_dev % 4 == 0) && ((y_stride * esz) % 4 == 0) &&
+                 ((code->N * esz) % 4 == 0) && (code->N * esz / 4 <= 16 * WIDE_T);
+    }
     auto launch = [&](auto kern) -> int {
         int blocks = 0, dev = 0, cus = 0;
         if (a.lds_bytes > 65536)
