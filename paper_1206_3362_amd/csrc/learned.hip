@@ -604,11 +604,11 @@ struct WideArgs {
     const uint32_t *pool; // labels for records (pool row f % pool_n, NULL: all-zero)
     int64_t pool_n, f0;
     const float *params;
-    const uint32_t *shift;  // 3 x nb raw shifts
     int N, M, Z, nb;
     // quotients by Z, p and nb as 24-bit multiplies: x / d = (x * r) >> s for
     // every x below the kernel's bound (checked exhaustively on the host)
     uint32_t rZ, sZ, rP, sP, rD, sD;
+    uint16_t shv[3 * 32];  // the shifts (3 x nb), staged in LDS
     int p, L, logL, Lc, B, Geff, k, T, NC, tpr;
     int pref;   // rows are whole 4-byte words: loaded as words, the next one ahead
     float A, invA, dv;
@@ -633,6 +633,48 @@ __device__ __forceinline__ uint32_t wide_mag(const void *yrow, uint32_t n)
     }
 }
 
+// median of three (the second smallest key once a <= c)
+__device__ __forceinline__ uint32_t med3u(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+// ORs the 64 bits of b (uniform) into a bit array at bit offset base: lanes
+// 0..2 take one word each (LDS atomics), words without set bits untouched
+__device__ __forceinline__ void or_bits(uint32_t *w, uint32_t base, unsigned long long b, uint32_t lane)
+{
+    const uint32_t k = base >> 5, o = base & 31;
+    const unsigned long long lo = b << o;
+    const uint32_t hi = o ? (uint32_t)(b >> (64 - o)) : 0u;
+    const uint32_t v = lane == 0 ? (uint32_t)lo : lane == 1 ? (uint32_t)(lo >> 32) : hi;
+    if (lane < 3 && v) atomicOr(&w[k + lane], v);
+}
+
+// Member keys |y| << 5 | q of QL consecutive block columns q0.. of the
+// checks r (lanes) of one block row whose shifts are si[]: all reads issued
+// before any is used. Folds them into the two smallest keys and the parity
+// of the negative members (the sign bit of sx).
+template <int QL, typename Y>
+__device__ __forceinline__ void member_keys(const Y *sty, const uint32_t *si, uint32_t Z, uint32_t r, uint32_t rm,
+                                            int q0, uint32_t &k1, uint32_t &k2, int &sx)
+{
+    uint32_t s[QL];
+    int v[QL];
+#pragma unroll
+    for (int u = 0; u < QL; u++) s[u] = si[q0 + u];
+#pragma unroll
+    for (int u = 0; u < QL; u++) v[u] = sty[(uint32_t)(q0 + u) * Z + min(r + s[u], rm + s[u])];
+#pragma unroll
+    for (int u = 0; u < QL; u++) {
+        sx ^= v[u];
+        const uint32_t key = ((uint32_t)(v[u] < 0 ? -v[u] : v[u]) << 5) | (uint32_t)(q0 + u);
+        k2 = med3u(k1, key, k2);
+        k1 = min(k1, key);
+    }
+}
+
 template <int DT, int C>
 __global__ __launch_bounds__(WIDE_T) void learned_wide_kernel(WideArgs a)
 {
@@ -649,11 +691,11 @@ __global__ __launch_bounds__(WIDE_T) void learned_wide_kernel(WideArgs a)
     uint32_t *sh = (uint32_t *)(smem + a.o_sh);
     float *nbias = (float *)(smem + a.o_net);
     bf16x4 *nw = (bf16x4 *)(smem + a.o_netw);
-    const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const uint32_t Z = a.Z;
     const int N = a.N, M = a.M, dc = a.nb;
 
-    for (int t = tid; t < 3 * dc; t += WIDE_T) sh[t] = a.shift[t];
+    for (int t = tid; t < 3 * dc; t += WIDE_T) sh[t] = a.shv[t];
     for (int t = tid; t < 32; t += WIDE_T) {
         nbias[t] = a.params[O_B1 + t];
         nbias[32 + t] = a.params[O_B2 + t];
@@ -694,7 +736,7 @@ __global__ __launch_bounds__(WIDE_T) void learned_wide_kernel(WideArgs a)
     const uint32_t j = lane & 31, c = 32 * wv + j;
     const bool blead = scorer && lane < 32 && (j % a.k) == 0 && (int)c < a.NC;
     const int NW = (N + 31) >> 5;
-    const int Nr = (N + 63) & ~63, Mr = (M + 63) & ~63;
+    const int NZc = (int)((Z + 63) >> 6);  // 64-wide chunks of a block row or column
 
     const FrameRange fr = xcd_frames(a.F);
     // The next frame's row is loaded into registers while this frame
@@ -739,79 +781,120 @@ __global__ __launch_bounds__(WIDE_T) void learned_wide_kernel(WideArgs a)
                         if (n0 + u * WIDE_T < N) ((Y *)slots)[n0 + u * WIDE_T] = v[u];
                 }
             }
+            // the syndrome is built by OR-ing 64-bit ballots at any bit offset
+            for (int w = tid; w < 2 * ((M + 63) >> 6); w += WIDE_T) syn[w] = 0u;
             __syncthreads();
-            // ---- z_0 = [y < 0]
-            for (int n = tid; n - (int)lane < Nr; n += WIDE_T) {  // uniform per wavefront
-                const unsigned long long b = __ballot(n < N && sty[n] < (Y)0);
-                if (lane == 0) {
-                    zw[n >> 5] = (uint32_t)b;
-                    zw[(n >> 5) + 1] = (uint32_t)(b >> 32);
+            // ---- z_0 = [y < 0] from the staged row, 64 bits per ballot
+            for (int n0 = 64 * (int)wv; n0 < N; n0 += 4 * WIDE_T) {
+                int v[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int n = n0 + u * WIDE_T + (int)lane;
+                    v[u] = n < N ? (int)sty[n] : 0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const unsigned long long b = __ballot(v[u] < 0);
+                    const int w = (n0 + u * WIDE_T) >> 5;
+                    if (lane < 2 && n0 + u * WIDE_T < N) zw[w + (int)lane] = lane ? (uint32_t)(b >> 32) : (uint32_t)b;
                 }
             }
-            // ---- check minima and syndrome s_0 from the staged row
-            for (int m0 = tid; m0 < Mr; m0 += WIDE_T) {
-                bool par = false;
-                if (m0 < M) {
-                    const uint32_t i = mul24((uint32_t)m0, a.rZ) >> a.sZ, r = m0 - mul24(i, Z);
-                    const uint32_t *si = sh + i * dc;
-                    // the two smallest keys |y| << 5 | q: min1 and min2 (with
-                    // multiplicity) and the lowest position holding min1
-                    uint32_t k1 = 0xFFFFFFFFu, k2 = 0xFFFFFFFFu, sx = 0;
-                    constexpr int QL = 8;
-                    for (int q0 = 0; q0 < dc; q0 += QL) {
-                        int v[QL];
-#pragma unroll
-                        for (int u = 0; u < QL; u++) {
-                            const int q = q0 + u < dc ? q0 + u : dc - 1;
-                            v[u] = sty[mul24((uint32_t)q, Z) + addmod(r, si[q], Z)];
-                        }
-#pragma unroll
-                        for (int u = 0; u < QL; u++) {
-                            if (q0 + u >= dc) break;
-                            sx ^= (uint32_t)v[u];  // bit 31: parity of the negative members
-                            const uint32_t key = ((uint32_t)(v[u] < 0 ? -v[u] : v[u]) << 5) | (uint32_t)(q0 + u);
-                            k2 = min(k2, max(k1, key));
-                            k1 = min(k1, key);
+            // ---- check minima and syndrome s_0 from the staged row. A
+            // wavefront takes 64 consecutive checks of one block row, so the
+            // row's shifts are uniform and the members' addresses consecutive
+            // (conflict-free) up to one wrap. Lanes past the row's end read
+            // in-bounds values that are never stored.
+            for (int ch = (int)wv; ch < 3 * NZc; ch += WIDE_T / 64) {
+                const int i = ch / NZc;
+                const uint32_t r0 = (uint32_t)(ch - i * NZc) << 6, r = r0 + lane;
+                const uint32_t rm = r - Z;  // rm + s wraps below Z
+                const uint32_t *si = sh + i * dc;
+                // the two smallest keys |y| << 5 | q: min1 and min2 (with
+                // multiplicity) and the position holding min1 (any one of equal
+                // minima: min2 then equals min1)
+                uint32_t k1 = 0xFFFFFFFFu, k2 = 0xFFFFFFFFu;
+                int sx = 0;
+                int q0 = 0;
+                for (; q0 + 8 <= dc; q0 += 8) member_keys<8>(sty, si, Z, r, rm, q0, k1, k2, sx);
+                if (q0 + 4 <= dc) { member_keys<4>(sty, si, Z, r, rm, q0, k1, k2, sx); q0 += 4; }
+                if (q0 + 2 <= dc) { member_keys<2>(sty, si, Z, r, rm, q0, k1, k2, sx); q0 += 2; }
+                if (q0 < dc) member_keys<1>(sty, si, Z, r, rm, q0, k1, k2, sx);
+                const bool valid = r < Z;
+                const uint32_t m = (uint32_t)i * Z + r;
+                if (valid) {
+                    chk[m] = (k1 >> 5) | ((k2 >> 5) << 16);
+                    chkp[m] = (uint8_t)(k1 & 31u);
+                }
+                const unsigned long long b = __ballot(valid && sx < 0);
+                if (b) {
+                    or_bits(syn, (uint32_t)i * Z + r0, b, lane);
+                    if (lane == 0) atomicAdd(&ctl[CW_WEIGHT], __popcll(b));
+                }
+            }
+            __syncthreads();
+            // ---- slot words: 64 consecutive bits of one block column per
+            // wavefront, S and u gathered from the bits' three checks with
+            // min1 as every weight (the argmin members are corrected below),
+            // |y| read again from the row in global memory (the staged copy is
+            // dead once the slots take its place)
+            {
+                int ch = (int)wv;
+                int xn = 0;
+                if (ch < dc * NZc) {
+                    const int jb = ch / NZc;
+                    const uint32_t c = ((uint32_t)(ch - jb * NZc) << 6) + lane;
+                    xn = yrow[(uint32_t)jb * Z + (c < Z ? c : 0u)];
+                }
+                for (; ch < dc * NZc; ch += WIDE_T / 64) {
+                    const int x = xn;
+                    const int jb = ch / NZc;
+                    // (the uniform chunk start kept apart from the lane index)
+                    const uint32_t c0 = __builtin_amdgcn_readfirstlane((uint32_t)(ch - jb * NZc) << 6);
+                    const uint32_t c = c0 + lane, cz = c + Z;
+                    {   // the next chunk's y, in flight while this one is built
+                        const int chn = ch + WIDE_T / 64;
+                        if (chn < dc * NZc) {
+                            const int jn = chn / NZc;
+                            const uint32_t cn = ((uint32_t)(chn - jn * NZc) << 6) + lane;
+                            xn = yrow[(uint32_t)jn * Z + (cn < Z ? cn : 0u)];
                         }
                     }
-                    par = (sx >> 31) != 0;
-                    chk[m0] = (k1 >> 5) | ((k2 >> 5) << 16);
-                    chkp[m0] = (uint8_t)(k1 & 31u);
-                }
-                const unsigned long long b = __ballot(par);
-                if (lane == 0) {
-                    syn[m0 >> 5] = (uint32_t)b;
-                    syn[(m0 >> 5) + 1] = (uint32_t)(b >> 32);
-                    if (b) atomicAdd(&ctl[CW_WEIGHT], __popcll(b));
-                }
-            }
-            __syncthreads();
-            // ---- slot words: S and u gathered from each bit's three checks,
-            // |y| read again from the row in global memory (it is in L2): the
-            // staged copy is dead once the slots take its place
-            for (int n0 = tid; n0 < N; n0 += 8 * WIDE_T) {
-                Y v[8];
+                    uint32_t s3[3];
 #pragma unroll
-                for (int u = 0; u < 8; u++) v[u] = n0 + u * WIDE_T < N ? yrow[n0 + u * WIDE_T] : (Y)0;
-#pragma unroll
-                for (int u = 0; u < 8; u++) {
-                    const uint32_t n = n0 + u * WIDE_T;
-                    if ((int)n >= N) break;
-                    const int x = v[u];
-                    const uint32_t av = (uint32_t)(x < 0 ? -x : x);
-                    const uint32_t jb = mul24(n, a.rZ) >> a.sZ, c = n - mul24(jb, Z);
-                    int S = 0;
-                    uint32_t uu = 0;
+                    for (int tt = 0; tt < 3; tt++) s3[tt] = sh[tt * dc + jb];  // broadcast reads
+                    // S = 2 (sum of w over unsatisfied checks) - (sum of w)
+                    uint32_t su = 0, sw = 0, uu = 0;
 #pragma unroll
                     for (int tt = 0; tt < 3; tt++) {
-                        const uint32_t m = mul24((uint32_t)tt, Z) + submod(c, sh[tt * dc + jb], Z);
-                        const uint32_t cw = chk[m];
-                        const int w = (int)(chkp[m] == jb ? (cw >> 16) : (cw & 0xFFFFu));
-                        const uint32_t sb = (syn[m >> 5] >> (m & 31)) & 1u;
-                        S += sb ? w : -w;
+                        const uint32_t mm = (uint32_t)tt * Z + min(c - s3[tt], cz - s3[tt]);
+                        const uint32_t w = ((const uint16_t *)chk)[2 * mm];  // min1
+                        // bit mm of the syndrome (the extract takes the offset mod 32)
+                        const uint32_t sb = __builtin_amdgcn_ubfe(syn[__builtin_amdgcn_ubfe(mm, 5, 27)], mm, 1);
+                        su += sb * w;
+                        sw += w;
                         uu += sb;
                     }
-                    slots[wide_slot(a, n)] = ((uint32_t)S << 14) | (min(av, WSAT) << 2) | uu;
+                    const uint32_t av = (uint32_t)(x < 0 ? -x : x);
+                    if (c < Z)
+                        slots[wide_slot(a, (uint32_t)jb * Z + c)] =
+                            ((2u * su - sw) << 14) | (min(av, WSAT) << 2) | uu;
+                }
+            }
+            __syncthreads();
+            // ---- the member of each check at min1 takes min2: one correction
+            // of +-(min2 - min1) to its S
+            for (int ch = (int)wv; ch < 3 * NZc; ch += WIDE_T / 64) {
+                const int i = ch / NZc;
+                const uint32_t r = ((uint32_t)(ch - i * NZc) << 6) + lane;
+                if (r < Z) {
+                    const uint32_t m = (uint32_t)i * Z + r, cwd = chk[m];
+                    const uint32_t d = (cwd >> 16) - (cwd & 0xFFFFu);
+                    if (d) {
+                        const uint32_t q = chkp[m], s = sh[i * dc + (int)q];
+                        const uint32_t sb = (syn[m >> 5] >> (m & 31)) & 1u;
+                        const uint32_t n = mul24(q, Z) + min(r + s, r + s - Z);
+                        atomicAdd(&slots[wide_slot(a, n)], (sb ? d : 0u - d) << 14);
+                    }
                 }
             }
             __syncthreads();
@@ -1317,13 +1400,12 @@ int learned_wide(const fwbf_code *code, const fwbf_params *plain, const fwbf_lea
     a.o_netw = take(64 * 5 * 8, 16);
     a.lds_bytes = (off + 15) / 16 * 16;
     if (a.lds_bytes > 160 * 1024) return fail(FWBF_E_UNSUPPORTED, "frame state exceeds 160 KiB of LDS");
-    DeviceTables tb;
-    int rc = device_tables(const_cast<fwbf_code *>(code), &tb);
-    if (rc) return rc;
+    int rc = FWBF_OK;
     a.y = y_dev; a.F = F; a.stride = y_stride;
     a.z = z_dev; a.iters = iters_dev; a.ok = ok_dev; a.learned_ok = learned_ok_dev;
     a.rec = records_dev; a.pool = pool_dev; a.pool_n = pool_n; a.f0 = f0;
-    a.params = scorer_dev; a.shift = tb.shift;
+    a.params = scorer_dev;
+    for (int t = 0; t < 3 * code->nb; t++) a.shv[t] = (uint16_t)code->shift[t];
     {
         const int esz = plain->dtype == FWBF_I8 ? 1 : 2;
         a.pref = ((uintptr_t)y_dev % 4 == 0) && ((y_stride * esz) % 4 == 0) &&
