@@ -103,14 +103,12 @@ template <> struct Tr<FWBF_I8> {
     using Mag = uint8_t;
     using Chk = uint32_t;  // min1 | min2 << 8 | pos << 16
     static constexpr bool isf = false;
-    static constexpr uint32_t BIG = 0xFF;
 };
 template <> struct Tr<FWBF_I16> {
     using Y = int16_t;
     using Mag = uint16_t;
     using Chk = uint32_t;  // min1 | min2 << 16; position in chkp
     static constexpr bool isf = false;
-    static constexpr uint32_t BIG = 0xFFFF;
 };
 template <> struct Tr<FWBF_F32> {
     using Y = float;
@@ -327,6 +325,207 @@ __device__ __forceinline__ void frame_sync()
     }
 }
 
+// ---------------------------------------------------------------------------
+// Initialisation of integer inputs in 64-wide chunks: a wavefront takes 64
+// consecutive checks of one block row (or bits of one block column), so the
+// row's (column's) list entries are uniform across it, read once and kept in
+// scalar registers, and the lanes' members are consecutive words up to one
+// wrap.  The staged row holds the signed values (their magnitudes are taken
+// where used).
+// ---------------------------------------------------------------------------
+
+// median of three (the second smallest key once a <= c)
+__device__ __forceinline__ uint32_t med3u(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+// ORs the 64 bits of b (uniform) into a bit array at bit offset base: lanes
+// 0..2 take one word each (LDS atomics), words without set bits untouched
+__device__ __forceinline__ void or_bits(uint32_t *w, uint32_t base, unsigned long long b, uint32_t lane)
+{
+    const uint32_t k = base >> 5, o = base & 31;
+    const unsigned long long lo = b << o;
+    const uint32_t hi = o ? (uint32_t)(b >> (64 - o)) : 0u;
+    const uint32_t v = lane == 0 ? (uint32_t)lo : lane == 1 ? (uint32_t)(lo >> 32) : hi;
+    if (lane < 3 && v) atomicOr(&w[k + lane], v);
+}
+
+// Keys |y| << 8 | t of the row-list entries t = q0 .. q0 + QL - 1 (entry:
+// column block << 16 | shift) for the checks r of one block row (lanes; rm
+// = r - Z), all reads issued before any is used, folded into the two
+// smallest keys and the parity of the negative members (sign bit of sx).
+template <int QL, typename Y>
+__device__ __forceinline__ void row_keys(const Y *ys, const uint32_t *re, uint32_t Z, uint32_t r, uint32_t rm, int q0,
+                                         uint32_t &k1, uint32_t &k2, int &sx)
+{
+    uint32_t e[QL];
+    int v[QL];
+#pragma unroll
+    for (int u = 0; u < QL; u++) e[u] = __builtin_amdgcn_readfirstlane(re[q0 + u]);
+#pragma unroll
+    for (int u = 0; u < QL; u++) {
+        const uint32_t sft = e[u] & 0xFFFFu;
+        v[u] = (int)ys[(e[u] >> 16) * Z + min(r + sft, rm + sft)];
+    }
+#pragma unroll
+    for (int u = 0; u < QL; u++) {
+        sx ^= v[u];
+        const uint32_t key = ((uint32_t)(v[u] < 0 ? -v[u] : v[u]) << 8) | (uint32_t)(q0 + u);
+        k2 = med3u(k1, key, k2);
+        k1 = min(k1, key);
+    }
+}
+
+// first minimum of check m
+template <int DT>
+__device__ __forceinline__ int chk_min1(const Lds &s, uint32_t m)
+{
+    if constexpr (DT == FWBF_I8) return ((const uint8_t *)s.chk)[4 * m];
+    else return ((const uint16_t *)s.chk)[2 * m];
+}
+
+// Sum over the column-list entries t = t0 .. t0 + QL - 1 (entry: row block
+// << 24 | position << 16 | shift) of +-min1 of the bits c (lanes; cz = c + Z)
+// of one block column, + for an unsatisfied check; reads issued together.
+template <int DT, int QL>
+__device__ __forceinline__ int col_terms(const Lds &s, const uint32_t *ce, uint32_t Z, uint32_t c, uint32_t cz, int t0)
+{
+    uint32_t e[QL], mm[QL], sw[QL];
+    int w[QL];
+#pragma unroll
+    for (int u = 0; u < QL; u++) e[u] = __builtin_amdgcn_readfirstlane(ce[t0 + u]);
+#pragma unroll
+    for (int u = 0; u < QL; u++) {
+        const uint32_t sft = e[u] & 0xFFFFu;
+        mm[u] = (e[u] >> 24) * Z + min(c - sft, cz - sft);
+    }
+#pragma unroll
+    for (int u = 0; u < QL; u++) {
+        w[u] = chk_min1<DT>(s, mm[u]);
+        sw[u] = s.syn[__builtin_amdgcn_ubfe(mm[u], 5, 27)];
+    }
+    int S = 0;
+#pragma unroll
+    for (int u = 0; u < QL; u++) S += __builtin_amdgcn_ubfe(sw[u], mm[u], 1) ? w[u] : -w[u];  // offset taken mod 32
+    return S;
+}
+
+// slot of bit n
+__device__ __forceinline__ uint32_t slot_of(const DecodeArgs &a, uint32_t n, uint32_t *pos_out)
+{
+    uint32_t g, pos;
+    if (a.strided) { pos = fdiv(n, a.magG, a.maskG); g = n - pos * a.Geff; }
+    else { g = fdiv(n, a.magP, a.maskP); pos = n - g * a.p; }
+    *pos_out = pos;
+    return g * a.Lc + pos;
+}
+
+// Check minima (min1, min2 with multiplicity, position of min1) and the
+// syndrome s_0 of integer inputs; the syndrome words start zeroed.
+template <int DT, int T>
+__device__ __forceinline__ void int_check_minima(const DecodeArgs &a, const Lds &s, int tid, uint32_t lane)
+{
+    using Tt = Tr<DT>;
+    const typename Tt::Y *ys = (const typename Tt::Y *)s.mag;
+    const uint32_t Z = a.Z;
+    const int NZc = (int)((Z + 63) >> 6);
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    for (int ch = wv; ch < a.mb * NZc; ch += T / 64) {
+        const int i = ch / NZc;
+        const uint32_t r0 = (uint32_t)(ch - i * NZc) << 6, r = r0 + lane;
+        const bool valid = r < Z;
+        const uint32_t rr = valid ? r : 0u, rm = rr - Z;  // rm + s wraps below Z
+        const int deg = __builtin_amdgcn_readfirstlane(s.rdeg[i]);
+        const uint32_t *re = s.row + i * a.dcmax;
+        // the two smallest keys: min1 and min2 with multiplicity, the first
+        // one's entry the lowest position holding min1
+        uint32_t k1 = 0xFFFFFFFFu, k2 = 0xFFFFFFFFu;
+        int sx = 0, q0 = 0;
+        for (; q0 + 4 <= deg; q0 += 4) row_keys<4>(ys, re, Z, rr, rm, q0, k1, k2, sx);
+        if (deg - q0 == 3) row_keys<3>(ys, re, Z, rr, rm, q0, k1, k2, sx);
+        else if (deg - q0 == 2) row_keys<2>(ys, re, Z, rr, rm, q0, k1, k2, sx);
+        else if (deg - q0 == 1) row_keys<1>(ys, re, Z, rr, rm, q0, k1, k2, sx);
+        if (valid) {
+            const uint32_t m = (uint32_t)i * Z + rr;
+            const uint32_t m1 = deg > 0 ? (k1 >> 8) : 0u, m2 = deg > 1 ? (k2 >> 8) : 0u;  // empty minima: 0
+            const uint32_t pos = deg > 0 ? (k1 & 0xFFu) : 0u;
+            ((typename Tt::Chk *)s.chk)[m] = pack_chk<DT>(m1, m2, pos);
+            if constexpr (DT == FWBF_I16) s.chkp[m] = (uint8_t)pos;
+        }
+        const unsigned long long b = __ballot(valid && sx < 0);
+        if (b) {
+            or_bits(s.syn, (uint32_t)i * Z + r0, b, lane);
+            if (lane == 0) atomicAdd(&s.ctl[CTL_WEIGHT], __popcll(b));
+        }
+    }
+}
+
+// Initial keys of integer inputs (eq. (1)): every bit gathers +-min1 of its
+// checks; padding slots get key 0; with IMWBF weights each check then moves
+// the metric of the member holding its min1 by +-a_den (min2 - min1) (that
+// member's weight is min2).  The staged row is dead here (its memory may be
+// the slots'), so |y| is read from the frame in global memory.
+template <int DT, bool KEY32, int T, bool WAVE>
+__device__ __forceinline__ void int_initial_keys(const DecodeArgs &a, const Lds &s, int tid, uint32_t lane,
+                                                 const typename Tr<DT>::Y *yrow)
+{
+    const uint32_t Z = a.Z;
+    const int N = a.N;
+    const int NZc = (int)((Z + 63) >> 6);
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    for (int pi = 0; pi < a.P; pi++) {
+        const int g = pi * a.GP + (tid >> a.logL);
+        const int l = tid & (a.L - 1);
+        int lim = 0;  // positions below lim hold a bit
+        if (g < a.Geff)
+            lim = a.strided ? min(a.p, (int)fdiv((uint32_t)(N - g + a.Geff - 1), a.magG, a.maskG)) : min(a.p, N - g * a.p);
+        for (int kk = lim > l ? (lim - l + a.L - 1) >> a.logL : 0; kk < a.C; kk++) s.keys[g * a.Lc + l + kk * a.L] = 0;
+    }
+    for (int ch = wv; ch < a.nb * NZc; ch += T / 64) {
+        const int j = ch / NZc;
+        const uint32_t c0 = __builtin_amdgcn_readfirstlane((uint32_t)(ch - j * NZc) << 6), c = c0 + lane;
+        const bool valid = c < Z;
+        const uint32_t cc = valid ? c : 0u, cz = cc + Z;
+        const uint32_t n = (uint32_t)j * Z + cc;
+        const int x = (int)yrow[n];
+        const int deg = __builtin_amdgcn_readfirstlane(s.cdeg[j]);
+        const uint32_t *ce = s.col + j * a.dvmax;
+        // four entries at a time (entries past the column's degree add nothing)
+        int S = 0, t0 = 0;
+        for (; t0 + 4 <= deg; t0 += 4) S += col_terms<DT, 4>(s, ce, Z, cc, cz, t0);
+        if (t0 + 2 <= deg) { S += col_terms<DT, 2>(s, ce, Z, cc, cz, t0); t0 += 2; }
+        if (t0 < deg) S += col_terms<DT, 1>(s, ce, Z, cc, cz, t0);
+        const int av = x < 0 ? -x : x;
+        const uint32_t v = (uint32_t)(a.aden * S - a.anum * av + (int32_t)a.bias);
+        uint32_t pos;
+        const uint32_t slot = slot_of(a, n, &pos);
+        if (valid) s.keys[slot] = KEY32 ? ((v << a.idxb) | (a.idxmask - pos)) : v;
+    }
+    if (a.weights != FWBF_IMWBF) return;
+    frame_sync<WAVE>();
+    for (int ch = wv; ch < a.mb * NZc; ch += T / 64) {
+        const int i = ch / NZc;
+        const uint32_t r = ((uint32_t)(ch - i * NZc) << 6) + lane;
+        if (r >= Z) continue;
+        const uint32_t m = (uint32_t)i * Z + r, cw = ((const uint32_t *)s.chk)[m];
+        uint32_t m1, m2, q;
+        if constexpr (DT == FWBF_I8) { m1 = cw & 0xFF; m2 = (cw >> 8) & 0xFF; q = (cw >> 16) & 0xFF; }
+        else { m1 = cw & 0xFFFF; m2 = cw >> 16; q = s.chkp[m]; }
+        const int d = (int)m2 - (int)m1;
+        if (d == 0 || (int)q >= s.rdeg[i]) continue;  // (an empty row has no member to move)
+        const uint32_t e = s.row[i * a.dcmax + q], sft = e & 0xFFFFu;
+        const uint32_t nn = (e >> 16) * Z + min(r + sft, r + sft - Z);
+        const uint32_t sb = (s.syn[m >> 5] >> (m & 31)) & 1u;
+        const int dd = a.aden * (sb ? d : -d);
+        uint32_t pos;
+        const uint32_t slot = slot_of(a, nn, &pos);
+        atomicAdd(&s.keys[slot], KEY32 ? ((uint32_t)dd << a.idxb) : (uint32_t)dd);
+    }
+}
+
 template <int DT, bool KEY32, int T, bool WAVE = false>
 __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
 {
@@ -363,7 +562,7 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
             const bool neg = n < N && v[u] < (Y)0;
             if (n < N) {
                 if constexpr (Tt::isf) mag[n] = fabsf(v[u]);
-                else mag[n] = (Mag)(v[u] < 0 ? -(int)v[u] : (int)v[u]);
+                else mag[n] = (Mag)v[u];  // integers: the signed value (magnitudes taken where used)
             }
             const unsigned long long b = __ballot(neg);
             if (lane == 0) {
@@ -373,18 +572,21 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
         }
     }
     for (int w = tid; w < (Mr >> 5); w += T) s.tog[w] = 0;
+    if constexpr (!Tt::isf)
+        for (int w = tid; w < (Mr >> 5); w += T) s.syn[w] = 0;
     if (tid == 0) { s.ctl[CTL_FLAGS] = 0; s.ctl[CTL_WEIGHT] = 0; }
     frame_sync<WAVE>();
 
     // ---- check minima (weights) and the syndrome s_0 (Step 1 at k=0) -----
-    for (int m = tid; m < Mr; m += T) {
+    if constexpr (!Tt::isf) int_check_minima<DT, T>(a, s, tid, (uint32_t)lane);
+    else for (int m = tid; m < Mr; m += T) {
         bool par = false;
         if (m < M) {
             const uint32_t i = fdiv(m, a.magZ, a.maskZ);
             const int r = m - (int)i * a.Z;
             const int deg = s.rdeg[i];
             const uint32_t *re = s.row + i * a.dcmax;
-            if constexpr (Tt::isf) {
+            {
                 float m1 = __builtin_inff(), m2 = __builtin_inff();
                 uint32_t pos = 0;
                 for (int q = 0; q < deg; q++) {
@@ -400,21 +602,6 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
                 if (deg < 2) m2 = 0.0f;  // empty minimum over N(m) minus the member
                 chk[m] = pack_chk<DT>(__float_as_uint(m1), __float_as_uint(m2), 0);
                 s.chkp[m] = (uint8_t)pos;
-            } else {
-                uint32_t m1 = Tt::BIG + 1, m2 = Tt::BIG + 1, pos = 0;
-                for (int q = 0; q < deg; q++) {
-                    const uint32_t e = re[q];
-                    int cc = r + (int)(e & 0xFFFF);
-                    cc -= (cc >= a.Z) ? a.Z : 0;
-                    const uint32_t n = (e >> 16) * a.Z + cc;
-                    const uint32_t v = mag[n];
-                    par ^= (s.zw[n >> 5] >> (n & 31)) & 1;
-                    if (v < m1) { m2 = m1; m1 = v; pos = q; }
-                    else if (v < m2) m2 = v;
-                }
-                if (deg < 2) m2 = 0;
-                chk[m] = pack_chk<DT>(m1 & Tt::BIG, m2 & Tt::BIG, pos);
-                if constexpr (DT == FWBF_I16) s.chkp[m] = (uint8_t)pos;
             }
         }
         const unsigned long long b = __ballot(par);
@@ -432,7 +619,8 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
         okf = weight0 == 0;
     } else {
         // ---- initial metrics (eq. (1)) into the slots ---------------------
-        for (int pi = 0; pi < a.P; pi++) {
+        if constexpr (!Tt::isf) int_initial_keys<DT, KEY32, T, WAVE>(a, s, tid, (uint32_t)lane, yrow);
+        else for (int pi = 0; pi < a.P; pi++) {
             const int g = pi * a.GP + (tid >> a.logL);
             const int l = tid & (a.L - 1);
             for (int kk = 0; kk < a.C; kk++) {
@@ -524,12 +712,13 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
             }
             frame_sync<WAVE>();
 
-            if constexpr (Tt::isf) {
+            if constexpr (Tt::isf || T > 64) {
                 // ---- flip the chosen bits and toggle their checks' syndrome -----
                 // Every toggle is an atomic xor that returns the bit it
                 // replaced: the weight moves by one per toggle and each toggle
                 // is listed with the check's new bit (a check toggled by two
-                // winners is listed twice and ends unchanged).
+                // winners is listed twice and ends unchanged; integer
+                // inputs then add +2 a_den w and -2 a_den w to its members).
                 for (int u = tid; u < a.W; u += T) {
                     const uint32_t n = s.win[u];
                     const uint32_t pv = s.prv[u];
