@@ -48,7 +48,9 @@ namespace fwbf {
 namespace {
 
 constexpr uint32_t NONE = 0xFFFFFFFFu;
-constexpr int CTL_FLAGS = 0, CTL_WEIGHT = 1;
+// control words: the unsatisfied-check count, and the flags of rounds k even
+// and odd (a round's slot is cleared at the start of the round before it)
+constexpr int CTL_WEIGHT = 1, CTL_FLAGS0 = 2;
 constexpr int F_ANY = 1, F_DIFF = 2;
 // task-list entry: check index, with this bit set when the toggle left the
 // check unsatisfied (check indices stay below 2^31)
@@ -283,6 +285,40 @@ __device__ __forceinline__ unsigned long long thread_best(const DecodeArgs &a, c
         }
         return ((unsigned long long)best << 32) | (0xFFFFFFFFu - (l + bk * (uint32_t)a.L));
     }
+}
+
+// the largest of the C packed keys of one thread (reads KB at a time)
+__device__ __forceinline__ uint32_t thread_best32(const DecodeArgs &a, const uint32_t *keys, int s0)
+{
+    constexpr int KB = 4;
+    uint32_t best = 0;
+    for (int k0 = 0; k0 < a.C; k0 += KB) {
+        uint32_t v[KB];
+#pragma unroll
+        for (int u = 0; u < KB; u++) v[u] = k0 + u < a.C ? keys[s0 + (k0 + u) * a.L] : 0u;
+#pragma unroll
+        for (int u = 0; u < KB; u++) best = max(best, v[u]);
+    }
+    return best;
+}
+
+// maximum over aligned groups of w lanes of a 32-bit value (w a power of two
+// <= 64, every lane active): DPP row moves fused with the max, then two
+// cross-row exchanges; every lane of a group ends with the maximum
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t group_max32(uint32_t v, int w)
+{
+    if (w > 1) v = max(v, dpp32<0xB1>(v));   // quad_perm [1,0,3,2]
+    if (w > 2) v = max(v, dpp32<0x4E>(v));   // quad_perm [2,3,0,1]
+    if (w > 4) v = max(v, dpp32<0x141>(v));  // row_half_mirror
+    if (w > 8) v = max(v, dpp32<0x140>(v));  // row_mirror
+    if (w > 16) v = max(v, (uint32_t)__shfl_xor((int)v, 16, 64));
+    if (w > 32) v = max(v, (uint32_t)__shfl_xor((int)v, 32, 64));
+    return v;
 }
 
 // row-local data movement (DPP) of a 64-bit value: xor 1, xor 2, mirror
@@ -526,6 +562,53 @@ __device__ __forceinline__ void int_initial_keys(const DecodeArgs &a, const Lds 
     }
 }
 
+// Flips bit n of block u (NONE: no flip) and toggles its checks' syndrome
+// bits with atomic xors that return the bit replaced: the weight moves by one
+// per toggle and each toggle is listed with the check's new bit (a check
+// toggled by two winners is listed twice and ends unchanged; integer inputs
+// then add +2 a_den w and -2 a_den w to its members).  The round's flags
+// record any flip and any block whose choice differs from the previous one.
+__device__ __forceinline__ void flip_block(const DecodeArgs &a, const Lds &s, uint32_t u, uint32_t n, int *flags)
+{
+    const uint32_t pv = s.prv[u];
+    s.prv[u] = n;
+    uint32_t *tl = s.tl + u * a.dvmax;
+    for (int t = 0; t < a.dvmax; t++) tl[t] = NONE;
+    int fl = (n != pv) ? F_DIFF : 0;
+    if (n != NONE) {
+        fl |= F_ANY;
+        atomicXor(&s.zw[n >> 5], 1u << (n & 31));
+        const uint32_t j = fdiv(n, a.magZ, a.maskZ);
+        const int c = (int)(n - j * a.Z);
+        const int deg = s.cdeg[j];
+        int dw = 0;
+        // four checks at a time, their toggles issued together
+        for (int t0 = 0; t0 < deg; t0 += 4) {
+            uint32_t mq[4], so[4];
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const uint32_t e = s.col[j * a.dvmax + min(t0 + v, deg - 1)];
+                int r = c - (int)(e & 0xFFFF);
+                r += (r < 0) ? a.Z : 0;
+                mq[v] = (e >> 24) * a.Z + r;
+            }
+#pragma unroll
+            for (int v = 0; v < 4; v++)
+                so[v] = t0 + v < deg ? atomicXor(&s.syn[mq[v] >> 5], 1u << (mq[v] & 31)) : 0u;
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                if (t0 + v < deg) {
+                    const uint32_t bit = 1u << (mq[v] & 31);
+                    dw += (so[v] & bit) ? -1 : 1;
+                    tl[t0 + v] = (so[v] & bit) ? mq[v] : (mq[v] | TL_UNSAT);
+                }
+            }
+        }
+        if (dw) atomicAdd(&s.ctl[CTL_WEIGHT], dw);
+    }
+    if (fl) atomicOr(flags, fl);
+}
+
 template <int DT, bool KEY32, int T, bool WAVE = false>
 __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
 {
@@ -574,7 +657,7 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
     for (int w = tid; w < (Mr >> 5); w += T) s.tog[w] = 0;
     if constexpr (!Tt::isf)
         for (int w = tid; w < (Mr >> 5); w += T) s.syn[w] = 0;
-    if (tid == 0) { s.ctl[CTL_FLAGS] = 0; s.ctl[CTL_WEIGHT] = 0; }
+    if (tid == 0) { s.ctl[CTL_FLAGS0] = 0; s.ctl[CTL_FLAGS0 + 1] = 0; s.ctl[CTL_WEIGHT] = 0; }
     frame_sync<WAVE>();
 
     // ---- check minima (weights) and the syndrome s_0 (Step 1 at k=0) -----
@@ -639,23 +722,37 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
         for (int u = tid; u < a.Geff && a.L > 64; u += T) s.gb[u] = 0;
         frame_sync<WAVE>();
 
+        // the flips of a block follow its choice at once (no barrier between)
+        // where one wavefront holds the block and the flip pass is the one
+        // that lists every toggle
+        const bool merged = (Tt::isf || T > 64) && a.select != FWBF_TOPL && a.L <= 64;
         for (;;) {
-            // the previous round's flags were read before the barrier that
-            // ended it; the flip phase below sets them again
-            if (tid == 0) s.ctl[CTL_FLAGS] = 0;
+            // this round's flags; the next round's slot was last read in the
+            // round before this one, so it is cleared here
+            const int fi = CTL_FLAGS0 + (k & 1);
+            if (tid == 0) s.ctl[CTL_FLAGS0 + ((k + 1) & 1)] = 0;
             // ---- Step 2: choose at most one bit per block ------------------
             if (a.select != FWBF_TOPL) {
                 for (int pi = 0; pi < a.P; pi++) {
                     const int g = pi * a.GP + (tid >> a.logL);
                     const int l = tid & (a.L - 1);
-                    unsigned long long best = thread_best<KEY32>(a, s.keys, g * a.Lc + l, l);
-                    best = group_max64(best, a.L < 64 ? a.L : 64);
+                    unsigned long long best;
+                    if constexpr (KEY32) {
+                        // packed keys: the maximum runs on 32 bits, then unpacks
+                        const uint32_t b32 = group_max32(thread_best32(a, s.keys, g * a.Lc + l), a.L < 64 ? a.L : 64);
+                        best = ((unsigned long long)(b32 >> a.idxb) << 32) | (0xFFFFFFFFu - (a.idxmask - (b32 & a.idxmask)));
+                    } else {
+                        best = thread_best<KEY32>(a, s.keys, g * a.Lc + l, l);
+                        best = group_max64(best, a.L < 64 ? a.L : 64);
+                    }
                     if (a.L <= 64) {
                         if ((tid & (a.L - 1)) == 0 && g < a.Geff) {
                             const uint32_t val = (uint32_t)(best >> 32);
                             const uint32_t pos = 0xFFFFFFFFu - (uint32_t)best;
                             const bool flip = (a.select == FWBF_SINGLE) || val > a.zero_val;
-                            s.win[g] = flip ? bit_of(a, g, pos) : NONE;
+                            const uint32_t n = flip ? bit_of(a, g, pos) : NONE;
+                            s.win[g] = n;
+                            if (merged) flip_block(a, s, (uint32_t)g, n, &s.ctl[fi]);
                         }
                     } else if (lane == 0 && g < a.Geff) {
                         atomicMax(&s.gb[g], best);
@@ -714,53 +811,12 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
 
             if constexpr (Tt::isf || T > 64) {
                 // ---- flip the chosen bits and toggle their checks' syndrome -----
-                // Every toggle is an atomic xor that returns the bit it
-                // replaced: the weight moves by one per toggle and each toggle
-                // is listed with the check's new bit (a check toggled by two
-                // winners is listed twice and ends unchanged; integer
-                // inputs then add +2 a_den w and -2 a_den w to its members).
-                for (int u = tid; u < a.W; u += T) {
-                    const uint32_t n = s.win[u];
-                    const uint32_t pv = s.prv[u];
-                    s.prv[u] = n;
-                    uint32_t *tl = s.tl + u * a.dvmax;
-                    for (int t = 0; t < a.dvmax; t++) tl[t] = NONE;
-                    int fl = (n != pv) ? F_DIFF : 0;
-                    if (n != NONE) {
-                        fl |= F_ANY;
-                        atomicXor(&s.zw[n >> 5], 1u << (n & 31));
-                        const uint32_t j = fdiv(n, a.magZ, a.maskZ);
-                        const int c = (int)(n - j * a.Z);
-                        const int deg = s.cdeg[j];
-                        int dw = 0;
-                        // four checks at a time, their toggles issued together
-                        for (int t0 = 0; t0 < deg; t0 += 4) {
-                            uint32_t mq[4], so[4];
-#pragma unroll
-                            for (int v = 0; v < 4; v++) {
-                                const uint32_t e = s.col[j * a.dvmax + min(t0 + v, deg - 1)];
-                                int r = c - (int)(e & 0xFFFF);
-                                r += (r < 0) ? a.Z : 0;
-                                mq[v] = (e >> 24) * a.Z + r;
-                            }
-#pragma unroll
-                            for (int v = 0; v < 4; v++)
-                                so[v] = t0 + v < deg ? atomicXor(&s.syn[mq[v] >> 5], 1u << (mq[v] & 31)) : 0u;
-#pragma unroll
-                            for (int v = 0; v < 4; v++) {
-                                if (t0 + v < deg) {
-                                    const uint32_t bit = 1u << (mq[v] & 31);
-                                    dw += (so[v] & bit) ? -1 : 1;
-                                    tl[t0 + v] = (so[v] & bit) ? mq[v] : (mq[v] | TL_UNSAT);
-                                }
-                            }
-                        }
-                        if (dw) atomicAdd(&s.ctl[CTL_WEIGHT], dw);
-                    }
-                    if (fl) atomicOr(&s.ctl[CTL_FLAGS], fl);
+                // (flip_block; done above, with the choice, when merged)
+                if (!merged) {
+                    for (int u = tid; u < a.W; u += T) flip_block(a, s, (uint32_t)u, s.win[u], &s.ctl[fi]);
+                    frame_sync<WAVE>();
                 }
-                frame_sync<WAVE>();
-                const int flags = s.ctl[CTL_FLAGS];
+                const int flags = s.ctl[fi];
                 if (!(a.flags & FWBF_FLAG_NO_CYCLE_EXIT)) {
                     if (!(flags & F_ANY)) {  // no flip: fixed point until K_max
                         k = (a.flags & FWBF_FLAG_EXECUTED_ROUNDS) ? k : a.max_iter;
@@ -802,10 +858,10 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
                             atomicXor(&s.tog[m >> 5], 1u << (m & 31));
                         }
                     }
-                    if (fl) atomicOr(&s.ctl[CTL_FLAGS], fl);
+                    if (fl) atomicOr(&s.ctl[fi], fl);
                 }
                 frame_sync<WAVE>();
-                const int flags = s.ctl[CTL_FLAGS];
+                const int flags = s.ctl[fi];
                 if (!(a.flags & FWBF_FLAG_NO_CYCLE_EXIT)) {
                     if (!(flags & F_ANY)) {  // no flip: fixed point until K_max
                         k = (a.flags & FWBF_FLAG_EXECUTED_ROUNDS) ? k : a.max_iter;
