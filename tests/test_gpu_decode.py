@@ -377,3 +377,49 @@ def test_strided_blocks_eg255(eg):
         kw = dict(select=fwbf.STRIDED, groups=G, weights=2, alpha=1.0, max_iter=20)
         print(f"case eg255 strided G={G}", flush=True)
         assert_same(gpu_decode(g, y, **kw), oracle_decode(o, y, **kw), f"eg255 strided {kw}")
+
+
+def _irregular_text(mb, nb, Z, seed):
+    """A base with zero blocks and blocks of two shifts (every column and row
+    keeps at least one and two entries): rows and columns of unequal degree."""
+    rng = np.random.default_rng(seed)
+    while True:
+        cells = []
+        for _ in range(mb * nb):
+            u = rng.random()
+            k = 0 if u < 0.25 else (2 if u > 0.85 else 1)
+            cells.append(sorted(rng.choice(Z, size=k, replace=False).tolist()))
+        cols = [sum(len(cells[i * nb + j]) for i in range(mb)) for j in range(nb)]
+        rows = [sum(len(cells[i * nb + j]) for j in range(nb)) for i in range(mb)]
+        if min(cols) >= 1 and min(rows) >= 2:
+            break
+    toks = [",".join(map(str, c)) if c else "-1" for c in cells]
+    lines = [" ".join(toks[i * nb:(i + 1) * nb]) for i in range(mb)]
+    return f"qc-ldpc v1\nZ {Z}\nbase {mb} {nb}\n" + "\n".join(lines) + "\n"
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.int8, np.int16])
+@pytest.mark.parametrize("T", [64, 256])
+def test_irregular_multishift_general_kernel(dt, T):
+    """The general kernel on an irregular base (zero blocks, two-shift blocks,
+    Z = 97 not a multiple of 64) at one and four wavefronts per frame: every
+    weight rule and selection, bit-exact with the oracle. (At four wavefronts
+    integer frames list every toggle and skip the claim pass, and blocks held
+    by one wavefront flip within the choice phase.)"""
+    need_gpu()
+    from paper_1206_3362_amd import fwbf
+    text = _irregular_text(4, 14, 97, 11)
+    g, o = fwbf.Code.from_text(text), O.Code.from_text(text)
+    assert "-1" in text and any("," in t for t in text.split())  # zero and two-shift blocks
+    rate = max(o.K, 1) / o.N
+    # 32 frames at 3 dB (most fail) and 32 at 6 dB (about 80% decode)
+    y = np.concatenate([synth.awgn_frames(g.N, 32, synth.sigma_for(eb, rate), T + int(eb), None, dt)
+                        for eb in (3.0, 6.0)])
+    sels = [dict(select=fwbf.GROUPS, groups=1), dict(select=fwbf.GROUPS, groups=5),
+            dict(select=fwbf.GROUPS, groups=97), dict(select=fwbf.SINGLE), dict(select=fwbf.TOPL, lam=4),
+            dict(select=fwbf.STRIDED, groups=7)]
+    for sel in sels:
+        for w in (0, 1, 2):
+            kw = dict(weights=w, alpha=0.3, alpha_num=1, alpha_den=3, max_iter=40, **sel)
+            print(f"case irregular N={g.N} dtype={np.dtype(dt).name} T={T} {kw}", flush=True)
+            assert_same(gpu_decode(g, y, threads_per_frame=T, **kw), oracle_decode(o, y, **kw), f"irregular T={T} {kw}")
