@@ -194,6 +194,13 @@ __device__ __forceinline__ uint32_t metric_val(const DecodeArgs &a, const Lds &s
     const uint32_t *ce = s.col + j * a.dvmax;
     const typename T::Chk *chk = (const typename T::Chk *)s.chk;
     if constexpr (T::isf) {
+        // y_n is read first (from global memory where its LDS copy shares the
+        // slots' memory) and its magnitude taken only at the end, so that the
+        // read's latency overlaps the check terms' LDS reads
+        // (a global-memory pointer: a generic load would also count as an LDS
+        // access, and the LDS waits below would wait for it)
+        typedef const __attribute__((address_space(1))) float gfloat;
+        float mg = a.mag_alias ? ((gfloat *)s.yrow)[n] : ((const float *)s.mag)[n];
         float S = 0.0f;
         auto term = [&](uint32_t e) {
             int r = c - (int)(e & 0xFFFF);
@@ -203,7 +210,33 @@ __device__ __forceinline__ uint32_t metric_val(const DecodeArgs &a, const Lds &s
             return ((s.syn[m >> 5] >> (m & 31)) & 1) ? w : -w;
         };
         if (!a.multi) {
-            for (int t = 0; t < deg; t++) S = (t == 0) ? term(ce[t]) : S + term(ce[t]);
+            // four terms' reads issued together, then added in list order
+            for (int t0 = 0; t0 < deg; t0 += 4) {
+                uint32_t e[4], m[4], sw[4], pp[4];
+                uint64_t cw[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    e[u] = ce[min(t0 + u, deg - 1)];
+                    int r = c - (int)(e[u] & 0xFFFF);
+                    r += (r < 0) ? a.Z : 0;
+                    m[u] = (e[u] >> 24) * a.Z + r;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    cw[u] = chk[m[u]];
+                    pp[u] = s.chkp[m[u]];
+                    sw[u] = s.syn[m[u] >> 5];
+                }
+                // (no branch here: a branch would let the compiler move the
+                // reads above into it, one after another)
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const float w = weight_f(cw[u], pp[u], (e[u] >> 16) & 0xFF, imwbf);
+                    const float tm = ((sw[u] >> (m[u] & 31)) & 1) ? w : -w;
+                    const float nS = (t0 + u == 0) ? tm : S + tm;
+                    S = t0 + u < deg ? nS : S;
+                }
+            }
         } else {
             // the shifts of one block row are listed in descending order:
             // start at the first shift <= c (row c - s), then wrap
@@ -222,7 +255,8 @@ __device__ __forceinline__ uint32_t metric_val(const DecodeArgs &a, const Lds &s
                 t0 = t1;
             }
         }
-        return orderable(__builtin_fmaf(-a.alpha, magnitude<DT>(a, s, n), S));
+        asm volatile("" : "+v"(mg));
+        return orderable(__builtin_fmaf(-a.alpha, fabsf(mg), S));
     } else {
         int32_t S = 0;
         for (int t = 0; t < deg; t++) {
