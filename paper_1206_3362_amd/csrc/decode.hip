@@ -169,25 +169,15 @@ __device__ __forceinline__ uint32_t orderable(float e)
 
 
 
-// |y_n| of the current frame
-template <int DT>
-__device__ __forceinline__ typename Tr<DT>::Mag magnitude(const DecodeArgs &a, const Lds &s, uint32_t n)
-{
-    using T = Tr<DT>;
-    if (!a.mag_alias) return ((const typename T::Mag *)s.mag)[n];
-    const typename T::Y v = ((const typename T::Y *)s.yrow)[n];
-    if constexpr (T::isf) return fabsf(v);
-    else return (typename T::Mag)(v < 0 ? -(int)v : (int)v);
-}
-
-// Metric of bit n (eq. (1)) from the current syndrome, as an order-
-// preserving 32-bit value: int inputs a_den*S - a_num*|y_n| + bias, float
-// inputs fmaf(-alpha, |y_n|, S) with S summed over M(n) in ascending check
-// order from the first term.
+// Metric of bit n (eq. (1)) of float inputs from the current syndrome, as an
+// order-preserving 32-bit value: fmaf(-alpha, |y_n|, S) with S summed over
+// M(n) in ascending check order from the first term.  (Integer inputs keep
+// their metrics exact under additions and never recompute them.)
 template <int DT>
 __device__ __forceinline__ uint32_t metric_val(const DecodeArgs &a, const Lds &s, uint32_t n, bool imwbf)
 {
     using T = Tr<DT>;
+    static_assert(T::isf, "float inputs only");
     const uint32_t j = fdiv(n, a.magZ, a.maskZ);
     const int c = (int)(n - j * a.Z);
     const int deg = s.cdeg[j];
@@ -257,17 +247,6 @@ __device__ __forceinline__ uint32_t metric_val(const DecodeArgs &a, const Lds &s
         }
         asm volatile("" : "+v"(mg));
         return orderable(__builtin_fmaf(-a.alpha, fabsf(mg), S));
-    } else {
-        int32_t S = 0;
-        for (int t = 0; t < deg; t++) {
-            const uint32_t e = ce[t];
-            int r = c - (int)(e & 0xFFFF);
-            r += (r < 0) ? a.Z : 0;
-            const uint32_t m = (e >> 24) * a.Z + r;
-            const int32_t w = weight_i<DT>(s, m, (e >> 16) & 0xFF, imwbf);
-            S += ((s.syn[m >> 5] >> (m & 31)) & 1) ? w : -w;
-        }
-        return (uint32_t)(a.aden * S - a.anum * (int32_t)magnitude<DT>(a, s, n) + (int32_t)a.bias);
     }
 }
 
@@ -533,6 +512,72 @@ __device__ __forceinline__ void int_check_minima(const DecodeArgs &a, const Lds 
     }
 }
 
+// Float magnitudes of the row-list entries q0 .. q0 + QL - 1 for the checks
+// r of one block row (lanes), reads issued together: min1 and min2 (with
+// multiplicity) as the bit patterns of non-negative floats, whose unsigned
+// order is the float order (a NaN's pattern lies above +inf, so a NaN never
+// becomes a minimum, as under float comparisons); pos takes the first entry
+// holding min1; neg collects, per member, [y < 0] as a lane mask (xor).
+template <int QL>
+__device__ __forceinline__ void row_fmins(const float *ys, const uint32_t *re, uint32_t Z, uint32_t r, uint32_t rm, int q0,
+                                          uint32_t &m1, uint32_t &m2, uint32_t &pos, unsigned long long &neg)
+{
+    uint32_t e[QL];
+    float v[QL];
+#pragma unroll
+    for (int u = 0; u < QL; u++) e[u] = __builtin_amdgcn_readfirstlane(re[q0 + u]);
+#pragma unroll
+    for (int u = 0; u < QL; u++) {
+        const uint32_t sft = e[u] & 0xFFFFu;
+        v[u] = ys[(e[u] >> 16) * Z + min(r + sft, rm + sft)];
+    }
+#pragma unroll
+    for (int u = 0; u < QL; u++) {
+        neg ^= __ballot(v[u] < 0.0f);
+        const uint32_t av = __float_as_uint(v[u]) & 0x7FFFFFFFu;
+        pos = av < m1 ? (uint32_t)(q0 + u) : pos;
+        m2 = med3u(m1, av, m2);
+        m1 = min(m1, av);
+    }
+}
+
+// Check minima and the syndrome s_0 of float inputs (the staged row holds
+// the signed values; the syndrome words start zeroed).
+template <int T>
+__device__ __forceinline__ void f32_check_minima(const DecodeArgs &a, const Lds &s, int tid, uint32_t lane)
+{
+    const float *ys = (const float *)s.mag;
+    const uint32_t Z = a.Z;
+    const int NZc = (int)((Z + 63) >> 6);
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    constexpr uint32_t INF = 0x7F800000u;
+    for (int ch = wv; ch < a.mb * NZc; ch += T / 64) {
+        const int i = ch / NZc;
+        const uint32_t r0 = (uint32_t)(ch - i * NZc) << 6, r = r0 + lane;
+        const bool valid = r < Z;
+        const uint32_t rr = valid ? r : 0u, rm = rr - Z;
+        const int deg = __builtin_amdgcn_readfirstlane(s.rdeg[i]);
+        const uint32_t *re = s.row + i * a.dcmax;
+        uint32_t m1 = INF, m2 = INF, pos = 0;
+        unsigned long long neg = 0;
+        int q0 = 0;
+        for (; q0 + 4 <= deg; q0 += 4) row_fmins<4>(ys, re, Z, rr, rm, q0, m1, m2, pos, neg);
+        if (deg - q0 == 3) row_fmins<3>(ys, re, Z, rr, rm, q0, m1, m2, pos, neg);
+        else if (deg - q0 == 2) row_fmins<2>(ys, re, Z, rr, rm, q0, m1, m2, pos, neg);
+        else if (deg - q0 == 1) row_fmins<1>(ys, re, Z, rr, rm, q0, m1, m2, pos, neg);
+        if (valid) {
+            const uint32_t m = (uint32_t)i * Z + rr;
+            ((uint64_t *)s.chk)[m] = (uint64_t)m1 | ((uint64_t)(deg < 2 ? 0u : m2) << 32);  // empty minimum: 0
+            s.chkp[m] = (uint8_t)pos;
+        }
+        const unsigned long long b = neg & __ballot(valid);
+        if (b) {
+            or_bits(s.syn, (uint32_t)i * Z + r0, b, lane);
+            if (lane == 0) atomicAdd(&s.ctl[CTL_WEIGHT], __popcll(b));
+        }
+    }
+}
+
 // Initial keys of integer inputs (eq. (1)): every bit gathers +-min1 of its
 // checks; padding slots get key 0; with IMWBF weights each check then moves
 // the metric of the member holding its min1 by +-a_den (min2 - min1) (that
@@ -650,12 +695,10 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
     using Tt = Tr<DT>;
     using Y = typename Tt::Y;
     using Mag = typename Tt::Mag;
-    using Chk = typename Tt::Chk;
     const int tid = WAVE ? (int)(threadIdx.x & 63) : (int)threadIdx.x, lane = tid & 63;
     const bool imwbf = a.weights == FWBF_IMWBF;
     const int N = a.N, M = a.M;
     Mag *mag = (Mag *)s.mag;
-    Chk *chk = (Chk *)s.chk;
     if (a.skip && a.skip[f]) return;  // the same answer for every thread of the frame
 
     // ---- Initialization: |y|, z_0 = [y < 0] (Section III) ----------------
@@ -678,8 +721,7 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
             if (n >= Nr) break;
             const bool neg = n < N && v[u] < (Y)0;
             if (n < N) {
-                if constexpr (Tt::isf) mag[n] = fabsf(v[u]);
-                else mag[n] = (Mag)v[u];  // integers: the signed value (magnitudes taken where used)
+                mag[n] = (Mag)v[u];  // the signed value (magnitudes taken where used)
             }
             const unsigned long long b = __ballot(neg);
             if (lane == 0) {
@@ -689,45 +731,13 @@ __device__ void decode_frame(const DecodeArgs &a, Lds s, int64_t f)
         }
     }
     for (int w = tid; w < (Mr >> 5); w += T) s.tog[w] = 0;
-    if constexpr (!Tt::isf)
-        for (int w = tid; w < (Mr >> 5); w += T) s.syn[w] = 0;
+    for (int w = tid; w < (Mr >> 5); w += T) s.syn[w] = 0;
     if (tid == 0) { s.ctl[CTL_FLAGS0] = 0; s.ctl[CTL_FLAGS0 + 1] = 0; s.ctl[CTL_WEIGHT] = 0; }
     frame_sync<WAVE>();
 
     // ---- check minima (weights) and the syndrome s_0 (Step 1 at k=0) -----
     if constexpr (!Tt::isf) int_check_minima<DT, T>(a, s, tid, (uint32_t)lane);
-    else for (int m = tid; m < Mr; m += T) {
-        bool par = false;
-        if (m < M) {
-            const uint32_t i = fdiv(m, a.magZ, a.maskZ);
-            const int r = m - (int)i * a.Z;
-            const int deg = s.rdeg[i];
-            const uint32_t *re = s.row + i * a.dcmax;
-            {
-                float m1 = __builtin_inff(), m2 = __builtin_inff();
-                uint32_t pos = 0;
-                for (int q = 0; q < deg; q++) {
-                    const uint32_t e = re[q];
-                    int cc = r + (int)(e & 0xFFFF);
-                    cc -= (cc >= a.Z) ? a.Z : 0;
-                    const uint32_t n = (e >> 16) * a.Z + cc;
-                    const float v = mag[n];
-                    par ^= (s.zw[n >> 5] >> (n & 31)) & 1;
-                    if (v < m1) { m2 = m1; m1 = v; pos = q; }
-                    else if (v < m2) m2 = v;
-                }
-                if (deg < 2) m2 = 0.0f;  // empty minimum over N(m) minus the member
-                chk[m] = pack_chk<DT>(__float_as_uint(m1), __float_as_uint(m2), 0);
-                s.chkp[m] = (uint8_t)pos;
-            }
-        }
-        const unsigned long long b = __ballot(par);
-        if (lane == 0) {
-            s.syn[m >> 5] = (uint32_t)b;
-            s.syn[(m >> 5) + 1] = (uint32_t)(b >> 32);
-            if (b) atomicAdd(&s.ctl[CTL_WEIGHT], __popcll(b));
-        }
-    }
+    else f32_check_minima<T>(a, s, tid, (uint32_t)lane);
     frame_sync<WAVE>();
 
     int k = 0, okf = 0;
