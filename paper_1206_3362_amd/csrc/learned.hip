@@ -591,7 +591,7 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
 // rank is scored by lane c % 32 of wavefront c / 32.
 constexpr int WIDE_T = 1024;
 constexpr uint32_t WSAT = 4095;
-constexpr int CW_WEIGHT = 0, CW_FLAGS = 1, CW_NTOG = 2;
+constexpr int CW_WEIGHT = 0, CW_FLAGS = 1, CW_NTOG = 2, CW_SAT = 3;
 
 struct WideArgs {
     const void *y;
@@ -732,6 +732,12 @@ __global__ __launch_bounds__(WIDE_T) void learned_wide_kernel(WideArgs a)
         const uint32_t pos = l + ((uint32_t)kk << a.logL);
         realm |= (uint64_t)(gact && (int)pos < a.p && (int)(gp + pos) < N) << kk;
     }
+    const int nreal = __popcll(realm);  // the real slots are the thread's first nreal
+    // slot kk0 + u (kk0 a multiple of 4, u < 4) of this thread: sbase +
+    // ((kk0 ^ swk) << logL) + offu[u], the swizzle split over the two parts
+    uint32_t offu[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) offu[u] = ((uint32_t)u ^ (swk & 3u)) << a.logL;
     const bool scorer = (int)wv < a.tpr;  // wavefront-uniform
     const uint32_t j = lane & 31, c = 32 * wv + j;
     const bool blead = scorer && lane < 32 && (j % a.k) == 0 && (int)c < a.NC;
@@ -748,7 +754,7 @@ __global__ __launch_bounds__(WIDE_T) void learned_wide_kernel(WideArgs a)
     bool have = false;  // pre[] holds this frame's row
     for (int64_t f = fr.first; f < fr.end; f += fr.step) {
         const Y *yrow = (const Y *)a.y + f * a.stride;
-        if (tid == 0) { ctl[CW_WEIGHT] = 0; ctl[CW_FLAGS] = 0; ctl[CW_NTOG] = 0; }
+        if (tid == 0) { ctl[CW_WEIGHT] = 0; ctl[CW_FLAGS] = 0; ctl[CW_NTOG] = 0; ctl[CW_SAT] = 0; }
         {
             // ---- the row into LDS, over the slots (y of bit n at element n)
             uint32_t *stw = slots;
@@ -840,6 +846,7 @@ __global__ __launch_bounds__(WIDE_T) void learned_wide_kernel(WideArgs a)
             {
                 int ch = (int)wv;
                 int xn = 0;
+                uint32_t maxav = 0;  // (lanes past a column's end read a real bit of it)
                 if (ch < dc * NZc) {
                     const int jb = ch / NZc;
                     const uint32_t c = ((uint32_t)(ch - jb * NZc) << 6) + lane;
@@ -878,7 +885,10 @@ __global__ __launch_bounds__(WIDE_T) void learned_wide_kernel(WideArgs a)
                     if (c < Z)
                         slots[wide_slot(a, (uint32_t)jb * Z + c)] =
                             ((2u * su - sw) << 14) | (min(av, WSAT) << 2) | uu;
+                    maxav = max(maxav, av);
                 }
+                // some magnitude saturates its field: the scan then reads it from global memory
+                if (__ballot(maxav >= WSAT) && lane == 0) ctl[CW_SAT] = 1;
             }
             __syncthreads();
             // ---- the member of each check at min1 takes min2: one correction
@@ -914,6 +924,7 @@ __global__ __launch_bounds__(WIDE_T) void learned_wide_kernel(WideArgs a)
         int t = 0, okf = 0, rec_end = 0;
         uint32_t prv = NONE;
         const uint32_t *cw = a.pool ? a.pool + (size_t)((a.f0 + f) % a.pool_n) * NW : nullptr;
+        const bool anysat = DT == FWBF_I16 && ctl[CW_SAT] != 0;  // uniform
         for (;;) {
             if (ctl[CW_WEIGHT] == 0) { okf = 1; break; }
             if (t == a.T) break;
@@ -925,24 +936,32 @@ __global__ __launch_bounds__(WIDE_T) void learned_wide_kernel(WideArgs a)
                 float bE = -__builtin_huge_valf();
                 uint32_t bi = NONE;
                 // four slot reads in flight at a time (the loop itself is not
-                // unrolled: register pressure at 1024 threads per workgroup)
+                // unrolled: register pressure at 1024 threads per workgroup);
+                // two forms: one proposal per block and no saturated magnitude
+                // in the frame (the live slots are the real ones), or any case
+                auto scan = [&](auto one) {
+                    constexpr bool K1 = decltype(one)::value;
 #pragma unroll 1
-                for (int kk = 0; kk < C; kk += 4) {
-                    uint32_t v[4];
+                    for (int kk = 0; kk < C; kk += 4) {
+                        uint32_t v[4];
+                        const uint32_t base = sbase + (((uint32_t)kk ^ (swk & ~3u)) << a.logL);
 #pragma unroll
-                    for (int u = 0; u < 4; u++) v[u] = slots[sbase + ((((uint32_t)(kk + u)) ^ swk) << a.logL)];
+                        for (int u = 0; u < 4; u++) v[u] = slots[base + offu[u]];
 #pragma unroll
-                    for (int u = 0; u < 4; u++) {
-                        const bool live = (livem >> (kk + u)) & 1;
-                        uint32_t av = (v[u] >> 2) & WSAT;
-                        if constexpr (DT == FWBF_I16)
-                            if (live && av == WSAT) av = wide_mag<DT>(yrow, gp + l + ((uint32_t)(kk + u) << a.logL));
-                        const float E = __builtin_fmaf(-al, (float)av, be * (float)((int32_t)v[u] >> 14));
-                        const bool take = live && E > bE;
-                        bE = take ? E : bE;
-                        bi = take ? (uint32_t)(kk + u) : bi;
+                        for (int u = 0; u < 4; u++) {
+                            const bool live = K1 ? kk + u < nreal : ((livem >> (kk + u)) & 1) != 0;
+                            uint32_t av = (v[u] >> 2) & WSAT;
+                            if constexpr (DT == FWBF_I16 && !K1)
+                                if (live && av == WSAT) av = wide_mag<DT>(yrow, gp + l + ((uint32_t)(kk + u) << a.logL));
+                            const float E = __builtin_fmaf(-al, (float)av, be * (float)((int32_t)v[u] >> 14));
+                            const bool take = live && E > bE;
+                            bE = take ? E : bE;
+                            bi = take ? (uint32_t)(kk + u) : bi;
+                        }
                     }
-                }
+                };
+                if (a.k == 1 && !anysat) scan(std::true_type{});
+                else scan(std::false_type{});
                 const uint32_t nme = gp + l + (bi << a.logL);
                 unsigned long long best = bi == NONE ? 0ull : (((unsigned long long)orderable(bE) << 32) | (0xFFFFFFFFu - nme));
                 best = group_max64(best, a.L);
