@@ -79,6 +79,44 @@ def _near_tie(scores):
     return False
 
 
+def _check_against_reference(name, g, o, y, p, dt, A, T, G, k, pG):
+    """Decode y with the wide learned pass and compare frame by frame with
+    the float64 reference (see the test below for the bar)."""
+    Fn = y.shape[0]
+    lp = fwbf.LearnedParams(T, G, k, A)
+    plain = fwbf.DecodeParams(dtype=dt, groups=pG, max_iter=100, flags=fwbf.FLAG_GENERIC_KERNEL)
+    rec = fwbf.record_buffer(Fn, T, G, k)
+    print(f"wide learned pass {name}: N={g.N} frames={Fn}", flush=True)
+    z, it, ok, lok = fwbf.decode_learned(g, torch.from_numpy(y).cuda(), plain, lp, torch.from_numpy(p).cuda(),
+                                         records=rec)
+    torch.cuda.synchronize()
+    zg = O.unpack(z.cpu().numpy().view(np.uint32), o.N)
+    itg, okg, lokg = it.cpu().numpy(), ok.cpu().numpy().astype(bool), lok.cpu().numpy().astype(bool)
+    zf, itf, okf, okr, tr = _reference(o, y, p, T, G, k, A, pG)
+    rg = fwbf.records_host(rec)
+    for f in range(Fn):
+        assert _round0_matches(rg, tr, f), (name, f)
+    same = (zg == zf).all(1) & (itg == itf) & (okg == okf) & (lokg == okr)
+    near = 0
+    for f in range(Fn):
+        # every round's proposals, up to the first round that a near-tie may
+        # have decided differently
+        rounds = R.trace_of_frame(tr, f)
+        decide = len(rounds) - 1
+        parted = False
+        for t_, (cand, _) in enumerate(rounds):
+            n_gpu = rg[f, t_]["n"][rg[f, t_]["valid"] == 1].astype(np.int64)
+            if not np.array_equal(n_gpu, cand.ravel()[cand.ravel() >= 0]):
+                decide, parted = t_ - 1, True
+                break
+        if parted or not same[f]:
+            assert decide >= 0 and _near_tie(rounds[decide][1]), (name, f, decide)
+            near += 1
+    print(f"{name}: {int(same.sum())}/{Fn} frames identical, {near} near-tie differences, "
+          f"learned-pass successes {int(lokg.sum())} (reference {int(okr.sum())})", flush=True)
+    assert same.mean() >= 0.9
+
+
 CASES = [
     # name, (mb, nb, Z, seed, min_girth), dtype, A, T, G, k, frames, Eb/N0, plain G
     ("n930_i16_g64", (3, 30, 31, 21, 4), fwbf.I16, 256.0, 6, 64, 1, 48, 6.0, 16),
@@ -102,35 +140,31 @@ def test_wide_learned_pass_matches_reference(name, spec, dt, A, T, G, k, Fn, eb,
     p[-2 * T:-T] = 0.2
     p[-T:] = 1.0
     y = _frames(o, Fn, eb, 5, dt)
-    lp = fwbf.LearnedParams(T, G, k, A)
-    plain = fwbf.DecodeParams(dtype=dt, groups=pG, max_iter=100, flags=fwbf.FLAG_GENERIC_KERNEL)
-    rec = fwbf.record_buffer(Fn, T, G, k)
-    print(f"wide learned pass {name}: N={g.N} frames={Fn}", flush=True)
-    z, it, ok, lok = fwbf.decode_learned(g, torch.from_numpy(y).cuda(), plain, lp, torch.from_numpy(p).cuda(),
-                                         records=rec)
-    torch.cuda.synchronize()
-    zg = O.unpack(z.cpu().numpy().view(np.uint32), o.N)
-    itg, okg, lokg = it.cpu().numpy(), ok.cpu().numpy().astype(bool), lok.cpu().numpy().astype(bool)
-    zf, itf, okf, okr, tr = _reference(o, y, p, T, G, k, A, pG)
-    rg = fwbf.records_host(rec)
-    for f in range(Fn):
-        assert _round0_matches(rg, tr, f), (name, f)
-    same = (zg == zf).all(1) & (itg == itf) & (okg == okf) & (lokg == okr)
-    near = 0
-    for f in np.nonzero(~same)[0]:
-        rounds = R.trace_of_frame(tr, f)
-        decide = len(rounds) - 1
-        for t_, (cand, _) in enumerate(rounds):
-            n_gpu = rg[f, t_]["n"][rg[f, t_]["valid"] == 1].astype(np.int64)
-            if not np.array_equal(n_gpu, cand.ravel()[cand.ravel() >= 0]):
-                decide = t_ - 1
-                break
-        assert decide >= 0 and _near_tie(rounds[decide][1]), (name, f, decide)
-        near += 1
-    print(f"{name}: {int(same.sum())}/{Fn} frames identical, {near} near-tie differences, "
-          f"learned-pass successes {int(lokg.sum())} (reference {int(okr.sum())})", flush=True)
-    assert same.mean() >= 0.9
+    _check_against_reference(name, g, o, y, p, dt, A, T, G, k, pG)
 
+
+
+@pytest.mark.parametrize("spec,k,G,pG", [((3, 30, 31, 21, 4), 1, 64, 16), ((3, 30, 31, 22, 4), 4, 16, 8)],
+                         ids=["k1", "k4"])
+def test_wide_saturated_magnitudes_match_reference(spec, k, G, pG):
+    """int16 frames scaled up 12-fold (clipped to the documented +-32767):
+    the slot words hold min(|y|, 4095), so frames with a magnitude at or
+    above 4095 take the general scan, which reads those magnitudes from the
+    frame itself; the rest of the batch (unscaled frames) keeps the
+    one-proposal fast scan.  Same bar as the unscaled cases."""
+    g = fwbf.Code.from_seed(*spec)
+    o = O.Code.from_seed(*spec)
+    T = 6
+    p = random_params(T, 43)
+    p[-2 * T:-T] = 0.2
+    p[-T:] = 1.0
+    y = _frames(o, 48, 6.0, 9, fwbf.I16).astype(np.int32)
+    y[::2] = np.clip(y[::2] * 12, -32767, 32767)
+    y = y.astype(np.int16)
+    big = (np.abs(y[::2].astype(np.int32)) >= 4095).mean()
+    assert big > 0.05 and (np.abs(y[1::2].astype(np.int32)) < 4095).all()
+    print(f"saturated share of the scaled frames: {big:.3f}", flush=True)
+    _check_against_reference(f"saturated_{k}", g, o, y, p, fwbf.I16, 256.0, T, G, k, pG)
 
 def test_wide_kernel_equals_wave_kernel_on_checkpoint():
     """The committed N = 1008 scorer (T = 16, 32 blocks, k = 1) on 4096 int8
