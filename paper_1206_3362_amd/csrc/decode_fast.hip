@@ -368,55 +368,74 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                     }
                 }
                 // ---- flip, toggle the syndrome, update the member metrics --
-                // the winners flip their bits and list them; then one lane per
-                // (winner, check) pair toggles the check and adds +-2 a_den w
-                // to the metrics of the check's members, the sign given by
-                // the check's new bit (two winners toggling one check are
-                // serialised by the atomics: their changes cancel exactly)
-                const int rank = __popcll(fmask & ((1ull << lane) - 1));
-                if (flip) {
-                    atomicXor(&zw[n >> 5], 1u << (n & 31));
-                    flips[rank] = n;
-                }
-                wave_sync();
+                // the winners flip their bits; one lane per (winner, check)
+                // pair toggles the check and adds +-2 a_den w to the metrics
+                // of the check's members, the sign given by the check's new
+                // bit (two winners toggling one check are serialised by the
+                // atomics: their changes cancel exactly)
                 const int nflip = __popcll(fmask);
-                const int ntog = nflip * DV;
                 int sum_ones = 0;  // toggles that leave their check unsatisfied
-                constexpr uint32_t DVM = ((1u << 16) + DV - 1) / DV;  // i / DV = (i * DVM) >> 16 for i < 2^12
-                for (int base = 0; base < ntog; base += 64) {
-                    const int i = base + (int)lane;
-                    uint32_t nb1 = 0;
-                    if (i < ntog) {
-                        const uint32_t u = mul24((uint32_t)i, DVM) >> 16;
-                        const uint32_t t = (uint32_t)i - mul24(u, (uint32_t)DV);
-                        const uint32_t nf = flips[u];
-                        const uint32_t j = mul24(nf, a.rZ24) >> 20;  // block column: nf / Z
-                        const uint32_t c = nf - mul24(j, Z);
-                        const uint32_t *st = sh + mul24(t, (uint32_t)a.nb);
-                        const uint32_t rr = submod(c, st[j], Z);
-                        const uint32_t m = mul24(t, Z) + rr;
-                        const uint32_t old = atomicXor(&syn[m >> 5], 1u << (m & 31));
-                        nb1 = ((old >> (m & 31)) & 1u) ^ 1u;
-                        // the check's two weights and the position of its minimum
-                        uint32_t w1, w2, pos;
-                        if constexpr (DT == FWBF_I8) {
-                            const uint32_t cw = chk[m];
-                            w1 = cw & 0xFF; w2 = (cw >> 8) & 0xFF; pos = (cw >> 16) & 0xFF;
-                        } else {
-                            const uint32_t cw = chk[m];
-                            w1 = cw & 0xFFFF; w2 = cw >> 16; pos = chkp[m];
-                        }
-                        const uint32_t e1 = mul24(2u * (uint32_t)a.aden, w1) << a.idxb;
-                        const uint32_t e2 = a.imwbf ? mul24(2u * (uint32_t)a.aden, w2) << a.idxb : e1;
-                        const uint32_t d1 = nb1 ? e1 : 0u - e1, d2 = nb1 ? e2 : 0u - e2;
-                        // every member's slot first, then the adds
-                        uint32_t sl[DC];
-#pragma unroll
-                        for (int q = 0; q < DC; q++) sl[q] = slotof[mul24((uint32_t)q, Z) + addmod(rr, st[q], Z)];
-#pragma unroll
-                        for (int q = 0; q < DC; q++) atomicAdd(&keys[sl[q]], pos == (uint32_t)q ? d2 : d1);
+                // (winner, check) lane: toggle check t of the winner, then add
+                // +-2 a_den w to the check's members
+                auto toggle = [&](uint32_t nf, uint32_t t) -> uint32_t {
+                    const uint32_t j = mul24(nf, a.rZ24) >> 20;  // block column: nf / Z
+                    const uint32_t c = nf - mul24(j, Z);
+                    const uint32_t *st = sh + mul24(t, (uint32_t)a.nb);
+                    const uint32_t rr = submod(c, st[j], Z);
+                    const uint32_t m = mul24(t, Z) + rr;
+                    const uint32_t old = atomicXor(&syn[m >> 5], 1u << (m & 31));
+                    const uint32_t nb1 = ((old >> (m & 31)) & 1u) ^ 1u;
+                    // the check's two weights and the position of its minimum
+                    uint32_t w1, w2, pos;
+                    if constexpr (DT == FWBF_I8) {
+                        const uint32_t cw = chk[m];
+                        w1 = cw & 0xFF; w2 = (cw >> 8) & 0xFF; pos = (cw >> 16) & 0xFF;
+                    } else {
+                        const uint32_t cw = chk[m];
+                        w1 = cw & 0xFFFF; w2 = cw >> 16; pos = chkp[m];
                     }
-                    sum_ones += __popcll(__ballot(nb1));
+                    const uint32_t e1 = mul24(2u * (uint32_t)a.aden, w1) << a.idxb;
+                    const uint32_t e2 = a.imwbf ? mul24(2u * (uint32_t)a.aden, w2) << a.idxb : e1;
+                    const uint32_t d1 = nb1 ? e1 : 0u - e1, d2 = nb1 ? e2 : 0u - e2;
+                    // every member's slot first, then the adds
+                    uint32_t sl[DC];
+#pragma unroll
+                    for (int q = 0; q < DC; q++) sl[q] = slotof[mul24((uint32_t)q, Z) + addmod(rr, st[q], Z)];
+#pragma unroll
+                    for (int q = 0; q < DC; q++) atomicAdd(&keys[sl[q]], pos == (uint32_t)q ? d2 : d1);
+                    return nb1;
+                };
+                if (a.L >= DV) {
+                    // every lane of a block holds the block's winner after the
+                    // butterfly: lane t < DV of the block takes check t, and
+                    // the lead lane flips the bit
+                    if (flip) atomicXor(&zw[n >> 5], 1u << (n & 31));
+                    const uint32_t t = lane & (uint32_t)(a.L - 1);
+                    const bool tog = t < (uint32_t)DV && (int)g < a.Geff && (a.single || val > a.zero_val);
+                    uint32_t nb1 = 0;
+                    if (tog) nb1 = toggle(n, t);
+                    sum_ones = __popcll(__ballot(nb1));
+                } else {
+                    // fewer lanes than checks per block: the winners are
+                    // listed and one lane per (winner, check) pair takes it
+                    const int rank = __popcll(fmask & ((1ull << lane) - 1));
+                    if (flip) {
+                        atomicXor(&zw[n >> 5], 1u << (n & 31));
+                        flips[rank] = n;
+                    }
+                    wave_sync();
+                    const int ntog = nflip * DV;
+                    constexpr uint32_t DVM = ((1u << 16) + DV - 1) / DV;  // i / DV = (i * DVM) >> 16 for i < 2^12
+                    for (int base = 0; base < ntog; base += 64) {
+                        const int i = base + (int)lane;
+                        uint32_t nb1 = 0;
+                        if (i < ntog) {
+                            const uint32_t u = mul24((uint32_t)i, DVM) >> 16;
+                            const uint32_t t = (uint32_t)i - mul24(u, (uint32_t)DV);
+                            nb1 = toggle(flips[u], t);
+                        }
+                        sum_ones += __popcll(__ballot(nb1));
+                    }
                 }
                 weight += 2 * sum_ones - DV * nflip;
                 k += 1;
