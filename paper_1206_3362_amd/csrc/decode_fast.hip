@@ -52,6 +52,10 @@ struct FastArgs {
     int single, imwbf, max_iter, cycle_exit, vec_ok;
     int exec_rounds;  // report the rounds run before a repeated state (diagnostic)
     int aden, anum, idxb;
+    // a_den << idxb and 2 a_den << idxb (24-bit multiplicands of the check
+    // weights), -(a_num << idxb) (signed 24-bit multiplicand of |y|)
+    uint32_t kden, kden2;
+    int nknum;
     uint32_t idxmask, bias, zero_val;
     // LDS offsets in bytes
     // LDS: tables shared by the workgroup (o_sh, o_slot), then one region of
@@ -130,11 +134,143 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Initialisation of check m = i Z + r (block row i; member q is bit
+// q Z + ((r + js[q]) mod Z)): its two smallest |y| and the position of the
+// first into chk (chkp for int16), its term of eq. (1) pushed to the slots of
+// its members (the first block row also adds -a_num |y_n|, once per bit);
+// returns the check's syndrome bit.
+template <int DT, int DC>
+__device__ __forceinline__ uint32_t check_init(const FastArgs &a, int i, uint32_t r, const uint32_t (&js)[DC],
+                                               const typename FT<DT>::Y *yv, const uint16_t *slotof,
+                                               uint32_t *keys, uint32_t *chk, uint8_t *chkp)
+{
+    constexpr int QB = DC <= 2 ? 1 : DC <= 4 ? 2 : DC <= 8 ? 3 : DC <= 16 ? 4 : DC <= 32 ? 5 : 6;  // bits of q
+    const uint32_t Z = a.Z;
+    uint32_t nn[DC], av[DC], sl[DC];
+    int yq[DC];
+    uint32_t par = 0;
+    // every LDS read of the check first (its members' values
+    // and slots), so that they are in flight together and
+    // none waits behind the atomic pushes below
+    // member q is bit q Z + ((r + s_q) mod Z): the block
+    // offsets q Z are uniform, only the rotation is per lane
+#pragma unroll
+    for (int q = 0; q < DC; q++) nn[q] = addmod(r, js[q], Z);
+#pragma unroll
+    for (int q = 0; q < DC; q++) yq[q] = (int)(yv + q * Z)[nn[q]];
+#pragma unroll
+    for (int q = 0; q < DC; q++) sl[q] = (slotof + q * Z)[nn[q]];
+    // the two smallest keys |y| << QB | q: their magnitudes are
+    // min1 and min2 (with multiplicity), the first one's q is
+    // the lowest position holding min1
+    uint32_t k1 = 0xFFFFFFFFu, k2 = 0xFFFFFFFFu;
+    if constexpr (DT == FWBF_I8 && DC == 6) {
+        // int8 keys fit 16 bits (|y| <= 128): three pairs of
+        // members in packed 16-bit lanes; per half the
+        // smallest and second smallest of three, then the two
+        // halves merged (second smallest of six = the smaller
+        // of the larger first minimum and the smaller second
+        // minimum)
+        typedef short s16x2 __attribute__((ext_vector_type(2)));
+        typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+        u16x2 P[3];
+        uint32_t px = 0;
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            const s16x2 v = {(short)yq[2 * j], (short)yq[2 * j + 1]};
+            px ^= __builtin_bit_cast(uint32_t, v);
+            const s16x2 av2 = __builtin_elementwise_max(v, -v);
+            const u16x2 qq = {(unsigned short)(2 * j), (unsigned short)(2 * j + 1)};
+            P[j] = (__builtin_bit_cast(u16x2, av2) << (unsigned short)QB) | qq;
+            av[2 * j] = (uint32_t)av2.x;
+            av[2 * j + 1] = (uint32_t)av2.y;
+        }
+        const u16x2 A = __builtin_elementwise_min(P[0], P[1]), B = __builtin_elementwise_max(P[0], P[1]);
+        const u16x2 S1 = __builtin_elementwise_min(A, P[2]);
+        const u16x2 S2 = __builtin_elementwise_min(B, __builtin_elementwise_max(A, P[2]));
+        k1 = min((uint32_t)S1.x, (uint32_t)S1.y);
+        k2 = min(max((uint32_t)S1.x, (uint32_t)S1.y), min((uint32_t)S2.x, (uint32_t)S2.y));
+        par = ((px >> 15) ^ (px >> 31)) & 1u;  // parity of the negative members
+    } else {
+        uint32_t sx = 0;
+#pragma unroll
+        for (int q = 0; q < DC; q++) {
+            const int v = yq[q];
+            const uint32_t av_ = (uint32_t)(v < 0 ? -v : v);
+            av[q] = av_;
+            sx ^= (uint32_t)v;  // bit 31: parity of the negative members
+            const uint32_t key = (av_ << QB) | (uint32_t)q;
+            k2 = min(k2, max(k1, key));
+            k1 = min(k1, key);
+        }
+        par = sx >> 31;
+    }
+    const uint32_t m1 = k1 >> QB, pos = k1 & ((1u << QB) - 1);
+    const uint32_t m2 = DC < 2 ? 0u : (k2 >> QB);
+    const uint32_t m = i * Z + r;
+    if constexpr (DT == FWBF_I8) {
+        chk[m] = m1 | (m2 << 8) | (pos << 16);
+    } else {
+        chk[m] = m1 | (m2 << 16);
+        chkp[m] = (uint8_t)pos;
+    }
+    // push this check's term of eq. (1) to its members: the
+    // two signed values (a_den w << idxb) are formed once
+    // (minima are at most 32768: 16 bits)
+    const uint32_t e1 = mul24(a.kden, m1 & 0xFFFFu);
+    const uint32_t e2 = a.imwbf ? mul24(a.kden, m2 & 0xFFFFu) : e1;
+    const uint32_t d1 = par ? e1 : 0u - e1, d2 = par ? e2 : 0u - e2;
+#pragma unroll
+    for (int q = 0; q < DC; q++) {
+        uint32_t d = pos == (uint32_t)q ? d2 : d1;
+        if (i == 0) d += (uint32_t)__mul24((int)av[q], a.nknum);  // - a_num |y| << idxb
+        atomicAdd(&keys[sl[q]], d);
+    }
+    return par;
+}
+
+// Round update of check t of the flipped bit nf: toggles the check's
+// syndrome bit (an LDS xor returning the old word) and adds +-2 a_den w to
+// the metrics of its members, the sign given by the new bit; returns the new
+// bit (1: the check is now unsatisfied).
+template <int DT, int DC>
+__device__ __forceinline__ uint32_t toggle_check(const FastArgs &a, uint32_t nf, uint32_t t, const uint32_t *sh,
+                                                 const uint16_t *slotof, uint32_t *syn, const uint32_t *chk,
+                                                 const uint8_t *chkp, uint32_t *keys)
+{
+    const uint32_t Z = a.Z;
+    const uint32_t j = mul24(nf, a.rZ24) >> 20;  // block column: nf / Z
+    const uint32_t c = nf - mul24(j, Z);
+    const uint32_t *st = sh + mul24(t, (uint32_t)a.nb);
+    const uint32_t rr = submod(c, st[j], Z);
+    const uint32_t m = mul24(t, Z) + rr;
+    const uint32_t old = atomicXor(&syn[m >> 5], 1u << (m & 31));
+    const uint32_t nb1 = ((old >> (m & 31)) & 1u) ^ 1u;
+    // the check's two weights and the position of its minimum
+    uint32_t w1, w2, pos;
+    if constexpr (DT == FWBF_I8) {
+        const uint32_t cw = chk[m];
+        w1 = cw & 0xFF; w2 = (cw >> 8) & 0xFF; pos = (cw >> 16) & 0xFF;
+    } else {
+        const uint32_t cw = chk[m];
+        w1 = cw & 0xFFFF; w2 = cw >> 16; pos = chkp[m];
+    }
+    const uint32_t e1 = mul24(a.kden2, w1);
+    const uint32_t e2 = a.imwbf ? mul24(a.kden2, w2) : e1;
+    const uint32_t d1 = nb1 ? e1 : 0u - e1, d2 = nb1 ? e2 : 0u - e2;
+    // every member's slot first, then the adds
+    uint32_t sl[DC];
+#pragma unroll
+    for (int q = 0; q < DC; q++) sl[q] = slotof[mul24((uint32_t)q, Z) + addmod(rr, st[q], Z)];
+#pragma unroll
+    for (int q = 0; q < DC; q++) atomicAdd(&keys[sl[q]], pos == (uint32_t)q ? d2 : d1);
+    return nb1;
+}
+
 template <int DT, int DV, int DC, int C>
 __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu(5))) void fast_kernel(FastArgs a)
 {
     using Y = typename FT<DT>::Y;
-    constexpr int QB = DC <= 2 ? 1 : DC <= 4 ? 2 : DC <= 8 ? 3 : DC <= 16 ? 4 : DC <= 32 ? 5 : 6;  // bits of q
     extern __shared__ __align__(16) unsigned char smem[];
     // the wavefront index is uniform across the wavefront: in a scalar
     // register, so LDS base addresses derived from it are scalar too
@@ -242,88 +378,7 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
             for (uint32_t r0 = 0; r0 < Z; r0 += 64) {
                 const uint32_t r = r0 + lane;
                 const bool valid = r < Z;
-                uint32_t nn[DC], av[DC], sl[DC];
-                int yq[DC];
-                uint32_t par = 0;
-                if (valid) {
-                    // every LDS read of the check first (its members' values
-                    // and slots), so that they are in flight together and
-                    // none waits behind the atomic pushes below
-                    // member q is bit q Z + ((r + s_q) mod Z): the block
-                    // offsets q Z are uniform, only the rotation is per lane
-#pragma unroll
-                    for (int q = 0; q < DC; q++) nn[q] = addmod(r, js[q], Z);
-#pragma unroll
-                    for (int q = 0; q < DC; q++) yq[q] = (int)yv[q * Z + nn[q]];
-#pragma unroll
-                    for (int q = 0; q < DC; q++) sl[q] = slotof[q * Z + nn[q]];
-                    // the two smallest keys |y| << QB | q: their magnitudes are
-                    // min1 and min2 (with multiplicity), the first one's q is
-                    // the lowest position holding min1
-                    uint32_t k1 = 0xFFFFFFFFu, k2 = 0xFFFFFFFFu;
-                    if constexpr (DT == FWBF_I8 && DC == 6) {
-                        // int8 keys fit 16 bits (|y| <= 128): three pairs of
-                        // members in packed 16-bit lanes; per half the
-                        // smallest and second smallest of three, then the two
-                        // halves merged (second smallest of six = the smaller
-                        // of the larger first minimum and the smaller second
-                        // minimum)
-                        typedef short s16x2 __attribute__((ext_vector_type(2)));
-                        typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-                        u16x2 P[3];
-                        uint32_t px = 0;
-#pragma unroll
-                        for (int j = 0; j < 3; j++) {
-                            const s16x2 v = {(short)yq[2 * j], (short)yq[2 * j + 1]};
-                            px ^= __builtin_bit_cast(uint32_t, v);
-                            const s16x2 av2 = __builtin_elementwise_max(v, -v);
-                            const u16x2 qq = {(unsigned short)(2 * j), (unsigned short)(2 * j + 1)};
-                            P[j] = (__builtin_bit_cast(u16x2, av2) << (unsigned short)QB) | qq;
-                            av[2 * j] = (uint32_t)av2.x;
-                            av[2 * j + 1] = (uint32_t)av2.y;
-                        }
-                        const u16x2 A = __builtin_elementwise_min(P[0], P[1]), B = __builtin_elementwise_max(P[0], P[1]);
-                        const u16x2 S1 = __builtin_elementwise_min(A, P[2]);
-                        const u16x2 S2 = __builtin_elementwise_min(B, __builtin_elementwise_max(A, P[2]));
-                        k1 = min((uint32_t)S1.x, (uint32_t)S1.y);
-                        k2 = min(max((uint32_t)S1.x, (uint32_t)S1.y), min((uint32_t)S2.x, (uint32_t)S2.y));
-                        par = ((px >> 15) ^ (px >> 31)) & 1u;  // parity of the negative members
-                    } else {
-                        uint32_t sx = 0;
-#pragma unroll
-                        for (int q = 0; q < DC; q++) {
-                            const int v = yq[q];
-                            const uint32_t av_ = (uint32_t)(v < 0 ? -v : v);
-                            av[q] = av_;
-                            sx ^= (uint32_t)v;  // bit 31: parity of the negative members
-                            const uint32_t key = (av_ << QB) | (uint32_t)q;
-                            k2 = min(k2, max(k1, key));
-                            k1 = min(k1, key);
-                        }
-                        par = sx >> 31;
-                    }
-                    const uint32_t m1 = k1 >> QB, pos = k1 & ((1u << QB) - 1);
-                    const uint32_t m2 = DC < 2 ? 0u : (k2 >> QB);
-                    const uint32_t m = i * Z + r;
-                    if constexpr (DT == FWBF_I8) {
-                        chk[m] = m1 | (m2 << 8) | (pos << 16);
-                    } else {
-                        chk[m] = m1 | (m2 << 16);
-                        chkp[m] = (uint8_t)pos;
-                    }
-                    // push this check's term of eq. (1) to its members: the
-                    // two signed values (a_den w << idxb) are formed once
-                    // (minima are at most 32768: 16 bits)
-                    const uint32_t e1 = mul24((uint32_t)a.aden, m1 & 0xFFFFu) << a.idxb;
-                    const uint32_t e2 = a.imwbf ? mul24((uint32_t)a.aden, m2 & 0xFFFFu) << a.idxb : e1;
-                    const uint32_t d1 = par ? e1 : 0u - e1, d2 = par ? e2 : 0u - e2;
-#pragma unroll
-                    for (int q = 0; q < DC; q++) {
-                        uint32_t d = pos == (uint32_t)q ? d2 : d1;
-                        if (i == 0) d -= mul24((uint32_t)a.anum, av[q]) << a.idxb;
-                        atomicAdd(&keys[sl[q]], d);
-                    }
-                }
+                const uint32_t par = valid ? check_init<DT, DC>(a, i, r, js, yv, slotof, keys, chk, chkp) : 0u;
                 const unsigned long long b = __ballot(valid && par);
                 weight += __popcll(b);
                 // syndrome words: checks i*Z + r0 .. +63 (not word aligned in general)
@@ -377,34 +432,6 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                 int sum_ones = 0;  // toggles that leave their check unsatisfied
                 // (winner, check) lane: toggle check t of the winner, then add
                 // +-2 a_den w to the check's members
-                auto toggle = [&](uint32_t nf, uint32_t t) -> uint32_t {
-                    const uint32_t j = mul24(nf, a.rZ24) >> 20;  // block column: nf / Z
-                    const uint32_t c = nf - mul24(j, Z);
-                    const uint32_t *st = sh + mul24(t, (uint32_t)a.nb);
-                    const uint32_t rr = submod(c, st[j], Z);
-                    const uint32_t m = mul24(t, Z) + rr;
-                    const uint32_t old = atomicXor(&syn[m >> 5], 1u << (m & 31));
-                    const uint32_t nb1 = ((old >> (m & 31)) & 1u) ^ 1u;
-                    // the check's two weights and the position of its minimum
-                    uint32_t w1, w2, pos;
-                    if constexpr (DT == FWBF_I8) {
-                        const uint32_t cw = chk[m];
-                        w1 = cw & 0xFF; w2 = (cw >> 8) & 0xFF; pos = (cw >> 16) & 0xFF;
-                    } else {
-                        const uint32_t cw = chk[m];
-                        w1 = cw & 0xFFFF; w2 = cw >> 16; pos = chkp[m];
-                    }
-                    const uint32_t e1 = mul24(2u * (uint32_t)a.aden, w1) << a.idxb;
-                    const uint32_t e2 = a.imwbf ? mul24(2u * (uint32_t)a.aden, w2) << a.idxb : e1;
-                    const uint32_t d1 = nb1 ? e1 : 0u - e1, d2 = nb1 ? e2 : 0u - e2;
-                    // every member's slot first, then the adds
-                    uint32_t sl[DC];
-#pragma unroll
-                    for (int q = 0; q < DC; q++) sl[q] = slotof[mul24((uint32_t)q, Z) + addmod(rr, st[q], Z)];
-#pragma unroll
-                    for (int q = 0; q < DC; q++) atomicAdd(&keys[sl[q]], pos == (uint32_t)q ? d2 : d1);
-                    return nb1;
-                };
                 if (a.L >= DV) {
                     // every lane of a block holds the block's winner after the
                     // butterfly: lane t < DV of the block takes check t, and
@@ -413,7 +440,7 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                     const uint32_t t = lane & (uint32_t)(a.L - 1);
                     const bool tog = t < (uint32_t)DV && (int)g < a.Geff && (a.single || val > a.zero_val);
                     uint32_t nb1 = 0;
-                    if (tog) nb1 = toggle(n, t);
+                    if (tog) nb1 = toggle_check<DT, DC>(a, n, t, sh, slotof, syn, chk, chkp, keys);
                     sum_ones = __popcll(__ballot(nb1));
                 } else {
                     // fewer lanes than checks per block: the winners are
@@ -432,7 +459,7 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                         if (i < ntog) {
                             const uint32_t u = mul24((uint32_t)i, DVM) >> 16;
                             const uint32_t t = (uint32_t)i - mul24(u, (uint32_t)DV);
-                            nb1 = toggle(flips[u], t);
+                            nb1 = toggle_check<DT, DC>(a, flips[u], t, sh, slotof, syn, chk, chkp, keys);
                         }
                         sum_ones += __popcll(__ballot(nb1));
                     }
@@ -453,6 +480,7 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
         }
     }
 }
+
 
 }  // namespace
 
@@ -533,8 +561,7 @@ int try_fast_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int
     // smallest C with Geff * L <= 64 lanes, L = 2^ceil(log2(ceil(p / C)))
     int C = 0, L = 0;
     for (int cc : {4, 8, 16, 32, 64}) {
-        const int need = (a.p + cc - 1) / cc;
-        const int l = 1 << ilog2c(need);
+        const int l = 1 << ilog2c((a.p + cc - 1) / cc);
         if ((int64_t)a.Geff * l <= 64) { C = cc; L = l; break; }
     }
     if (!C) return 0;
@@ -568,6 +595,10 @@ int try_fast_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int
     a.idxb = ilog2c((uint32_t)a.Lc);
     if (vb + a.idxb > 32) return 0;
     a.idxmask = a.idxb ? (1u << a.idxb) - 1 : 0;
+    if (((int64_t)2 * a.aden << a.idxb) >= (1 << 24) || ((int64_t)a.anum << a.idxb) >= (1 << 23)) return 0;
+    a.kden = (uint32_t)a.aden << a.idxb;
+    a.kden2 = 2u * (uint32_t)a.aden << a.idxb;
+    a.nknum = -(a.anum << a.idxb);
     const int esz = p->dtype == FWBF_I8 ? 1 : 2;
     a.vec_ok = (((uintptr_t)y & 15) == 0) && ((stride * esz) % 16 == 0);
     // LDS layout
