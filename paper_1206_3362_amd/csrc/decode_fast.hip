@@ -267,6 +267,47 @@ __device__ __forceinline__ uint32_t toggle_check(const FastArgs &a, uint32_t nf,
     return nb1;
 }
 
+// The same update split over a pair of lanes (u = 0, 1), each taking half
+// of the check's members (q = u DC/2 .. u DC/2 + DC/2 - 1); the even lane
+// toggles the syndrome bit and its partner takes the new bit from it (DPP
+// within the quad). stq[k] = s_{t,q} for this lane's members and
+// sb = slotof + u (DC/2) Z (fixed per lane). Returns the new bit on the even lane, 0 on the
+// odd one.
+template <int DT, int DC>
+__device__ __forceinline__ uint32_t toggle_half(const FastArgs &a, uint32_t nf, uint32_t t, uint32_t u,
+                                                const uint32_t (&stq)[DC / 2], const uint16_t *sb,
+                                                const uint32_t *sh, uint32_t *syn, const uint32_t *chk,
+                                                const uint8_t *chkp, uint32_t *keys)
+{
+    constexpr int H = DC / 2;
+    const uint32_t Z = a.Z;
+    const uint32_t j = mul24(nf, a.rZ24) >> 20;  // block column: nf / Z
+    const uint32_t c = nf - mul24(j, Z);
+    const uint32_t rr = submod(c, sh[mul24(t, (uint32_t)a.nb) + j], Z);
+    const uint32_t m = mul24(t, Z) + rr;
+    const uint32_t bit = 1u << (m & 31);
+    const uint32_t old = atomicXor(&syn[m >> 5], u == 0 ? bit : 0u);
+    const uint32_t nb1 = dpp<0xA0>((old & bit) ? 0u : 1u);  // quad_perm [0,0,2,2]: the even lane's bit
+    uint32_t w1, w2, pos;
+    if constexpr (DT == FWBF_I8) {
+        const uint32_t cw = chk[m];
+        w1 = cw & 0xFF; w2 = (cw >> 8) & 0xFF; pos = (cw >> 16) & 0xFF;
+    } else {
+        const uint32_t cw = chk[m];
+        w1 = cw & 0xFFFF; w2 = cw >> 16; pos = chkp[m];
+    }
+    const uint32_t e1 = mul24(a.kden2, w1);
+    const uint32_t e2 = a.imwbf ? mul24(a.kden2, w2) : e1;
+    const uint32_t d1 = nb1 ? e1 : 0u - e1, d2 = nb1 ? e2 : 0u - e2;
+    const uint32_t pk = pos - u * (uint32_t)H;  // the minimum's index among this lane's members
+    uint32_t sl[H];
+#pragma unroll
+    for (int k = 0; k < H; k++) sl[k] = (sb + k * Z)[addmod(rr, stq[k], Z)];
+#pragma unroll
+    for (int k = 0; k < H; k++) atomicAdd(&keys[sl[k]], pk == (uint32_t)k ? d2 : d1);
+    return u == 0 ? nb1 : 0u;
+}
+
 template <int DT, int DV, int DC, int C>
 __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu(5))) void fast_kernel(FastArgs a)
 {
@@ -314,6 +355,13 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
         nreal = max(0, min(C, lim - (int)pos0));
     }
     const uint32_t key0 = (a.bias << a.idxb) | (a.idxmask - pos0);
+    // blocks of at least 2 dv lanes: lanes 2t, 2t + 1 (t < dv) of a block
+    // share check t of the block's winner, half of its members each
+    const uint32_t tl = lane & (uint32_t)(a.L - 1), tt = tl >> 1, tu = tl & 1;
+    uint32_t stq[DC / 2];
+    const uint16_t *sb = slotof + tu * (DC / 2) * Z;
+#pragma unroll
+    for (int k = 0; k < DC / 2; k++) stq[k] = tt < (uint32_t)DV ? sh[tt * a.nb + tu * (DC / 2) + k] : 0u;
 
     const FrameRange fr = xcd_frames_waves(a.F, FAST_WAVES, (int)wv);
     for (int64_t f = fr.first; f < fr.end; f += fr.step) {
@@ -432,7 +480,13 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                 int sum_ones = 0;  // toggles that leave their check unsatisfied
                 // (winner, check) lane: toggle check t of the winner, then add
                 // +-2 a_den w to the check's members
-                if (a.L >= DV) {
+                if (a.L >= 2 * DV) {
+                    if (flip) atomicXor(&zw[n >> 5], 1u << (n & 31));
+                    const bool tog = tt < (uint32_t)DV && (int)g < a.Geff && (a.single || val > a.zero_val);
+                    uint32_t nb1 = 0;
+                    if (tog) nb1 = toggle_half<DT, DC>(a, n, tt, tu, stq, sb, sh, syn, chk, chkp, keys);
+                    sum_ones = __popcll(__ballot(nb1));
+                } else if (a.L >= DV) {
                     // every lane of a block holds the block's winner after the
                     // butterfly: lane t < DV of the block takes check t, and
                     // the lead lane flips the bit
