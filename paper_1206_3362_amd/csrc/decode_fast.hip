@@ -68,6 +68,16 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t mag, uint32_t mask
     return __umulhi(n, mag) + (n & mask);
 }
 
+// A uniform value the compiler must take as defined here: tests of kernel
+// arguments made inside a loop from such a copy stay scalar compares at
+// their use, instead of being hoisted out of the loop as 64-bit lane masks
+// that stay live (and, with enough of them, spill) for the whole loop.
+__device__ __forceinline__ int fresh(int v)
+{
+    asm volatile("" : "+s"(v));
+    return v;
+}
+
 // (a + b) mod Z for a, b in [0, Z)
 __device__ __forceinline__ uint32_t addmod(uint32_t a, uint32_t b, uint32_t Z)
 {
@@ -140,7 +150,7 @@ __device__ __forceinline__ void wave_sync()
 // its members (the first block row also adds -a_num |y_n|, once per bit);
 // returns the check's syndrome bit.
 template <int DT, int DC>
-__device__ __forceinline__ uint32_t check_init(const FastArgs &a, int i, uint32_t r, const uint32_t (&js)[DC],
+__device__ __forceinline__ uint32_t check_init(const FastArgs &a, int i, int imwbf, uint32_t r, const uint32_t (&js)[DC],
                                                const typename FT<DT>::Y *yv, const uint16_t *slotof,
                                                uint32_t *keys, uint32_t *chk, uint8_t *chkp)
 {
@@ -218,7 +228,7 @@ __device__ __forceinline__ uint32_t check_init(const FastArgs &a, int i, uint32_
     // two signed values (a_den w << idxb) are formed once
     // (minima are at most 32768: 16 bits)
     const uint32_t e1 = mul24(a.kden, m1 & 0xFFFFu);
-    const uint32_t e2 = a.imwbf ? mul24(a.kden, m2 & 0xFFFFu) : e1;
+    const uint32_t e2 = imwbf ? mul24(a.kden, m2 & 0xFFFFu) : e1;
     const uint32_t d1 = par ? e1 : 0u - e1, d2 = par ? e2 : 0u - e2;
 #pragma unroll
     for (int q = 0; q < DC; q++) {
@@ -234,7 +244,7 @@ __device__ __forceinline__ uint32_t check_init(const FastArgs &a, int i, uint32_
 // the metrics of its members, the sign given by the new bit; returns the new
 // bit (1: the check is now unsatisfied).
 template <int DT, int DC>
-__device__ __forceinline__ uint32_t toggle_check(const FastArgs &a, uint32_t nf, uint32_t t, const uint32_t *sh,
+__device__ __forceinline__ uint32_t toggle_check(const FastArgs &a, int imwbf, uint32_t nf, uint32_t t, const uint32_t *sh,
                                                  const uint16_t *slotof, uint32_t *syn, const uint32_t *chk,
                                                  const uint8_t *chkp, uint32_t *keys)
 {
@@ -256,7 +266,7 @@ __device__ __forceinline__ uint32_t toggle_check(const FastArgs &a, uint32_t nf,
         w1 = cw & 0xFFFF; w2 = cw >> 16; pos = chkp[m];
     }
     const uint32_t e1 = mul24(a.kden2, w1);
-    const uint32_t e2 = a.imwbf ? mul24(a.kden2, w2) : e1;
+    const uint32_t e2 = imwbf ? mul24(a.kden2, w2) : e1;
     const uint32_t d1 = nb1 ? e1 : 0u - e1, d2 = nb1 ? e2 : 0u - e2;
     // every member's slot first, then the adds
     uint32_t sl[DC];
@@ -274,7 +284,7 @@ __device__ __forceinline__ uint32_t toggle_check(const FastArgs &a, uint32_t nf,
 // sb = slotof + u (DC/2) Z (fixed per lane). Returns the new bit on the even lane, 0 on the
 // odd one.
 template <int DT, int DC>
-__device__ __forceinline__ uint32_t toggle_half(const FastArgs &a, uint32_t nf, uint32_t t, uint32_t u,
+__device__ __forceinline__ uint32_t toggle_half(const FastArgs &a, int imwbf, uint32_t nf, uint32_t t, uint32_t u,
                                                 const uint32_t (&stq)[DC / 2], const uint16_t *sb,
                                                 const uint32_t *sh, uint32_t *syn, const uint32_t *chk,
                                                 const uint8_t *chkp, uint32_t *keys)
@@ -297,7 +307,7 @@ __device__ __forceinline__ uint32_t toggle_half(const FastArgs &a, uint32_t nf, 
         w1 = cw & 0xFFFF; w2 = cw >> 16; pos = chkp[m];
     }
     const uint32_t e1 = mul24(a.kden2, w1);
-    const uint32_t e2 = a.imwbf ? mul24(a.kden2, w2) : e1;
+    const uint32_t e2 = imwbf ? mul24(a.kden2, w2) : e1;
     const uint32_t d1 = nb1 ? e1 : 0u - e1, d2 = nb1 ? e2 : 0u - e2;
     const uint32_t pk = pos - u * (uint32_t)H;  // the minimum's index among this lane's members
     uint32_t sl[H];
@@ -343,8 +353,6 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
     const bool lead = ((lane & (a.L - 1)) == 0) && (int)g < a.Geff;
     const uint32_t pos0 = (lane & (a.L - 1)) * C;
     const uint32_t gp = g * a.p;
-    // bit at position pos of this lane's block
-    auto bit_at = [&](uint32_t pos) { return a.strided ? mul24(pos, (uint32_t)a.Geff) + g : gp + pos; };
     const int NW = (N + 31) >> 5;
     // this lane's slots that hold a bit are its first nreal (positions pos0,
     // pos0 + 1, ...), and the initial key of position pos0 + j is key0 - j:
@@ -365,14 +373,16 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
 
     const FrameRange fr = xcd_frames_waves(a.F, FAST_WAVES, (int)wv);
     for (int64_t f = fr.first; f < fr.end; f += fr.step) {
-        if (a.skip && a.skip[f]) continue;  // uniform across the wave
+        const uint8_t *skip = a.skip;
+        asm volatile("" : "+s"(skip));
+        if (skip && skip[f]) continue;  // uniform across the wave
         const Y *yrow = (const Y *)a.y + f * a.stride;
         wave_sync();
         for (int w = lane; w < ((M + 63) >> 6) * 2; w += 64) syn[w] = 0;
         for (int w = lane; w < ((N + 63) >> 6) * 2; w += 64) zw[w] = 0;
         // ---- received values -> LDS ---------------------------------------
         constexpr int E = 16 / (int)sizeof(Y);  // values per 16-byte chunk
-        const int nchunk = a.vec_ok ? min(N / E, 128) : 0;
+        const int nchunk = fresh(a.vec_ok) ? min(N / E, 128) : 0;
         uint32_t zmask[2] = {0, 0};
         for (int it = 0; it < 2; it++) {
             const int cidx = lane + 64 * it;
@@ -424,9 +434,10 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
 #pragma unroll
             for (int q = 0; q < DC; q++) js[q] = sh[i * a.nb + q];
             for (uint32_t r0 = 0; r0 < Z; r0 += 64) {
+                const int imwbf = fresh(a.imwbf);
                 const uint32_t r = r0 + lane;
                 const bool valid = r < Z;
-                const uint32_t par = valid ? check_init<DT, DC>(a, i, r, js, yv, slotof, keys, chk, chkp) : 0u;
+                const uint32_t par = valid ? check_init<DT, DC>(a, i, imwbf, r, js, yv, slotof, keys, chk, chkp) : 0u;
                 const unsigned long long b = __ballot(valid && par);
                 weight += __popcll(b);
                 // syndrome words: checks i*Z + r0 .. +63 (not word aligned in general)
@@ -441,6 +452,9 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
             okf = weight == 0;
         } else {
             for (;;) {
+                // this round's copies of the launch's switches
+                const int Lr = fresh(a.L), single = fresh(a.single), strided = fresh(a.strided);
+                const int imwbf = fresh(a.imwbf), cycle_exit = fresh(a.cycle_exit), exec_rounds = fresh(a.exec_rounds);
                 // ---- Step 2: block maxima ----------------------------------
                 // every chunk read is issued before any is compared
                 uint4 kv[C / 4];
@@ -449,24 +463,25 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                 uint32_t best = 0;
 #pragma unroll
                 for (int kk = 0; kk < C / 4; kk++) best = max(best, max(max(kv[kk].x, kv[kk].y), max(kv[kk].z, kv[kk].w)));
-                best = group_max(best, a.L);
+                best = group_max(best, Lr);
                 const uint32_t val = best >> a.idxb;
-                const uint32_t n = bit_at(a.idxmask - (best & a.idxmask));
-                const bool flip = lead && (a.single || val > a.zero_val);
+                const uint32_t bp = a.idxmask - (best & a.idxmask);
+                const uint32_t n = strided ? mul24(bp, (uint32_t)a.Geff) + g : gp + bp;
+                const bool flip = lead && (single || val > a.zero_val);
                 const uint32_t cur = flip ? n : NONE;
                 const unsigned long long fmask = __ballot(flip);
                 const unsigned long long dmask = __ballot(lead && cur != prv);
                 prv = lead ? cur : prv;
-                if (a.cycle_exit) {
+                if (cycle_exit) {
                     if (fmask == 0) {  // no flip: fixed point until K_max
-                        k = a.exec_rounds ? k : a.max_iter;
+                        k = exec_rounds ? k : a.max_iter;
                         break;
                     }
                     if (dmask == 0) {
                         // same flips as the round before: states alternate,
                         // z_{K_max} = z_k if K_max - k is even, else z_k ^ flips
                         if (((a.max_iter - k) & 1) && flip) atomicXor(&zw[n >> 5], 1u << (n & 31));
-                        k = a.exec_rounds ? k : a.max_iter;
+                        k = exec_rounds ? k : a.max_iter;
                         break;
                     }
                 }
@@ -480,21 +495,21 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                 int sum_ones = 0;  // toggles that leave their check unsatisfied
                 // (winner, check) lane: toggle check t of the winner, then add
                 // +-2 a_den w to the check's members
-                if (a.L >= 2 * DV) {
+                if (Lr >= 2 * DV) {
                     if (flip) atomicXor(&zw[n >> 5], 1u << (n & 31));
-                    const bool tog = tt < (uint32_t)DV && (int)g < a.Geff && (a.single || val > a.zero_val);
+                    const bool tog = tt < (uint32_t)DV && (int)g < a.Geff && (single || val > a.zero_val);
                     uint32_t nb1 = 0;
-                    if (tog) nb1 = toggle_half<DT, DC>(a, n, tt, tu, stq, sb, sh, syn, chk, chkp, keys);
+                    if (tog) nb1 = toggle_half<DT, DC>(a, imwbf, n, tt, tu, stq, sb, sh, syn, chk, chkp, keys);
                     sum_ones = __popcll(__ballot(nb1));
-                } else if (a.L >= DV) {
+                } else if (Lr >= DV) {
                     // every lane of a block holds the block's winner after the
                     // butterfly: lane t < DV of the block takes check t, and
                     // the lead lane flips the bit
                     if (flip) atomicXor(&zw[n >> 5], 1u << (n & 31));
-                    const uint32_t t = lane & (uint32_t)(a.L - 1);
-                    const bool tog = t < (uint32_t)DV && (int)g < a.Geff && (a.single || val > a.zero_val);
+                    const uint32_t t = lane & (uint32_t)(Lr - 1);
+                    const bool tog = t < (uint32_t)DV && (int)g < a.Geff && (single || val > a.zero_val);
                     uint32_t nb1 = 0;
-                    if (tog) nb1 = toggle_check<DT, DC>(a, n, t, sh, slotof, syn, chk, chkp, keys);
+                    if (tog) nb1 = toggle_check<DT, DC>(a, imwbf, n, t, sh, slotof, syn, chk, chkp, keys);
                     sum_ones = __popcll(__ballot(nb1));
                 } else {
                     // fewer lanes than checks per block: the winners are
@@ -513,7 +528,7 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                         if (i < ntog) {
                             const uint32_t u = mul24((uint32_t)i, DVM) >> 16;
                             const uint32_t t = (uint32_t)i - mul24(u, (uint32_t)DV);
-                            nb1 = toggle_check<DT, DC>(a, flips[u], t, sh, slotof, syn, chk, chkp, keys);
+                            nb1 = toggle_check<DT, DC>(a, imwbf, flips[u], t, sh, slotof, syn, chk, chkp, keys);
                         }
                         sum_ones += __popcll(__ballot(nb1));
                     }
@@ -529,7 +544,7 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
         uint32_t *zo = a.z + f * NW;
         for (int w = lane; w < NW; w += 64) zo[w] = zw[w];
         if (lane == 0) {
-            a.iters[f] = a.iters_add ? a.iters[f] + k : k;
+            a.iters[f] = fresh(a.iters_add) ? a.iters[f] + k : k;
             a.ok[f] = (uint8_t)okf;
         }
     }
