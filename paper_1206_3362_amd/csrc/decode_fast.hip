@@ -68,16 +68,6 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t mag, uint32_t mask
     return __umulhi(n, mag) + (n & mask);
 }
 
-// A uniform value the compiler must take as defined here: tests of kernel
-// arguments made inside a loop from such a copy stay scalar compares at
-// their use, instead of being hoisted out of the loop as 64-bit lane masks
-// that stay live (and, with enough of them, spill) for the whole loop.
-__device__ __forceinline__ int fresh(int v)
-{
-    asm volatile("" : "+s"(v));
-    return v;
-}
-
 // (a + b) mod Z for a, b in [0, Z)
 __device__ __forceinline__ uint32_t addmod(uint32_t a, uint32_t b, uint32_t Z)
 {

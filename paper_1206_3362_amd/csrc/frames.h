@@ -50,6 +50,27 @@ __device__ __forceinline__ FrameRange xcd_frames_waves(int64_t F, int W, int w)
 
 namespace fwbf {
 
+// A uniform value the compiler must take as defined here: tests of kernel
+// arguments made inside a loop from such a copy stay scalar compares at
+// their use, instead of being hoisted out of the loop as 64-bit lane masks
+// that stay live (and, with enough of them, spill) for the whole loop.
+__device__ __forceinline__ int fresh(int v)
+{
+    asm volatile("" : "+s"(v));
+    return v;
+}
+__device__ __forceinline__ float fresh(float v)
+{
+    asm volatile("" : "+s"(v));
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ T *fresh(T *v)
+{
+    asm volatile("" : "+s"(v));
+    return v;
+}
+
 // Product of the low 24 bits of a and b (v_mul_u32_u24, full rate), as an
 // unsigned 32-bit value: HIP's __umul24 returns int, which would turn a
 // product at or above 2^31 negative under shifts and comparisons.

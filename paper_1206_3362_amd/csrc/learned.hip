@@ -306,10 +306,10 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
     const int NC = a.Geff * a.k;  // proposals per round (<= 32)
 
     const FrameRange fr = xcd_frames_waves(a.F, LEARN_WAVES, (int)wv);
-    const int nchunk = a.vec_ok ? min(N >> 4, 128) : 0;
     // the 16-byte pieces of a frame (up to two per lane; every lane loads,
     // idle lanes a copy of the last piece, so the loads need no lane mask)
     auto fetch = [&](int64_t ff, uint4 *x) {
+        const int nchunk = fresh(a.vec_ok) ? min(N >> 4, 128) : 0;
         if (nchunk == 0) return;
         const uint4 *src = (const uint4 *)(a.y + ff * a.stride);
         x[0] = src[min((int)lane, nchunk - 1)];
@@ -319,6 +319,7 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
     uint4 nxt[2] = {make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0)};
     if (fr.first < fr.end) fetch(fr.first, nxt);
     for (int64_t f = fr.first; f < fr.end; f += fr.step) {
+        const int nchunk = fresh(a.vec_ok) ? min(N >> 4, 128) : 0;
         const int8_t *yrow = a.y + f * a.stride;
         const uint4 vc[2] = {nxt[0], nxt[1]};
         if (f + fr.step < fr.end) fetch(f + fr.step, nxt);
@@ -429,13 +430,18 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
         uint32_t prv = NONE;
         const uint32_t *cw = a.pool ? a.pool + (size_t)((a.f0 + f) % a.pool_n) * NW : nullptr;
         for (;;) {
+            // this round's copies of the launch's switches
+            const int Lr = fresh(a.L), kr = fresh(a.k);
+            fwbf_record *const rec = fresh(a.rec);
+            const bool pool = fresh(a.pool) != nullptr;
+            const float invA = fresh(a.invA);
             if (weight == 0) { okf = 1; break; }
             if (t == a.T) break;
             const float al = a.params[O_AL + t], be = a.params[O_AL + a.T + t];
             // k best per block by E_t (ties: lower index); each chosen slot is
             // excluded before the next pass
             uint64_t excl = 0;
-            for (int rk = 0; rk < a.k; rk++) {
+            for (int rk = 0; rk < kr; rk++) {
                 // the lane's best live slot, scanned in ascending position with
                 // a strict comparison (ties keep the lower position; -0 == +0)
                 const uint64_t livem = realm & ~excl;
@@ -459,7 +465,7 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
                 unsigned long long best = bi == NONE ? 0ull
                                                      : (((unsigned long long)orderable(bE) << 32) |
                                                         (0xFFFFFFFFu - (pos0 + bi)));
-                best = group_max64(best, a.L);
+                best = group_max64(best, Lr);
                 const uint32_t bpos = 0xFFFFFFFFu - (uint32_t)best;
                 const bool real = (best >> 32) != 0;
                 if (real && (int)g < a.Geff && bpos / C == (lane & (a.L - 1))) excl |= 1ull << (bpos & (C - 1));
@@ -481,7 +487,7 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
                 // the same quotients as dividing: a power-of-two scale is a
                 // multiply by its reciprocal, u / dv takes one of dv + 1 values
                 float fa, fe;
-                if (a.invA != 0.0f) { fa = (float)ca * a.invA; fe = E * a.invA; }
+                if (invA != 0.0f) { fa = (float)ca * invA; fe = E * invA; }
                 else { fa = (float)ca / a.A; fe = E / a.A; }
                 const float fu = cu == 0 ? 0.0f : cu == 1 ? qu1 : cu == 2 ? qu2 : cu == 3 ? qu3 : (float)cu / a.dv;
                 x = pack4(fa, fe, fu, nbias[96 + t]);
@@ -489,7 +495,7 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
             const float score = net_score(net, x);
             // every one of the 32 slots is written in each round run; slots
             // j >= NC (no proposal) get valid = 0
-            if (a.rec && lane < 32) {
+            if (rec && lane < 32) {
                 fwbf_record r;
                 r.S = cS;
                 r.a = (uint16_t)ca;
@@ -498,19 +504,19 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
                 uint32_t lab = 0;
                 if (realc) {
                     const uint32_t zb = (zw[cj.x >> 5] >> (cj.x & 31)) & 1u;
-                    const uint32_t cb = cw ? (cw[cj.x >> 5] >> (cj.x & 31)) & 1u : 0u;
+                    const uint32_t cb = pool ? (cw[cj.x >> 5] >> (cj.x & 31)) & 1u : 0u;
                     lab = zb ^ cb;
                 }
                 r.label = (uint8_t)lab;
                 r.valid = realc ? 1 : 0;
                 r.n = (uint16_t)(realc ? cj.x : 0xFFFF);
-                a.rec[((size_t)f * a.T + t) * 32 + j] = r;
+                rec[((size_t)f * a.T + t) * 32 + j] = r;
             }
             rec_end = t + 1;
             // best score among the k proposals of each block (ties: lower index)
             unsigned long long sk = realc ? (((unsigned long long)orderable(score) << 32) | (0xFFFFFFFFu - cj.x)) : 0ull;
-            if (a.k > 1) sk = group_max64(sk, a.k);
-            const bool blead = lane < 32 && (j % a.k) == 0 && j < (uint32_t)NC;
+            if (kr > 1) sk = group_max64(sk, kr);
+            const bool blead = lane < 32 && (j % kr) == 0 && j < (uint32_t)NC;
             const uint32_t nsel = 0xFFFFFFFFu - (uint32_t)sk;
             const bool flip = blead && (sk >> 32) > orderable(0.0f) && sk != 0;
             const uint32_t cur = flip ? nsel : NONE;
@@ -564,7 +570,7 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
         }
         lwave_sync();
         // records of the rounds not run are marked invalid
-        if (a.rec)
+        if (fresh(a.rec))
             for (int s = rec_end; s < a.T; s++)
                 if (lane < 32) a.rec[((size_t)f * a.T + s) * 32 + lane].valid = 0;
         uint32_t *zo = a.z + f * NW;
@@ -572,7 +578,7 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
         if (lane == 0) {
             a.iters[f] = t;
             a.ok[f] = (uint8_t)okf;
-            if (a.learned_ok) a.learned_ok[f] = (uint8_t)okf;
+            if (fresh(a.learned_ok)) a.learned_ok[f] = (uint8_t)okf;
         }
     }
 }
