@@ -932,12 +932,17 @@ __global__ __launch_bounds__(WIDE_T) void learned_wide_kernel(WideArgs a)
         const uint32_t *cw = a.pool ? a.pool + (size_t)((a.f0 + f) % a.pool_n) * NW : nullptr;
         const bool anysat = DT == FWBF_I16 && ctl[CW_SAT] != 0;  // uniform
         for (;;) {
+            // this round's copies of the launch's switches
+            const int kr = fresh(a.k), Lr = fresh(a.L), logLr = fresh(a.logL);
+            fwbf_record *const rec = fresh(a.rec);
+            const bool pool = fresh(a.pool) != nullptr;
+            const float invA = fresh(a.invA);
             if (ctl[CW_WEIGHT] == 0) { okf = 1; break; }
             if (t == a.T) break;
             const float al = a.params[O_AL + t], be = a.params[O_AL + a.T + t];
             // ---- the k best live slots of each block by E_t (ties: lower index)
             uint64_t excl = 0;
-            for (int rk = 0; rk < a.k; rk++) {
+            for (int rk = 0; rk < kr; rk++) {
                 const uint64_t livem = realm & ~excl;
                 float bE = -__builtin_huge_valf();
                 uint32_t bi = NONE;
@@ -950,7 +955,7 @@ __global__ __launch_bounds__(WIDE_T) void learned_wide_kernel(WideArgs a)
 #pragma unroll 1
                     for (int kk = 0; kk < C; kk += 4) {
                         uint32_t v[4];
-                        const uint32_t base = sbase + (((uint32_t)kk ^ (swk & ~3u)) << a.logL);
+                        const uint32_t base = sbase + (((uint32_t)kk ^ (swk & ~3u)) << logLr);
 #pragma unroll
                         for (int u = 0; u < 4; u++) v[u] = slots[base + offu[u]];
 #pragma unroll
@@ -958,7 +963,7 @@ __global__ __launch_bounds__(WIDE_T) void learned_wide_kernel(WideArgs a)
                             const bool live = K1 ? kk + u < nreal : ((livem >> (kk + u)) & 1) != 0;
                             uint32_t av = (v[u] >> 2) & WSAT;
                             if constexpr (DT == FWBF_I16 && !K1)
-                                if (live && av == WSAT) av = wide_mag<DT>(yrow, gp + l + ((uint32_t)(kk + u) << a.logL));
+                                if (live && av == WSAT) av = wide_mag<DT>(yrow, gp + l + ((uint32_t)(kk + u) << logLr));
                             const float E = __builtin_fmaf(-al, (float)av, be * (float)((int32_t)v[u] >> 14));
                             const bool take = live && E > bE;
                             bE = take ? E : bE;
@@ -966,15 +971,15 @@ __global__ __launch_bounds__(WIDE_T) void learned_wide_kernel(WideArgs a)
                         }
                     }
                 };
-                if (a.k == 1 && !anysat) scan(std::true_type{});
+                if (kr == 1 && !anysat) scan(std::true_type{});
                 else scan(std::false_type{});
-                const uint32_t nme = gp + l + (bi << a.logL);
+                const uint32_t nme = gp + l + (bi << logLr);
                 unsigned long long best = bi == NONE ? 0ull : (((unsigned long long)orderable(bE) << 32) | (0xFFFFFFFFu - nme));
-                best = group_max64(best, a.L);
+                best = group_max64(best, Lr);
                 const bool real = (best >> 32) != 0;
                 const uint32_t bn = 0xFFFFFFFFu - (uint32_t)best;
                 if (real && bi != NONE && bn == nme) excl |= 1ull << bi;
-                if (gact && l == 0) cand[g * a.k + rk] = real ? bn : NONE;
+                if (gact && l == 0) cand[g * kr + rk] = real ? bn : NONE;
             }
             if (tid == 0) { ctl[CW_FLAGS] = 0; ctl[CW_NTOG] = 0; }
             __syncthreads();
@@ -996,13 +1001,13 @@ __global__ __launch_bounds__(WIDE_T) void learned_wide_kernel(WideArgs a)
                 if (realc) {
                     const float E = __builtin_fmaf(-al, (float)ca, be * (float)cS);
                     float fa, fe;
-                    if (a.invA != 0.0f) { fa = (float)ca * a.invA; fe = E * a.invA; }
+                    if (invA != 0.0f) { fa = (float)ca * invA; fe = E * invA; }
                     else { fa = (float)ca / a.A; fe = E / a.A; }
                     const float fu = cu == 0 ? 0.0f : cu == 1 ? qu1 : cu == 2 ? qu2 : qu3;
                     x = pack4(fa, fe, fu, nbias[96 + t]);
                 }
                 const float score = net_score(net, x);
-                if (a.rec && lane < 32) {
+                if (rec && lane < 32) {
                     fwbf_record r;
                     r.S = cS;
                     r.a = (uint16_t)ca;
@@ -1011,17 +1016,17 @@ __global__ __launch_bounds__(WIDE_T) void learned_wide_kernel(WideArgs a)
                     uint32_t lab = 0;
                     if (realc) {
                         const uint32_t zb = (zw[cn >> 5] >> (cn & 31)) & 1u;
-                        const uint32_t cb = cw ? (cw[cn >> 5] >> (cn & 31)) & 1u : 0u;
+                        const uint32_t cb = pool ? (cw[cn >> 5] >> (cn & 31)) & 1u : 0u;
                         lab = zb ^ cb;
                     }
                     r.label = (uint8_t)lab;
                     r.valid = realc ? 1 : 0;
                     r.n = (uint16_t)(realc ? cn : 0xFFFF);
-                    a.rec[(((size_t)f * a.T + t) * a.tpr + wv) * 32 + j] = r;
+                    rec[(((size_t)f * a.T + t) * a.tpr + wv) * 32 + j] = r;
                 }
                 // best score among the k proposals of each block (ties: lower index)
                 unsigned long long sk = realc ? (((unsigned long long)orderable(score) << 32) | (0xFFFFFFFFu - cn)) : 0ull;
-                if (a.k > 1) sk = group_max64(sk, a.k);
+                if (kr > 1) sk = group_max64(sk, kr);
                 nsel = 0xFFFFFFFFu - (uint32_t)sk;
                 flip = blead && sk != 0 && (uint32_t)(sk >> 32) > orderable(0.0f);
                 const uint32_t cur = flip ? nsel : NONE;
