@@ -159,7 +159,7 @@ __device__ __forceinline__ uint32_t check_init(const FastArgs &a, int i, int imw
 #pragma unroll
     for (int q = 0; q < DC; q++) yq[q] = (int)(yv + q * Z)[nn[q]];
 #pragma unroll
-    for (int q = 0; q < DC; q++) sl[q] = (slotof + q * Z)[nn[q]];
+    for (int q = 0; q < DC; q++) sl[q] = (slotof + 2 * q * Z)[nn[q]];
     // the two smallest keys |y| << QB | q: their magnitudes are
     // min1 and min2 (with multiplicity), the first one's q is
     // the lowest position holding min1
@@ -209,7 +209,8 @@ __device__ __forceinline__ uint32_t check_init(const FastArgs &a, int i, int imw
     const uint32_t m2 = DC < 2 ? 0u : (k2 >> QB);
     const uint32_t m = i * Z + r;
     if constexpr (DT == FWBF_I8) {
-        chk[m] = m1 | (m2 << 8) | (pos << 16);
+        ((uint16_t *)chk)[m] = (uint16_t)(m1 | (m2 << 8));
+        chkp[m] = (uint8_t)pos;
     } else {
         chk[m] = m1 | (m2 << 16);
         chkp[m] = (uint8_t)pos;
@@ -249,8 +250,8 @@ __device__ __forceinline__ uint32_t toggle_check(const FastArgs &a, int imwbf, u
     // the check's two weights and the position of its minimum
     uint32_t w1, w2, pos;
     if constexpr (DT == FWBF_I8) {
-        const uint32_t cw = chk[m];
-        w1 = cw & 0xFF; w2 = (cw >> 8) & 0xFF; pos = (cw >> 16) & 0xFF;
+        const uint32_t cw = ((const uint16_t *)chk)[m];
+        w1 = cw & 0xFF; w2 = cw >> 8; pos = chkp[m];
     } else {
         const uint32_t cw = chk[m];
         w1 = cw & 0xFFFF; w2 = cw >> 16; pos = chkp[m];
@@ -261,7 +262,7 @@ __device__ __forceinline__ uint32_t toggle_check(const FastArgs &a, int imwbf, u
     // every member's slot first, then the adds
     uint32_t sl[DC];
 #pragma unroll
-    for (int q = 0; q < DC; q++) sl[q] = slotof[mul24((uint32_t)q, Z) + addmod(rr, st[q], Z)];
+    for (int q = 0; q < DC; q++) sl[q] = slotof[mul24((uint32_t)q, 2 * Z) + rr + st[q]];
 #pragma unroll
     for (int q = 0; q < DC; q++) atomicAdd(&keys[sl[q]], pos == (uint32_t)q ? d2 : d1);
     return nb1;
@@ -270,12 +271,13 @@ __device__ __forceinline__ uint32_t toggle_check(const FastArgs &a, int imwbf, u
 // The same update split over a pair of lanes (u = 0, 1), each taking half
 // of the check's members (q = u DC/2 .. u DC/2 + DC/2 - 1); the even lane
 // toggles the syndrome bit and its partner takes the new bit from it (DPP
-// within the quad). stq[k] = s_{t,q} for this lane's members and
-// sb = slotof + u (DC/2) Z (fixed per lane). Returns the new bit on the even lane, 0 on the
+// within the quad). sbq[k] = slotof + 2 q Z + s_{t,q} for this lane's
+// members q = u DC/2 + k (fixed per lane): the slot of member q of check
+// t Z + rr is sbq[k][rr] in the doubled slot table (below). Returns the new bit on the even lane, 0 on the
 // odd one.
 template <int DT, int DC>
 __device__ __forceinline__ uint32_t toggle_half(const FastArgs &a, int imwbf, uint32_t nf, uint32_t t, uint32_t u,
-                                                const uint32_t (&stq)[DC / 2], const uint16_t *sb,
+                                                const uint16_t *const (&sbq)[DC / 2],
                                                 const uint32_t *sh, uint32_t *syn, const uint32_t *chk,
                                                 const uint8_t *chkp, uint32_t *keys)
 {
@@ -290,8 +292,8 @@ __device__ __forceinline__ uint32_t toggle_half(const FastArgs &a, int imwbf, ui
     const uint32_t nb1 = dpp<0xA0>((old & bit) ? 0u : 1u);  // quad_perm [0,0,2,2]: the even lane's bit
     uint32_t w1, w2, pos;
     if constexpr (DT == FWBF_I8) {
-        const uint32_t cw = chk[m];
-        w1 = cw & 0xFF; w2 = (cw >> 8) & 0xFF; pos = (cw >> 16) & 0xFF;
+        const uint32_t cw = ((const uint16_t *)chk)[m];
+        w1 = cw & 0xFF; w2 = cw >> 8; pos = chkp[m];
     } else {
         const uint32_t cw = chk[m];
         w1 = cw & 0xFFFF; w2 = cw >> 16; pos = chkp[m];
@@ -302,7 +304,7 @@ __device__ __forceinline__ uint32_t toggle_half(const FastArgs &a, int imwbf, ui
     const uint32_t pk = pos - u * (uint32_t)H;  // the minimum's index among this lane's members
     uint32_t sl[H];
 #pragma unroll
-    for (int k = 0; k < H; k++) sl[k] = (sb + k * Z)[addmod(rr, stq[k], Z)];
+    for (int k = 0; k < H; k++) sl[k] = sbq[k][rr];
 #pragma unroll
     for (int k = 0; k < H; k++) atomicAdd(&keys[sl[k]], pk == (uint32_t)k ? d2 : d1);
     return u == 0 ? nb1 : 0u;
@@ -325,16 +327,22 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
     uint32_t *syn = (uint32_t *)(wbase + a.o_syn);
     uint32_t *flips = (uint32_t *)(wbase + a.o_y);  // the rounds' winners (over the received values)
     uint32_t *sh = (uint32_t *)(smem + a.o_sh);
-    uint16_t *slotof = (uint16_t *)(smem + a.o_slot);  // slot word of every bit (frame-independent)
+    uint16_t *slotof = (uint16_t *)(smem + a.o_slot);  // slot word of every bit, doubled (frame-independent)
 
     const uint32_t Z = a.Z;
     const int N = a.N, M = a.M;
     for (int t = threadIdx.x; t < DV * a.nb; t += 64 * FAST_WAVES) sh[t] = a.shift[t];
-    for (int n = threadIdx.x; n < a.N; n += 64 * FAST_WAVES) {
+    // the slot of every bit, each block column stored twice in a row
+    // (entry q 2Z + x holds bit q Z + (x mod Z)), so that the member of a
+    // check at rotation r + s (r, s < Z) needs no reduction mod Z
+    for (int e = threadIdx.x; e < 2 * a.N; e += 64 * FAST_WAVES) {
+        const uint32_t q = (uint32_t)e / (2 * Z);  // once per workgroup: a plain division
+        const uint32_t x = (uint32_t)e - 2 * q * Z;
+        const uint32_t n = q * Z + (x < Z ? x : x - Z);
         uint32_t gg, pp;
         if (a.strided) { pp = fdiv(n, a.magG, a.maskG); gg = n - pp * a.Geff; }
         else { gg = fdiv(n, a.magP, a.maskP); pp = n - gg * a.p; }
-        slotof[n] = (uint16_t)slot_addr(gg * a.L + pp / C, pp & (C - 1));
+        slotof[e] = (uint16_t)slot_addr(gg * a.L + pp / C, pp & (C - 1));
     }
     __syncthreads();  // the only workgroup barrier: the wavefronts run independently from here
 
@@ -356,10 +364,12 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
     // blocks of at least 2 dv lanes: lanes 2t, 2t + 1 (t < dv) of a block
     // share check t of the block's winner, half of its members each
     const uint32_t tl = lane & (uint32_t)(a.L - 1), tt = tl >> 1, tu = tl & 1;
-    uint32_t stq[DC / 2];
-    const uint16_t *sb = slotof + tu * (DC / 2) * Z;
+    const uint16_t *sbq[DC / 2];
 #pragma unroll
-    for (int k = 0; k < DC / 2; k++) stq[k] = tt < (uint32_t)DV ? sh[tt * a.nb + tu * (DC / 2) + k] : 0u;
+    for (int k = 0; k < DC / 2; k++) {
+        const uint32_t q = tu * (DC / 2) + k;
+        sbq[k] = slotof + 2 * q * Z + (tt < (uint32_t)DV ? sh[tt * a.nb + q] : 0u);
+    }
 
     const FrameRange fr = xcd_frames_waves(a.F, FAST_WAVES, (int)wv);
     for (int64_t f = fr.first; f < fr.end; f += fr.step) {
@@ -489,7 +499,7 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                     if (flip) atomicXor(&zw[n >> 5], 1u << (n & 31));
                     const bool tog = tt < (uint32_t)DV && (int)g < a.Geff && (single || val > a.zero_val);
                     uint32_t nb1 = 0;
-                    if (tog) nb1 = toggle_half<DT, DC>(a, imwbf, n, tt, tu, stq, sb, sh, syn, chk, chkp, keys);
+                    if (tog) nb1 = toggle_half<DT, DC>(a, imwbf, n, tt, tu, sbq, sh, syn, chk, chkp, keys);
                     sum_ones = __popcll(__ballot(nb1));
                 } else if (Lr >= DV) {
                     // every lane of a block holds the block's winner after the
@@ -664,11 +674,11 @@ int try_fast_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int
     int off = 0;
     auto take = [&](int bytes, int align) { off = (off + align - 1) / align * align; int o = off; off += bytes; return o; };
     a.o_sh = take(4 * dv * c->nb, 4);
-    a.o_slot = take(2 * c->N, 4);
+    a.o_slot = take(2 * 2 * c->N, 4);
     a.o_wave0 = (off + 15) / 16 * 16;
     off = 64 * C * 4;  // keys, then the rest of one wavefront's frame state
-    a.o_chk = take(4 * c->M, 4);
-    a.o_chkp = take(p->dtype == FWBF_I16 ? c->M : 0, 4);
+    a.o_chk = take((p->dtype == FWBF_I16 ? 4 : 2) * c->M, 4);  // min1 | min2 << 16 (int16), << 8 (int8)
+    a.o_chkp = take(c->M, 4);                                    // position of min1
     // the received values, needed only while initialising; in the rounds the
     // same bytes hold the flipped bits (Geff words)
     a.o_y = take(std::max(esz * ((c->N + 15) / 16 * 16), 4 * a.Geff), 16);
