@@ -7,11 +7,14 @@
 //     vectors from an interleaved slot layout (lane-consecutive 16-byte
 //     chunks, no bank conflicts);
 //   - the flip, the syndrome toggle and the metric update are one pass:
-//     each winner toggles its DV checks with an LDS xor that returns the old
-//     word; the new syndrome bit of each toggle fixes the sign of the change
-//     +-2 a_den w of every member metric.  Toggles of one check by two
-//     winners in the same round are serialised by the LDS atomics and their
-//     changes cancel exactly, so no separate parity pass is needed;
+//     every lane of a block holds the block's winner after the butterfly,
+//     and the block's own lanes take its DV checks (a lane pair per check,
+//     three members each, where a block has at least 2 DV lanes), toggling
+//     each with an LDS xor that returns the old word; the new syndrome bit
+//     fixes the sign of the change +-2 a_den w of every member metric.
+//     Toggles of one check by two winners in the same round are serialised
+//     by the LDS atomics and their changes cancel exactly, so no separate
+//     parity pass is needed;
 //   - the initial metrics are pushed from the check side while the check
 //     minima are computed (each check adds its signed reliability to its
 //     members; the first check of a column also adds -a_num |y_n|);
@@ -19,8 +22,12 @@
 //     count) stays in registers and wave ballots;
 //   - a workgroup holds FAST_WAVES independent wavefronts, each decoding its
 //     own frames with wavefront-scope barriers; the frame-independent tables
-//     (shifts, the slot of every bit) are stored once per workgroup, which
-//     with at most 96 VGPRs gives 5 wavefronts per SIMD.
+//     (shifts, the slot of every bit with each block column stored twice)
+//     are stored once per workgroup, which with at most 96 VGPRs gives 5
+//     wavefronts per SIMD;
+//   - tests of kernel arguments inside the loops use copies taken there
+//     (fresh()), so they stay scalar compares rather than loop-long lane
+//     masks that would spill.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -135,8 +142,9 @@ __device__ __forceinline__ void wave_sync()
 }
 
 // Initialisation of check m = i Z + r (block row i; member q is bit
-// q Z + ((r + js[q]) mod Z)): its two smallest |y| and the position of the
-// first into chk (chkp for int16), its term of eq. (1) pushed to the slots of
+// q Z + ((r + js[q]) mod Z)): its two smallest |y| into chk (16-bit
+// min1 | min2 << 8 for int8, 32-bit min1 | min2 << 16 for int16) and the
+// position of the first into chkp, its term of eq. (1) pushed to the slots of
 // its members (the first block row also adds -a_num |y_n|, once per bit);
 // returns the check's syndrome bit.
 template <int DT, int DC>
