@@ -255,17 +255,22 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
     uint32_t *list = (uint32_t *)(wbase + a.o_list);  // the bits flipped in a round
     uint4 *cand = (uint4 *)(wbase + a.o_cand);  // 32 proposals: n, slot word
     uint32_t *sh = (uint32_t *)(smem + a.o_sh);
-    uint16_t *slotof = (uint16_t *)(smem + a.o_slot);  // slot word of every bit
+    uint16_t *slotof = (uint16_t *)(smem + a.o_slot);  // slot word of every bit (each block column twice)
     float *nbias = (float *)(smem + a.o_net);               // b1[32], b2[32], W3[32]
     bf16x4 *nw = (bf16x4 *)(smem + a.o_netw);               // MFMA weight operands, 5 per lane
 
     const uint32_t Z = a.Z;
     const int N = a.N, M = a.M;
     for (int t = threadIdx.x; t < DV * a.nb; t += 64 * LEARN_WAVES) sh[t] = a.shift[t];
-    for (int n = threadIdx.x; n < a.N; n += 64 * LEARN_WAVES) {
+    // entry q 2Z + x holds the slot of bit q Z + (x mod Z): a check member at
+    // rotation r + s (r, s < Z) needs no reduction mod Z
+    for (int e = threadIdx.x; e < 2 * a.N; e += 64 * LEARN_WAVES) {
+        const uint32_t q = (uint32_t)e / (2 * Z);  // once per workgroup: a plain division
+        const uint32_t x = (uint32_t)e - 2 * q * Z;
+        const uint32_t n = q * Z + (x < Z ? x : x - Z);
         const uint32_t gg = fdiv(n, a.magP, a.maskP);
         const uint32_t pp = n - gg * a.p;
-        slotof[n] = (uint16_t)slot_word(gg * a.L + pp / C, pp & (C - 1));
+        slotof[e] = (uint16_t)slot_word(gg * a.L + pp / C, pp & (C - 1));
     }
     for (int t = threadIdx.x; t < 32; t += 64 * LEARN_WAVES) {
         nbias[t] = a.params[O_B1 + t];
@@ -399,7 +404,7 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
 #pragma unroll
                     for (int q = 0; q < DC; q++) yq[q] = (int)yv[nn[q]];
 #pragma unroll
-                    for (int q = 0; q < DC; q++) sl[q] = slotof[nn[q]];
+                    for (int q = 0; q < DC; q++) sl[q] = (slotof + q * Z)[nn[q]];
                     uint32_t k1 = 0xFFFFFFFFu, k2 = 0xFFFFFFFFu, sx = 0;
 #pragma unroll
                     for (int q = 0; q < DC; q++) {
@@ -558,7 +563,7 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
                     const uint32_t pos = (cwd >> 16) & 0xFFu;
                     uint32_t sl[DC];
 #pragma unroll
-                    for (int q = 0; q < DC; q++) sl[q] = slotof[mul24((uint32_t)q, Z) + addmod(rr, st[q], Z)];
+                    for (int q = 0; q < DC; q++) sl[q] = slotof[mul24((uint32_t)q, 2 * Z) + rr + st[q]];
 #pragma unroll
                     for (int q = 0; q < DC; q++) atomicAdd(&slots[sl[q]], pos == (uint32_t)q ? d2 : d1);
                 }
@@ -1539,7 +1544,7 @@ extern "C" int fwbf_decode_learned(const fwbf_code *code, const fwbf_params *pla
     a.o_net = take(4 * (96 + 64), 16);  // b1, b2, W3, then t / T for t < 64 rounds
     a.o_netw = take(64 * 5 * 8, 16);
     a.o_sh = take(4 * 3 * code->nb, 4);
-    a.o_slot = take(2 * code->N, 4);
+    a.o_slot = take(2 * 2 * code->N, 4);
     a.o_wave0 = (off + 15) / 16 * 16;
     off = 64 * C * 4;  // slots, then the rest of one wavefront's frame state
     a.o_chk = take(4 * code->M, 4);
