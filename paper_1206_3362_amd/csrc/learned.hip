@@ -452,9 +452,13 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
                 const uint64_t livem = realm & ~excl;
                 float bE = -__builtin_huge_valf();  // E is finite: a live slot always beats it
                 uint32_t bi = NONE;                  // no live slot yet
+                // every chunk read is issued before any is scanned
+                uint4 cv[C / 4];
+#pragma unroll
+                for (int kk = 0; kk < C; kk += 4) cv[kk >> 2] = ((const uint4 *)slots)[slot_chunk(lane, kk >> 2)];
 #pragma unroll
                 for (int kk = 0; kk < C; kk += 4) {
-                    const uint4 v = ((const uint4 *)slots)[slot_chunk(lane, kk >> 2)];
+                    const uint4 v = cv[kk >> 2];
                     const uint32_t vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
                     for (int u = 0; u < 4; u++) {
