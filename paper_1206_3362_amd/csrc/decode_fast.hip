@@ -501,9 +501,9 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                 // atomics: their changes cancel exactly)
                 const int nflip = __popcll(fmask);
                 int sum_ones = 0;  // toggles that leave their check unsatisfied
-                // (winner, check) lane: toggle check t of the winner, then add
-                // +-2 a_den w to the check's members
                 if (Lr >= 2 * DV) {
+                    // lanes 2t, 2t + 1 of the block share check t of its
+                    // winner (three members each), the lead lane flips the bit
                     if (flip) atomicXor(&zw[n >> 5], 1u << (n & 31));
                     const bool tog = tt < (uint32_t)DV && (int)g < a.Geff && (single || val > a.zero_val);
                     uint32_t nb1 = 0;
