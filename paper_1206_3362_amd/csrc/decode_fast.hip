@@ -75,12 +75,6 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t mag, uint32_t mask
     return __umulhi(n, mag) + (n & mask);
 }
 
-// (a + b) mod Z for a, b in [0, Z)
-__device__ __forceinline__ uint32_t addmod(uint32_t a, uint32_t b, uint32_t Z)
-{
-    const uint32_t s = a + b;
-    return min(s, s - Z);
-}
 // (a - b) mod Z for a, b in [0, Z)
 __device__ __forceinline__ uint32_t submod(uint32_t a, uint32_t b, uint32_t Z)
 {
@@ -149,25 +143,21 @@ __device__ __forceinline__ void wave_sync()
 // returns the check's syndrome bit.
 template <int DT, int DC>
 __device__ __forceinline__ uint32_t check_init(const FastArgs &a, int i, int imwbf, uint32_t r, const uint32_t (&js)[DC],
-                                               const typename FT<DT>::Y *yv, const uint16_t *slotof,
+                                               const typename FT<DT>::Y *ys, const uint16_t *slotof,
                                                uint32_t *keys, uint32_t *chk, uint8_t *chkp)
 {
     constexpr int QB = DC <= 2 ? 1 : DC <= 4 ? 2 : DC <= 8 ? 3 : DC <= 16 ? 4 : DC <= 32 ? 5 : 6;  // bits of q
     const uint32_t Z = a.Z;
-    uint32_t nn[DC], av[DC], sl[DC];
+    uint32_t av[DC], sl[DC];
     int yq[DC];
     uint32_t par = 0;
-    // every LDS read of the check first (its members' values
-    // and slots), so that they are in flight together and
-    // none waits behind the atomic pushes below
-    // member q is bit q Z + ((r + s_q) mod Z): the block
-    // offsets q Z are uniform, only the rotation is per lane
+    // member q is bit q Z + ((r + js[q]) mod Z); its slot comes from the
+    // doubled slot table without the reduction, and its received value from
+    // the slot-ordered copy (every read of the check before its pushes)
 #pragma unroll
-    for (int q = 0; q < DC; q++) nn[q] = addmod(r, js[q], Z);
+    for (int q = 0; q < DC; q++) sl[q] = (slotof + 2 * q * Z)[r + js[q]];
 #pragma unroll
-    for (int q = 0; q < DC; q++) yq[q] = (int)(yv + q * Z)[nn[q]];
-#pragma unroll
-    for (int q = 0; q < DC; q++) sl[q] = (slotof + 2 * q * Z)[nn[q]];
+    for (int q = 0; q < DC; q++) yq[q] = (int)ys[sl[q]];
     // the two smallest keys |y| << QB | q: their magnitudes are
     // min1 and min2 (with multiplicity), the first one's q is
     // the lowest position holding min1
@@ -369,6 +359,10 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
         nreal = max(0, min(C, lim - (int)pos0));
     }
     const uint32_t key0 = (a.bias << a.idxb) | (a.idxmask - pos0);
+    // the bit of this lane's slot j is ybase + j ystep (lanes without a block
+    // read from 0: their slots hold no bit)
+    const uint32_t ystep = a.strided ? (uint32_t)a.Geff : 1u;
+    const uint32_t ybase = (int)g < a.Geff ? (a.strided ? mul24(pos0, (uint32_t)a.Geff) + g : gp + pos0) : 0u;
     // blocks of at least 2 dv lanes: lanes 2t, 2t + 1 (t < dv) of a block
     // share check t of the block's winner, half of its members each
     const uint32_t tl = lane & (uint32_t)(a.L - 1), tt = tl >> 1, tu = tl & 1;
@@ -433,6 +427,35 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
             const int n = n0 + lane;
             const bool neg = n < N && yv[n] < (Y)0;
             if (neg) atomicOr(&zw[n >> 5], 1u << (n & 31));
+        }
+        // the received values in slot order, in place: the check phase reaches
+        // a member through its slot (no reduction mod Z for the value). Every
+        // lane reads the values of its C slots, then (the wavefront's LDS
+        // operations complete in order) writes them at its slots; a padding
+        // slot gets whatever follows its block (never read).
+        {
+            Y vals[C];
+            if (fresh(a.strided)) {
+#pragma unroll
+                for (int j = 0; j < C; j++) vals[j] = yv[ybase + (uint32_t)j * ystep];
+            } else {
+#pragma unroll
+                for (int j = 0; j < C; j++) vals[j] = yv[ybase + j];
+            }
+            wave_sync();
+#pragma unroll
+            for (int kk = 0; kk < C; kk += 4) {
+                if constexpr (sizeof(Y) == 1) {
+                    const uint32_t w = (uint32_t)(uint8_t)vals[kk] | ((uint32_t)(uint8_t)vals[kk + 1] << 8) |
+                                       ((uint32_t)(uint8_t)vals[kk + 2] << 16) | ((uint32_t)(uint8_t)vals[kk + 3] << 24);
+                    ((uint32_t *)yv)[chunk_of(lane, kk >> 2)] = w;
+                } else {
+                    const uint2 w = make_uint2((uint32_t)(uint16_t)vals[kk] | ((uint32_t)(uint16_t)vals[kk + 1] << 16),
+                                               (uint32_t)(uint16_t)vals[kk + 2] | ((uint32_t)(uint16_t)vals[kk + 3] << 16));
+                    ((uint2 *)yv)[chunk_of(lane, kk >> 2)] = w;
+                }
+            }
+            wave_sync();
         }
 
         // ---- check minima, syndrome s_0 and check-side initial metrics ----
@@ -689,7 +712,9 @@ int try_fast_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int
     a.o_chkp = take(c->M, 4);                                    // position of min1
     // the received values, needed only while initialising; in the rounds the
     // same bytes hold the flipped bits (Geff words)
-    a.o_y = take(std::max(esz * ((c->N + 15) / 16 * 16), 4 * a.Geff), 16);
+    // received values: bit order while loading, then slot order (64 C slots;
+    // a lane's reads run up to N + L C in bit order)
+    a.o_y = take(std::max({esz * ((c->N + 15) / 16 * 16), esz * (c->N + a.L * C), esz * 64 * C, 4 * a.Geff}), 16);
     a.o_z = take(((c->N + 63) / 64) * 8, 8);
     a.o_syn = take(((c->M + 63) / 64) * 8, 8);
     a.wave_bytes = (off + 15) / 16 * 16;
