@@ -353,9 +353,11 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
             }
         }
         lwave_sync();
-        // slot words: S = 0, u = 0 and |y| of the slot's bit; when every
-        // lane's slots are 16 aligned consecutive bits, |y| comes from one
-        // 16-byte read per 16 slots
+        // slot words: S = 0, u = 0, |y| of the slot's bit and its sign (bit 7,
+        // above u <= 3: the check phase reads a member's value from its slot
+        // word, whose |y| and sign the pushes of other checks leave alone);
+        // when every lane's slots are 16 aligned consecutive bits, |y| comes
+        // from one 16-byte read per 16 slots
         const bool a16 = (C % 16 == 0) && (a.p % 16 == 0);
         uint64_t realm = 0;
         uint4 y16 = make_uint4(0, 0, 0, 0);
@@ -376,7 +378,7 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
                 const bool real = (int)g < a.Geff && (int)pos < a.p && (int)n < N;
                 int yn = a16 ? (int)(int8_t)(yw >> (8 * u)) : (real ? (int)yv[n] : 0);
                 yn = real ? yn : 0;
-                vp[u] = (uint32_t)(yn < 0 ? -yn : yn) << 8;
+                vp[u] = ((uint32_t)(yn < 0 ? -yn : yn) << 8) | ((uint32_t)(yn < 0) << 7);
                 realm |= (uint64_t)real << (kk + u);
             }
             ((uint4 *)slots)[slot_chunk(lane, kk >> 2)] = v;
@@ -391,31 +393,28 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
             for (uint32_t r0 = 0; r0 < Z; r0 += 64) {
                 const uint32_t r = r0 + lane;
                 const bool valid = r < Z;
-                uint32_t nn[DC];
                 uint32_t par = 0;
                 if (valid) {
                     // the two smallest keys |y| << 3 | q (q < 8): min1, min2 (with
-                    // multiplicity) and the lowest position holding min1
+                    // multiplicity) and the lowest position holding min1.
+                    // Member q's slot comes from the doubled slot table (no
+                    // reduction mod Z) and its |y| and sign from its slot word
                     // (every LDS read of the check is issued before its pushes)
-                    uint32_t sl[DC];
-                    int yq[DC];
+                    uint32_t sl[DC], wq[DC];
 #pragma unroll
-                    for (int q = 0; q < DC; q++) nn[q] = q * Z + addmod(r, js[q], Z);
+                    for (int q = 0; q < DC; q++) sl[q] = (slotof + 2 * q * Z)[r + js[q]];
 #pragma unroll
-                    for (int q = 0; q < DC; q++) yq[q] = (int)yv[nn[q]];
-#pragma unroll
-                    for (int q = 0; q < DC; q++) sl[q] = (slotof + q * Z)[nn[q]];
+                    for (int q = 0; q < DC; q++) wq[q] = slots[sl[q]];
                     uint32_t k1 = 0xFFFFFFFFu, k2 = 0xFFFFFFFFu, sx = 0;
 #pragma unroll
                     for (int q = 0; q < DC; q++) {
-                        const int v = yq[q];
-                        const uint32_t av = (uint32_t)(v < 0 ? -v : v);
-                        sx ^= (uint32_t)v;  // bit 31: parity of the negative members
+                        const uint32_t av = (wq[q] >> 8) & 0xFFu;
+                        sx ^= wq[q];  // bit 7: parity of the negative members
                         const uint32_t key = (av << 3) | (uint32_t)q;
                         k2 = min(k2, max(k1, key));
                         k1 = min(k1, key);
                     }
-                    par = sx >> 31;
+                    par = (sx >> 7) & 1u;
                     const uint32_t m1 = k1 >> 3, m2 = k2 >> 3, pos = k1 & 7u;
                     chk[i * Z + r] = m1 | (m2 << 8) | (pos << 16);
                     // the check's two signed terms, formed once
@@ -489,7 +488,7 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
             const uint4 cj = j < (uint32_t)NC ? cand[j] : make_uint4(NONE, 0, 0, 0);
             const bool realc = cj.x != NONE;
             const int cS = (int32_t)cj.y >> 16;
-            const uint32_t ca = (cj.y >> 8) & 0xFFu, cu = cj.y & 0xFFu;
+            const uint32_t ca = (cj.y >> 8) & 0xFFu, cu = cj.y & 0x7Fu;  // bit 7: the sign of y
             bf16x4 x = pack4(0.f, 0.f, 0.f, 0.f);
             if (lane < 32 && realc) {
                 const float E = __builtin_fmaf(-al, (float)ca, be * (float)cS);
