@@ -9,7 +9,8 @@ before the timed region; a step decodes one resident batch and accumulates
 its error counts.  Value = coded decoded Gb/s = frames * N / time.
 
 Prints one JSON line (rank 0).  Only N=1 is supported: the decoder runs on a
-single GPU (frames are independent; see the design notes for sharding).
+single GPU (frames are independent: several GPUs would each decode their own
+share of the frames and add up the error counters once at the end).
 """
 from __future__ import annotations
 
@@ -81,7 +82,8 @@ def main():
         return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the FWBF decoder has no multi-GPU path "
-              "(frames are independent; see the design notes for how it would shard).",
+              "(frames are independent: several GPUs would each decode their own share "
+              "of the frames and add up the error counters at the end).",
               file=sys.stderr)
         sys.exit(2)
     if a.workload != "n1008_i8":

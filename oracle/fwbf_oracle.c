@@ -18,8 +18,7 @@
  * No incremental update, packed key, stall shortcut or other optimisation of
  * the GPU path appears here.
  *
- * Readings adopted where the paper is silent (each also listed in the
- * design notes of the repository):
+ * Readings adopted where the paper is silent:
  *   - rounds: at most K_max flip rounds; stop as soon as the syndrome is zero
  *     (Section III, Step 1 together with the definition of z_k in Section II);
  *   - z_0,n = 1 iff y_n < 0 (Section III, Initialization; sgn(0) taken as +);
