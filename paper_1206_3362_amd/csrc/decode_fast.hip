@@ -12,6 +12,9 @@
 //     three members each, where a block has at least 2 DV lanes), toggling
 //     each with an LDS xor that returns the old word; the new syndrome bit
 //     fixes the sign of the change +-2 a_den w of every member metric.
+//     The syndrome bit is bit 7 of the check's min1-position byte, so the
+//     one xor also returns the position and the check phase stores both
+//     with one byte write.
 //     Toggles of one check by two winners in the same round are serialised
 //     by the LDS atomics and their changes cancel exactly, so no separate
 //     parity pass is needed;
@@ -67,7 +70,7 @@ struct FastArgs {
     // LDS offsets in bytes
     // LDS: tables shared by the workgroup (o_sh, o_slot), then one region of
     // wave_bytes per wavefront (offsets relative to the region; keys at 0)
-    int o_chk, o_chkp, o_y, o_z, o_syn, o_sh, o_slot, o_wave0, wave_bytes, lds_bytes;
+    int o_chk, o_chkp, o_y, o_z, o_sh, o_slot, o_wave0, wave_bytes, lds_bytes;
 };
 
 __device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t mag, uint32_t mask)
@@ -208,10 +211,10 @@ __device__ __forceinline__ uint32_t check_init(const FastArgs &a, int i, int imw
     const uint32_t m = i * Z + r;
     if constexpr (DT == FWBF_I8) {
         ((uint16_t *)chk)[m] = (uint16_t)(m1 | (m2 << 8));
-        chkp[m] = (uint8_t)pos;
+        chkp[m] = (uint8_t)(pos | (par << 7));
     } else {
         chk[m] = m1 | (m2 << 16);
-        chkp[m] = (uint8_t)pos;
+        chkp[m] = (uint8_t)(pos | (par << 7));
     }
     // push this check's term of eq. (1) to its members: the
     // two signed values (a_den w << idxb) are formed once
@@ -234,8 +237,8 @@ __device__ __forceinline__ uint32_t check_init(const FastArgs &a, int i, int imw
 // bit (1: the check is now unsatisfied).
 template <int DT, int DC>
 __device__ __forceinline__ uint32_t toggle_check(const FastArgs &a, int imwbf, uint32_t nf, uint32_t t, const uint32_t *sh,
-                                                 const uint16_t *slotof, uint32_t *syn, const uint32_t *chk,
-                                                 const uint8_t *chkp, uint32_t *keys)
+                                                 const uint16_t *slotof, const uint32_t *chk, uint8_t *chkp,
+                                                 uint32_t *keys)
 {
     const uint32_t Z = a.Z;
     const uint32_t j = mul24(nf, a.rZ24) >> 20;  // block column: nf / Z
@@ -243,16 +246,20 @@ __device__ __forceinline__ uint32_t toggle_check(const FastArgs &a, int imwbf, u
     const uint32_t *st = sh + mul24(t, (uint32_t)a.nb);
     const uint32_t rr = submod(c, st[j], Z);
     const uint32_t m = mul24(t, Z) + rr;
-    const uint32_t old = atomicXor(&syn[m >> 5], 1u << (m & 31));
-    const uint32_t nb1 = ((old >> (m & 31)) & 1u) ^ 1u;
-    // the check's two weights and the position of its minimum
-    uint32_t w1, w2, pos;
+    // the syndrome bit is bit 7 of the check's position byte: toggled with
+    // an xor on its 32-bit word, which also returns the position
+    const uint32_t sb = 8u * (m & 3u);
+    const uint32_t ob = atomicXor(&((uint32_t *)chkp)[m >> 2], 0x80u << sb) >> sb;
+    const uint32_t nb1 = ((ob >> 7) & 1u) ^ 1u;
+    const uint32_t pos = ob & 7u;
+    // the check's two weights
+    uint32_t w1, w2;
     if constexpr (DT == FWBF_I8) {
         const uint32_t cw = ((const uint16_t *)chk)[m];
-        w1 = cw & 0xFF; w2 = cw >> 8; pos = chkp[m];
+        w1 = cw & 0xFF; w2 = cw >> 8;
     } else {
         const uint32_t cw = chk[m];
-        w1 = cw & 0xFFFF; w2 = cw >> 16; pos = chkp[m];
+        w1 = cw & 0xFFFF; w2 = cw >> 16;
     }
     const uint32_t e1 = mul24(a.kden2, w1);
     const uint32_t e2 = imwbf ? mul24(a.kden2, w2) : e1;
@@ -276,8 +283,8 @@ __device__ __forceinline__ uint32_t toggle_check(const FastArgs &a, int imwbf, u
 template <int DT, int DC>
 __device__ __forceinline__ uint32_t toggle_half(const FastArgs &a, int imwbf, uint32_t nf, uint32_t t, uint32_t u,
                                                 const uint16_t *const (&sbq)[DC / 2],
-                                                const uint32_t *sh, uint32_t *syn, const uint32_t *chk,
-                                                const uint8_t *chkp, uint32_t *keys)
+                                                const uint32_t *sh, const uint32_t *chk, uint8_t *chkp,
+                                                uint32_t *keys)
 {
     constexpr int H = DC / 2;
     const uint32_t Z = a.Z;
@@ -285,16 +292,19 @@ __device__ __forceinline__ uint32_t toggle_half(const FastArgs &a, int imwbf, ui
     const uint32_t c = nf - mul24(j, Z);
     const uint32_t rr = submod(c, sh[mul24(t, (uint32_t)a.nb) + j], Z);
     const uint32_t m = mul24(t, Z) + rr;
-    const uint32_t bit = 1u << (m & 31);
-    const uint32_t old = atomicXor(&syn[m >> 5], u == 0 ? bit : 0u);
-    const uint32_t nb1 = dpp<0xA0>((old & bit) ? 0u : 1u);  // quad_perm [0,0,2,2]: the even lane's bit
-    uint32_t w1, w2, pos;
+    // syndrome bit 7 of the position byte; the odd lane xors 0 and only
+    // takes the (unchanged) position from the word it reads
+    const uint32_t sb = 8u * (m & 3u);
+    const uint32_t ob = atomicXor(&((uint32_t *)chkp)[m >> 2], u == 0 ? 0x80u << sb : 0u) >> sb;
+    const uint32_t nb1 = dpp<0xA0>(((ob >> 7) & 1u) ^ 1u);  // quad_perm [0,0,2,2]: the even lane's bit
+    const uint32_t pos = ob & 7u;
+    uint32_t w1, w2;
     if constexpr (DT == FWBF_I8) {
         const uint32_t cw = ((const uint16_t *)chk)[m];
-        w1 = cw & 0xFF; w2 = cw >> 8; pos = chkp[m];
+        w1 = cw & 0xFF; w2 = cw >> 8;
     } else {
         const uint32_t cw = chk[m];
-        w1 = cw & 0xFFFF; w2 = cw >> 16; pos = chkp[m];
+        w1 = cw & 0xFFFF; w2 = cw >> 16;
     }
     const uint32_t e1 = mul24(a.kden2, w1);
     const uint32_t e2 = imwbf ? mul24(a.kden2, w2) : e1;
@@ -322,7 +332,6 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
     uint8_t *chkp = wbase + a.o_chkp;
     Y *yv = (Y *)(wbase + a.o_y);
     uint32_t *zw = (uint32_t *)(wbase + a.o_z);
-    uint32_t *syn = (uint32_t *)(wbase + a.o_syn);
     uint32_t *flips = (uint32_t *)(wbase + a.o_y);  // the rounds' winners (over the received values)
     uint32_t *sh = (uint32_t *)(smem + a.o_sh);
     uint16_t *slotof = (uint16_t *)(smem + a.o_slot);  // slot word of every bit, doubled (frame-independent)
@@ -380,7 +389,6 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
         if (skip && skip[f]) continue;  // uniform across the wave
         const Y *yrow = (const Y *)a.y + f * a.stride;
         wave_sync();
-        for (int w = lane; w < ((M + 63) >> 6) * 2; w += 64) syn[w] = 0;
         for (int w = lane; w < ((N + 63) >> 6) * 2; w += 64) zw[w] = 0;
         // ---- received values -> LDS ---------------------------------------
         constexpr int E = 16 / (int)sizeof(Y);  // values per 16-byte chunk
@@ -471,8 +479,6 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                 const uint32_t par = valid ? check_init<DT, DC>(a, i, imwbf, r, js, yv, slotof, keys, chk, chkp) : 0u;
                 const unsigned long long b = __ballot(valid && par);
                 weight += __popcll(b);
-                // syndrome words: checks i*Z + r0 .. +63 (not word aligned in general)
-                if (valid && par) atomicOr(&syn[(i * Z + r) >> 5], 1u << ((i * Z + r) & 31));
             }
         }
         wave_sync();
@@ -530,7 +536,7 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                     if (flip) atomicXor(&zw[n >> 5], 1u << (n & 31));
                     const bool tog = tt < (uint32_t)DV && (int)g < a.Geff && (single || val > a.zero_val);
                     uint32_t nb1 = 0;
-                    if (tog) nb1 = toggle_half<DT, DC>(a, imwbf, n, tt, tu, sbq, sh, syn, chk, chkp, keys);
+                    if (tog) nb1 = toggle_half<DT, DC>(a, imwbf, n, tt, tu, sbq, sh, chk, chkp, keys);
                     sum_ones = __popcll(__ballot(nb1));
                 } else if (Lr >= DV) {
                     // every lane of a block holds the block's winner after the
@@ -540,7 +546,7 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                     const uint32_t t = lane & (uint32_t)(Lr - 1);
                     const bool tog = t < (uint32_t)DV && (int)g < a.Geff && (single || val > a.zero_val);
                     uint32_t nb1 = 0;
-                    if (tog) nb1 = toggle_check<DT, DC>(a, imwbf, n, t, sh, slotof, syn, chk, chkp, keys);
+                    if (tog) nb1 = toggle_check<DT, DC>(a, imwbf, n, t, sh, slotof, chk, chkp, keys);
                     sum_ones = __popcll(__ballot(nb1));
                 } else {
                     // fewer lanes than checks per block: the winners are
@@ -559,7 +565,7 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
                         if (i < ntog) {
                             const uint32_t u = mul24((uint32_t)i, DVM) >> 16;
                             const uint32_t t = (uint32_t)i - mul24(u, (uint32_t)DV);
-                            nb1 = toggle_check<DT, DC>(a, imwbf, flips[u], t, sh, slotof, syn, chk, chkp, keys);
+                            nb1 = toggle_check<DT, DC>(a, imwbf, flips[u], t, sh, slotof, chk, chkp, keys);
                         }
                         sum_ones += __popcll(__ballot(nb1));
                     }
@@ -709,14 +715,13 @@ int try_fast_decode(const fwbf_code *c, const fwbf_params *p, const void *y, int
     a.o_wave0 = (off + 15) / 16 * 16;
     off = 64 * C * 4;  // keys, then the rest of one wavefront's frame state
     a.o_chk = take((p->dtype == FWBF_I16 ? 4 : 2) * c->M, 4);  // min1 | min2 << 16 (int16), << 8 (int8)
-    a.o_chkp = take(c->M, 4);                                    // position of min1
+    a.o_chkp = take((c->M + 3) / 4 * 4, 4);  // position of min1 | syndrome bit << 7 (whole words: atomics)
     // the received values, needed only while initialising; in the rounds the
     // same bytes hold the flipped bits (Geff words)
     // received values: bit order while loading, then slot order (64 C slots;
     // a lane's reads run up to N + L C in bit order)
     a.o_y = take(std::max({esz * ((c->N + 15) / 16 * 16), esz * (c->N + a.L * C), esz * 64 * C, 4 * a.Geff}), 16);
     a.o_z = take(((c->N + 63) / 64) * 8, 8);
-    a.o_syn = take(((c->M + 63) / 64) * 8, 8);
     a.wave_bytes = (off + 15) / 16 * 16;
     a.lds_bytes = a.o_wave0 + FAST_WAVES * a.wave_bytes;
     if (a.lds_bytes > 160 * 1024) return 0;
