@@ -218,7 +218,7 @@ struct LearnArgs {
     float invA;   // 1/A when A is a power of two (then x * invA == x / A), else 0
     // LDS: tables shared by the workgroup (o_sh, o_slot, o_net, o_netw), then one
     // region of wave_bytes per wavefront (offsets relative to it; slots at 0)
-    int o_chk, o_y, o_z, o_syn, o_list, o_sh, o_cand, o_slot, o_net, o_netw, o_wave0, wave_bytes, lds_bytes;
+    int o_chk, o_y, o_z, o_list, o_sh, o_cand, o_slot, o_net, o_netw, o_wave0, wave_bytes, lds_bytes;
 };
 
 // independent wavefronts (frames) per workgroup; the tables (shifts, slot
@@ -251,7 +251,6 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
     uint32_t *chk = (uint32_t *)(wbase + a.o_chk);
     int8_t *yv = (int8_t *)(wbase + a.o_y);
     uint32_t *zw = (uint32_t *)(wbase + a.o_z);
-    uint32_t *syn = (uint32_t *)(wbase + a.o_syn);
     uint32_t *list = (uint32_t *)(wbase + a.o_list);  // the bits flipped in a round
     uint4 *cand = (uint4 *)(wbase + a.o_cand);  // 32 proposals: n, slot word
     uint32_t *sh = (uint32_t *)(smem + a.o_sh);
@@ -329,7 +328,6 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
         const uint4 vc[2] = {nxt[0], nxt[1]};
         if (f + fr.step < fr.end) fetch(f + fr.step, nxt);
         lwave_sync();
-        for (int w = lane; w < ((M + 63) >> 6) * 2; w += 64) syn[w] = 0;
         for (int w = lane; w < ((N + 63) >> 6) * 2; w += 64) zw[w] = 0;
         {
             // the frame's pieces to LDS; z_0 = [y < 0] from their sign bits
@@ -416,7 +414,7 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
                     }
                     par = (sx >> 7) & 1u;
                     const uint32_t m1 = k1 >> 3, m2 = k2 >> 3, pos = k1 & 7u;
-                    chk[i * Z + r] = m1 | (m2 << 8) | (pos << 16);
+                    chk[i * Z + r] = m1 | (m2 << 8) | (pos << 16) | (par << 24);  // bit 24: syndrome
                     // the check's two signed terms, formed once
                     const uint32_t d1 = ((uint32_t)(par ? (int)m1 : -(int)m1) << 16) + par;
                     const uint32_t d2 = ((uint32_t)(par ? (int)m2 : -(int)m2) << 16) + par;
@@ -425,7 +423,6 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
                 }
                 const unsigned long long b = __ballot(valid && par);
                 weight += __popcll(b);
-                if (valid && par) atomicOr(&syn[(i * Z + r) >> 5], 1u << ((i * Z + r) & 31));
             }
         }
         lwave_sync();
@@ -558,9 +555,9 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
                     const uint32_t *st = sh + mul24(tt, (uint32_t)a.nb);
                     const uint32_t rr = submod(c, st[jb], Z);
                     const uint32_t m = mul24(tt, Z) + rr;
-                    const uint32_t old = atomicXor(&syn[m >> 5], 1u << (m & 31));
-                    nb1 = ((old >> (m & 31)) & 1u) ^ 1u;
-                    const uint32_t cwd = chk[m];
+                    // toggles the syndrome bit (bit 24) and returns the minima
+                    const uint32_t cwd = atomicXor(&chk[m], 1u << 24);
+                    nb1 = ((cwd >> 24) & 1u) ^ 1u;
                     const uint32_t e1 = ((2u * (cwd & 0xFFu)) << 16) + 1u, e2 = ((2u * ((cwd >> 8) & 0xFFu)) << 16) + 1u;
                     const uint32_t d1 = nb1 ? e1 : 0u - e1, d2 = nb1 ? e2 : 0u - e2;
                     const uint32_t pos = (cwd >> 16) & 0xFFu;
@@ -1553,7 +1550,6 @@ extern "C" int fwbf_decode_learned(const fwbf_code *code, const fwbf_params *pla
     a.o_chk = take(4 * code->M, 4);
     a.o_y = take((code->N + 15) / 16 * 16, 16);
     a.o_z = take(((code->N + 63) / 64) * 8, 8);
-    a.o_syn = take(((code->M + 63) / 64) * 8, 8);
     a.o_list = take(4 * 3 * a.Geff, 4);
     a.o_cand = take(16 * 32, 16);
     a.wave_bytes = (off + 15) / 16 * 16;
