@@ -474,7 +474,10 @@ __global__ __launch_bounds__(64 * FAST_WAVES) __attribute__((amdgpu_waves_per_eu
             for (int q = 0; q < DC; q++) js[q] = sh[i * a.nb + q];
             for (uint32_t r0 = 0; r0 < Z; r0 += 64) {
                 const int imwbf = fresh(a.imwbf);
-                const uint32_t r = r0 + lane;
+                // the addresses of this pass are the lane offset plus scalar
+                // sums (an opaque r0 keeps them from becoming per-member
+                // induction registers)
+                const uint32_t r = (uint32_t)fresh((int)r0) + lane;
                 const bool valid = r < Z;
                 const uint32_t par = valid ? check_init<DT, DC>(a, i, imwbf, r, js, yv, slotof, keys, chk, chkp) : 0u;
                 const unsigned long long b = __ballot(valid && par);
