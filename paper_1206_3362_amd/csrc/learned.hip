@@ -389,7 +389,9 @@ __global__ __launch_bounds__(64 * LEARN_WAVES) __attribute__((amdgpu_waves_per_e
 #pragma unroll
             for (int q = 0; q < DC; q++) js[q] = sh[i * a.nb + q];
             for (uint32_t r0 = 0; r0 < Z; r0 += 64) {
-                const uint32_t r = r0 + lane;
+                // an opaque r0: the pass's addresses are the lane offset plus
+                // scalar sums, not one induction register per member
+                const uint32_t r = (uint32_t)fresh((int)r0) + lane;
                 const bool valid = r < Z;
                 uint32_t par = 0;
                 if (valid) {
